@@ -1,0 +1,280 @@
+"""Pins for the oracle's stencil weights (eq. (1) with L = Laplacian, PHS r^3
+plus monomials up to degree m, sections I, II and V of the paper).
+
+Each test ties the oracle to something it does not share code with:
+  * polynomial reproduction and zero row sum (the P^T w = lap p block row);
+  * the classical five-point Laplacian when n equals the monomial count;
+  * invariance under scaling, translation, rotation and reflection;
+  * the symmetry of a regular 3x3 stencil;
+  * LAPACK's dgesv and an exact (50-digit) solve of the same system;
+  * per-stencil status codes for degenerate inputs.
+"""
+
+import os
+
+import mpmath
+import numpy as np
+import pytest
+
+import oracle
+from paper_2107_03632_amd import nodes
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+NFM = {2: 12, 4: 30, 6: 56}
+
+
+def _monomial_exponents(m):
+    return [(deg - b, b) for deg in range(m + 1) for b in range(deg + 1)]
+
+
+def _unit_offsets(x, y, i, idx):
+    dx = x[idx] - x[i]
+    dy = y[idx] - y[i]
+    s = np.sqrt(np.max(dx * dx + dy * dy))
+    return dx / s, dy / s, s
+
+
+@pytest.fixture(scope="module")
+def disk_small():
+    ns = nodes.unit_disk(3000, 200, seed=21)
+    nbr = oracle.knn(ns.x, ns.y, 56)
+    return ns, nbr
+
+
+@pytest.mark.parametrize("m", [2, 4, 6])
+def test_polynomial_reproduction_and_zero_sum(disk_small, m):
+    ns, nbr = disk_small
+    n = NFM[m]
+    rows = np.arange(0, ns.n_nodes, 7)
+    w, st = oracle.weights(ns.x, ns.y, nbr[:, :n], m=m, n=n, rows=rows)
+    assert np.all(st == oracle.OK)
+    worst = 0.0
+    for t, i in enumerate(rows):
+        idx = nbr[i, :n]
+        ux, uy, s = _unit_offsets(ns.x, ns.y, i, idx)
+        wh = w[t, :n] * s * s
+        for a, b in _monomial_exponents(m):
+            terms = wh * ux ** a * uy ** b
+            target = 2.0 if (a, b) in ((2, 0), (0, 2)) else 0.0
+            err = abs(terms.sum() - target) / max(1.0, np.abs(terms).sum())
+            worst = max(worst, err)
+    assert worst <= 1e-10, worst
+
+
+def test_five_point_special_case():
+    tab = np.loadtxt(os.path.join(GOLDEN, "five_point_laplacian.txt"))
+    for h in [1.0, 0.1, 1.0 / 45, 3e-3]:
+        x = tab[:, 0] * h + 0.3
+        y = tab[:, 1] * h - 0.7
+        nbr = np.tile(np.arange(6, dtype=np.int32), (6, 1))
+        w, st = oracle.weights(x, y, nbr, m=2, n=6, rows=[0])
+        assert st[0] == oracle.OK
+        np.testing.assert_allclose(w[0] * h * h, tab[:, 2], rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("m", [2, 4, 6])
+def test_scale_invariance(disk_small, m):
+    ns, nbr = disk_small
+    n = NFM[m]
+    rows = np.arange(3, ns.n_nodes, 97)
+    w0, _ = oracle.weights(ns.x, ns.y, nbr[:, :n], m=m, n=n, rows=rows)
+    for sig in [0.37, 2.0 ** -7, 13.0]:
+        w1, st = oracle.weights(ns.x * sig, ns.y * sig, nbr[:, :n], m=m, n=n, rows=rows)
+        assert np.all(st == 0)
+        rel = np.abs(w1 * sig * sig - w0).max(axis=1) / np.abs(w0).max(axis=1)
+        assert rel.max() <= 1e-10, rel.max()
+
+
+@pytest.mark.parametrize("m", [2, 4, 6])
+def test_rigid_motion_invariance(disk_small, m):
+    ns, nbr = disk_small
+    n = NFM[m]
+    rows = np.arange(5, ns.n_nodes, 101)
+    w0, _ = oracle.weights(ns.x, ns.y, nbr[:, :n], m=m, n=n, rows=rows)
+    th = 0.7
+    c, s = np.cos(th), np.sin(th)
+    for X, Y in [(ns.x + 3.25, ns.y - 1.5),           # translation
+                 (c * ns.x - s * ns.y, s * ns.x + c * ns.y),  # rotation
+                 (-ns.x, ns.y)]:                       # reflection
+        w1, st = oracle.weights(X, Y, nbr[:, :n], m=m, n=n, rows=rows)
+        assert np.all(st == 0)
+        rel = np.abs(w1 - w0).max(axis=1) / np.abs(w0).max(axis=1)
+        assert rel.max() <= 1e-9, rel.max()
+
+
+def test_regular_3x3_symmetry():
+    h = 0.05
+    g = np.array([-1.0, 0.0, 1.0]) * h
+    X, Y = np.meshgrid(g, g)
+    x, y = X.ravel() + 0.5, Y.ravel() + 0.5
+    nbr = np.tile(np.arange(9, dtype=np.int32), (9, 1))
+    w, st = oracle.weights(x, y, nbr, m=2, n=9, rows=[4])
+    assert st[0] == 0
+    w = w[0].reshape(3, 3)
+    edge = [w[0, 1], w[1, 0], w[1, 2], w[2, 1]]
+    corner = [w[0, 0], w[0, 2], w[2, 0], w[2, 2]]
+    scale = np.abs(w).max()
+    assert np.ptp(edge) <= 1e-12 * scale
+    assert np.ptp(corner) <= 1e-12 * scale
+    assert abs(edge[0] + 2 * corner[0] - 1 / h ** 2) <= 1e-12 * scale
+    assert abs(w.sum()) <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("m", [2, 4, 6])
+def test_solve_matches_lapack_and_exact(disk_small, m):
+    ns, nbr = disk_small
+    n = NFM[m]
+    for i in [0, 17, ns.n_nodes - 1, ns.n_nodes - 150, 1234]:
+        st, M, rhs, s = oracle.assemble(ns.x, ns.y, i, nbr[i, :n], m)
+        assert st == 0
+        st, LU, perm, dinv = oracle.lu(M)
+        assert st == 0
+        z = oracle.lu_solve(LU, perm, dinv, rhs)
+        cond = np.linalg.cond(M)
+        z_lapack = np.linalg.solve(M, rhs)
+        # both are backward stable: forward error within cond * eps
+        bound = 64 * cond * np.finfo(float).eps
+        assert np.abs(z - z_lapack).max() / np.abs(z_lapack).max() <= bound
+        # exact solution of the same (rounded) system, 50 digits
+        with mpmath.workdps(50):
+            zm = mpmath.lu_solve(mpmath.matrix(M.tolist()), mpmath.matrix(rhs.tolist()))
+            z_ex = np.array([float(v) for v in zm])
+        err = np.abs(z - z_ex).max() / np.abs(z_ex).max()
+        assert err <= bound, (err, cond)
+        # the factors reproduce P M = L U
+        L = np.tril(LU, -1) + np.eye(len(M))
+        U = np.triu(LU)
+        PM = M.copy()
+        for c, p in enumerate(perm):
+            PM[[c, p]] = PM[[p, c]]
+        assert np.abs(L @ U - PM).max() <= 1e-13 * np.abs(M).max() * len(M)
+        assert np.allclose(dinv, 1.0 / np.diag(U), rtol=0, atol=0)
+
+
+def test_assembly_against_high_precision_definition():
+    ns = nodes.unit_square(12, seed=9)
+    nbr = oracle.knn(ns.x, ns.y, 30)
+    i = 40
+    idx = nbr[i, :30]
+    st, M, rhs, s = oracle.assemble(ns.x, ns.y, i, idx, 4)
+    assert st == 0
+    with mpmath.workdps(40):
+        dx = [mpmath.mpf(ns.x[j]) - mpmath.mpf(ns.x[i]) for j in idx]
+        dy = [mpmath.mpf(ns.y[j]) - mpmath.mpf(ns.y[i]) for j in idx]
+        S = mpmath.sqrt(max(a * a + b * b for a, b in zip(dx, dy)))
+        u = [a / S for a in dx]
+        v = [b / S for b in dy]
+        for k in range(30):
+            for l in range(30):
+                r = mpmath.sqrt((u[k] - u[l]) ** 2 + (v[k] - v[l]) ** 2)
+                assert abs(float(r ** 3) - M[k, l]) <= 1e-14
+            for j, (a, b) in enumerate(_monomial_exponents(4)):
+                assert abs(float(u[k] ** a * v[k] ** b) - M[k, 30 + j]) <= 1e-14
+                assert M[30 + j, k] == M[k, 30 + j]
+            assert abs(float(9 * mpmath.sqrt(u[k] ** 2 + v[k] ** 2)) - rhs[k]) <= 1e-13
+    assert np.all(M[30:, 30:] == 0)
+    assert list(rhs[30:]) == [0, 0, 0, 2, 0, 2] + [0] * 9
+
+
+def test_status_codes():
+    ns = nodes.unit_square(8, seed=3)
+    x, y = ns.x.copy(), ns.y.copy()
+    nbr = oracle.knn(x, y, 12)
+    # duplicate support node
+    nb = nbr.copy()
+    nb[10, 5] = nb[10, 4]
+    # bad index
+    nb[11, 3] = x.size + 4
+    nb[12, 0] = -1
+    # non-finite coordinate used by stencil 13 (node nbr[13,2])
+    xx = x.copy()
+    xx[nbr[13, 2]] = np.inf
+    rows = [10, 11, 12, 13, 14]
+    w, st = oracle.weights(xx, y, nb, m=2, n=12, rows=rows)
+    assert st[0] == oracle.DUPLICATE
+    assert st[1] == oracle.BAD_INDEX
+    assert st[2] == oracle.BAD_INDEX
+    assert st[3] == oracle.NONFINITE
+    assert np.all(np.isnan(w[:4]))
+    # row 14 is fine unless it uses the poisoned node
+    assert (st[4] == oracle.OK) == (nbr[13, 2] not in nb[14])
+
+
+def test_singular_collinear_support():
+    # six nodes on a line: y, xy, y^2 columns of P vanish exactly
+    x = np.linspace(0.0, 1.0, 6)
+    y = np.full(6, 0.25)
+    nbr = np.tile(np.arange(6, dtype=np.int32), (6, 1))
+    w, st = oracle.weights(x, y, nbr, m=2, n=6, rows=[2])
+    assert st[0] == oracle.SINGULAR
+    assert np.all(np.isnan(w[0]))
+
+
+def test_padding_and_mixed_order(disk_small):
+    ns, nbr = disk_small
+    order = np.array([2, 4, 6] * (ns.n_nodes // 3 + 1), dtype=np.int8)[:ns.n_nodes]
+    rows = np.arange(0, ns.n_nodes, 50)
+    wm, st = oracle.weights(ns.x, ns.y, nbr, order=order, rows=rows)
+    assert np.all(st == 0)
+    for m in (2, 4, 6):
+        sel = order[rows] == m
+        wu, _ = oracle.weights(ns.x, ns.y, nbr, m=m, n=NFM[m], rows=rows[sel])
+        assert np.array_equal(wm[sel], wu)
+        assert np.all(wm[sel][:, NFM[m]:] == 0)
+
+
+@pytest.mark.parametrize("m", [2, 4])
+def test_weights_apply_laplacian_of_phs_interpolant(m):
+    """w . f equals lap s_f at the centre, where s_f is the r^3 + monomial
+    interpolant of f on the stencil; lap s_f is taken by 30-digit numerical
+    differentiation, independent of the closed form lap r^3 = 9 r."""
+    ns = nodes.unit_square(12, seed=17)
+    n = NFM[m]
+    nbr = oracle.knn(ns.x, ns.y, n)
+    rng = np.random.default_rng(5)
+    for i in [30, 77]:
+        idx = nbr[i]
+        w, st = oracle.weights(ns.x, ns.y, nbr, m=m, n=n, rows=[i])
+        assert st[0] == 0
+        px, py = ns.x[idx], ns.y[idx]
+        f = rng.standard_normal(n)
+        ex = _monomial_exponents(m)
+        A = np.sqrt((px[:, None] - px[None]) ** 2 + (py[:, None] - py[None]) ** 2) ** 3
+        cx, cy = ns.x[i], ns.y[i]
+        P = np.array([[(a_ - cx) ** e[0] * (b_ - cy) ** e[1] for e in ex]
+                      for a_, b_ in zip(px, py)])
+        Mi = np.block([[A, P], [P.T, np.zeros((len(ex), len(ex)))]])
+        coef = np.linalg.solve(Mi, np.concatenate([f, np.zeros(len(ex))]))
+        with mpmath.workdps(30):
+            def s_f(X, Y):
+                acc = mpmath.mpf(0)
+                for k in range(n):
+                    acc += coef[k] * mpmath.sqrt((X - px[k]) ** 2 + (Y - py[k]) ** 2) ** 3
+                for j, e in enumerate(ex):
+                    acc += coef[n + j] * (X - cx) ** e[0] * (Y - cy) ** e[1]
+                return acc
+            X0, Y0 = mpmath.mpf(cx), mpmath.mpf(cy)
+            lap = mpmath.diff(lambda t: s_f(t, Y0), X0, 2) + \
+                mpmath.diff(lambda t: s_f(X0, t), Y0, 2)
+        got = float(np.dot(w[0, :n], f))
+        assert abs(got - float(lap)) <= 1e-8 * np.abs(w[0, :n] * f).sum(), (got, float(lap))
+
+
+def test_lu_pivot_rule_first_maximum():
+    """Partial pivoting takes the first row holding the largest |entry|."""
+    A = np.array([[1.0, 2.0, 0.5],
+                  [-1.0, 3.0, 1.0],
+                  [1.0, -4.0, 2.0]])
+    st, LU, perm, dinv = oracle.lu(A)
+    assert st == 0
+    # column 0: |1| = |-1| = |1| -> row 0 stays; column 1 after elimination:
+    # rows hold 3-(-1)(2)... = 5 and -4-(1)(2) = -6 -> row 2
+    assert list(perm) == [0, 2, 2]
+    B = np.array([[0.0, 1.0], [2.0, 1.0]])
+    st, LU, perm, dinv = oracle.lu(B)
+    assert list(perm) == [1, 1]
+    C = np.array([[-3.0, 1.0, 0.0], [3.0, 0.0, 1.0], [1.0, 1.0, 1.0]])
+    st, LU, perm, _ = oracle.lu(C)
+    assert perm[0] == 0  # tie |-3| = |3|: the first row wins
+    # after step 0: row1 -> [0, 1, 1], row2 -> [0, 4/3, 1]; pivot row 2
+    assert perm[1] == 2
