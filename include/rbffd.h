@@ -1,0 +1,178 @@
+/*
+ * rbffd.h - C ABI of the MI355X (gfx950) RBF-FD Laplacian stencil library.
+ *
+ * The library computes, for every scattered 2-D node x_i, the weights w_ik of
+ * the local operator approximation  (lap u)(x_i) ~ sum_k w_ik u(x_{nbr_ik})
+ * (paper: eq. (1), section II), using the polyharmonic spline phi(r) = r^3
+ * augmented with all monomials of degree <= m (sections I and V), and the
+ * pieces around it: support selection, the CSR form of the operator with
+ * Dirichlet identity rows (section IV) and its product with a field.
+ *
+ * Conventions shared by every entry point
+ *   - Pointers are DEVICE pointers unless marked "host".  All arrays are
+ *     dense, row-major, owned by the caller; the library never allocates,
+ *     frees or keeps caller memory.  Scratch memory is passed in as a
+ *     workspace whose size the matching *_workspace_size query returns.
+ *   - stream is a hipStream_t (NULL = the default stream).  Work is enqueued
+ *     asynchronously on it; no entry point synchronises the host.
+ *   - Return value: RBFFD_SUCCESS (0) or a negative RBFFD_ERR_* code.
+ *     Arguments are checked before anything is enqueued, so a negative return
+ *     means nothing ran.  RBFFD_ERR_HIP - e signals a HIP launch error e.
+ *   - Numerical trouble is reported per stencil in a status array (values
+ *     RBFFD_OK ... RBFFD_DUPLICATE below) and the failed stencil's weights
+ *     are NaN, so it cannot be used silently.
+ *   - Calls on different streams are independent (no global mutable state).
+ */
+#ifndef RBFFD_H
+#define RBFFD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---------------------------------------------------- */
+#define RBFFD_SUCCESS 0
+#define RBFFD_ERR_ARG (-1)          /* invalid argument (null, size, range) */
+#define RBFFD_ERR_WORKSPACE (-2)    /* workspace missing or too small */
+#define RBFFD_ERR_UNSUPPORTED (-3)  /* valid but not built (e.g. K > 96) */
+#define RBFFD_ERR_HIP (-100)        /* RBFFD_ERR_HIP - hipError_t */
+
+/* ---- per-stencil status codes ------------------------------------------ */
+#define RBFFD_OK 0
+#define RBFFD_SINGULAR 1        /* a pivot of the LU is exactly zero */
+#define RBFFD_FELL_BACK_FP64 2  /* mixed precision: refinement failed, the
+                                   stencil was redone in FP64 (weights valid) */
+#define RBFFD_NONFINITE 3       /* non-finite coordinate, pivot or solution */
+#define RBFFD_BAD_INDEX 4       /* a support index lies outside [0, n_nodes) */
+#define RBFFD_DUPLICATE 5       /* two support nodes coincide */
+#define RBFFD_BAD_ORDER 6       /* per-node order not in {2,4,6} */
+
+/* ---- precision ---------------------------------------------------------- */
+#define RBFFD_FP64 0   /* FP64 assembly, factorisation and solves */
+#define RBFFD_MIXED 1  /* FP32 factorisation + FP64 iterative refinement */
+
+/* Text for a return code or a status code (host, static storage). */
+const char *rbffd_error_string(int code);
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int rbffd_version(void);
+
+/* ==========================================================================
+ * Support selection: N(x) of eq. (1), the k nearest nodes (section II; the
+ * support sizes of section V).
+ *
+ * nbr[i*k + s] (int32, [n_nodes][k]) lists, for node i, the k nodes j with the
+ * smallest keys (d2, j) in lexicographic order, ascending, where
+ * d2 = fl(fl(dx*dx) + fl(dy*dy)), dx = x[j] - x[i], dy = y[j] - y[i], with no
+ * fused multiply-add.  Node i itself comes first unless a coincident node has
+ * a smaller index.  Nodes whose key is NaN are never selected; slots that
+ * cannot be filled for that reason hold -1.
+ *
+ * x, y: [n_nodes] FP64.  1 <= k <= 64, k <= n_nodes, n_nodes < 2^31.
+ * The search is exact (a uniform cell grid visited ring by ring, stopped
+ * only when no unvisited cell can hold a smaller key).
+ * ======================================================================== */
+int rbffd_knn_workspace_size(int64_t n_nodes, int32_t k, size_t *bytes /* host */);
+int rbffd_knn(const double *x, const double *y, int64_t n_nodes, int32_t k,
+              int32_t *nbr, void *workspace, size_t workspace_bytes, void *stream);
+
+/* ==========================================================================
+ * Stencil weights: w of eq. (1) for L = Laplacian with phi(r) = r^3 and all
+ * 2-D monomials of degree <= m (sections I, II, V).
+ *
+ * For stencil i with support idx_k = nbr[i*k_stride + k], k < n:
+ *   d_k  = (x[idx_k] - x[i], y[idx_k] - y[i]),  s = max_k |d_k|,  u_k = d_k / s
+ *   M    = [A P; P^T 0],  A_kl = |u_k - u_l|^3,  P_kj = p_j(u_k)
+ *          (monomials in graded order 1, x, y, x^2, xy, y^2, x^3, ...)
+ *   rhs  = [9 |u_k| ; lap p_j(0)]        (lap r^3 = 9 r in 2-D)
+ *   M z  = rhs by LU with partial pivoting (first largest |entry| wins ties),
+ *   w_ik = z_k / s^2   for k < n;   w_ik = 0 for n <= k < k_stride.
+ * The FP64 path performs exactly this sequence of IEEE operations (the
+ * elimination uses fma(-l, u, a) and the reciprocal of each pivot).
+ *
+ * Order: order == NULL -> every node uses (m, n), m in {2,4,6},
+ *        (m+1)(m+2)/2 <= n <= k_stride, n + (m+1)(m+2)/2 <= 96.
+ *        order != NULL -> order[i] (int8, device, [n_nodes]) in {2,4,6}
+ *        selects m per node and n = n_for_order[m/2 - 1] (host, [3]); nodes
+ *        are bucketed by system size inside the call.
+ * precision: RBFFD_FP64 or RBFFD_MIXED.
+ * w: [n_nodes][k_stride] FP64 out.  status: [n_nodes] int32 out (may be NULL).
+ * save (may be NULL): factors for rbffd_weights_backward; see
+ * rbffd_weights_save_size.  Only with RBFFD_FP64.
+ * ======================================================================== */
+int rbffd_weights_workspace_size(int64_t n_nodes, int32_t has_order, int32_t precision,
+                                 size_t *bytes /* host */);
+/* Bytes of the save buffer for the largest system size kmax = n + M(m) in
+ * the call: n_nodes * (8*kmax*kmax + 8*kmax + 8 + kmax) rounded up. */
+int rbffd_weights_save_size(int64_t n_nodes, int32_t kmax, size_t *bytes /* host */);
+int rbffd_weights(const double *x, const double *y, int64_t n_nodes,
+                  const int32_t *nbr, int32_t k_stride,
+                  const int8_t *order, int32_t m, int32_t n,
+                  const int32_t *n_for_order /* host [3] or NULL */,
+                  int32_t precision,
+                  double *w, int32_t *status,
+                  void *save, size_t save_bytes,
+                  void *workspace, size_t workspace_bytes, void *stream);
+
+/* ==========================================================================
+ * Adjoint of rbffd_weights (FP64): given G = dL/dw ([n_nodes][k_stride]),
+ * returns dL/dx, dL/dy ([n_nodes], overwritten) for all node coordinates,
+ * with the supports held fixed.  Uses the factors that rbffd_weights stored
+ * in save (same nodes, supports and orders): mu = M^{-1} [G/s^2; 0] (M is
+ * symmetric), then per support node
+ *   dL/du_k = 9 mu_k u_k/|u_k| - sum_l 3|u_k-u_l|(u_k-u_l)(mu_k w_l + mu_l w_k)
+ *             - sum_j grad p_j(u_k)(mu_k lambda_j + w_k mu_{n+j})
+ * (w, lambda: the unit-scale solution z), dL/dx_{idx_k} += dL/du_k / s and
+ * dL/dx_i -= dL/du_k / s.  The sum over stencils is gathered per node in a
+ * fixed order, so results are deterministic.  Stencils whose forward status
+ * was not RBFFD_OK contribute nothing.
+ * ======================================================================== */
+int rbffd_weights_backward_workspace_size(int64_t n_nodes, int32_t k_stride,
+                                          size_t *bytes /* host */);
+int rbffd_weights_backward(const double *x, const double *y, int64_t n_nodes,
+                           const int32_t *nbr, int32_t k_stride,
+                           const int8_t *order, int32_t m, int32_t n,
+                           const int32_t *n_for_order /* host [3] or NULL */,
+                           const double *grad_w, const void *save, size_t save_bytes,
+                           const int32_t *status,
+                           double *grad_x, double *grad_y,
+                           void *workspace, size_t workspace_bytes, void *stream);
+
+/* ==========================================================================
+ * CSR form of the discrete operator (eq. (1) rows; Dirichlet rows of
+ * section IV become identity rows).
+ *
+ * Row i: is_boundary[i] != 0 -> the single entry (i, 1.0); otherwise the
+ * pairs (nbr[i][k], w[i][k]), k < n_i, sorted by (column, k).  n_i is n, or
+ * n_for_order[order[i]/2 - 1] when order != NULL.  is_boundary may be NULL
+ * (all rows interior).  row_ptr: [n_nodes + 1] int64 out; col (int32),
+ * val (FP64): capacity entries, capacity >= n_nodes * max n_i (the exact
+ * nnz is row_ptr[n_nodes], known only on the device).
+ * ======================================================================== */
+int rbffd_assemble_csr_workspace_size(int64_t n_nodes, size_t *bytes /* host */);
+int rbffd_assemble_csr(int64_t n_nodes, const int32_t *nbr, int32_t k_stride,
+                       const int8_t *order, int32_t n,
+                       const int32_t *n_for_order /* host [3] or NULL */,
+                       const double *w, const uint8_t *is_boundary,
+                       int64_t *row_ptr, int32_t *col, double *val, int64_t capacity,
+                       void *workspace, size_t workspace_bytes, void *stream);
+
+/* ==========================================================================
+ * y = W u - f for a CSR matrix (the operator product of eq. (3)); f may be
+ * NULL (then y = W u).  Each row is summed in CSR order with fma, starting
+ * from 0.  The operator is square: row_ptr [n_rows+1] int64, col int32,
+ * val FP64, u/f/y [n_rows] FP64; a row holding a column outside [0, n_rows)
+ * yields NaN (such an entry is never read).
+ * ======================================================================== */
+int rbffd_spmv(int64_t n_rows, const int64_t *row_ptr, const int32_t *col,
+               const double *val, const double *u, const double *f, double *y,
+               void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RBFFD_H */

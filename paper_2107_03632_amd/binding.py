@@ -1,0 +1,225 @@
+"""Python binding of librbffd.so: same names as the C ABI, torch tensors in.
+
+Argument marshalling only.  Every step runs in the HIP library on the
+caller's current torch stream; torch provides device memory (outputs and
+workspaces) and the stream handle.  There is no CPU path: if the library is
+missing or a tensor is not on the GPU, the call raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librbffd.so")
+
+FP64, MIXED = 0, 1
+OK, SINGULAR, FELL_BACK_FP64, NONFINITE, BAD_INDEX, DUPLICATE, BAD_ORDER = range(7)
+DEFAULT_N_FOR_ORDER = (12, 30, 56)
+
+_lock = threading.Lock()
+_lib = None
+
+
+class RbffdError(RuntimeError):
+    pass
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise RbffdError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        lib = ctypes.CDLL(LIB_PATH)
+        P, I64, I32, SZ = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
+        PSZ = ctypes.POINTER(ctypes.c_size_t)
+        sig = {
+            "rbffd_error_string": ([ctypes.c_int], ctypes.c_char_p),
+            "rbffd_version": ([], ctypes.c_int),
+            "rbffd_knn_workspace_size": ([I64, I32, PSZ], ctypes.c_int),
+            "rbffd_knn": ([P, P, I64, I32, P, P, SZ, P], ctypes.c_int),
+            "rbffd_weights_workspace_size": ([I64, I32, I32, PSZ], ctypes.c_int),
+            "rbffd_weights_save_size": ([I64, I32, PSZ], ctypes.c_int),
+            "rbffd_weights": ([P, P, I64, P, I32, P, I32, I32, P, I32, P, P, P, SZ, P, SZ, P],
+                              ctypes.c_int),
+            "rbffd_weights_backward_workspace_size": ([I64, I32, PSZ], ctypes.c_int),
+            "rbffd_weights_backward": ([P, P, I64, P, I32, P, I32, I32, P, P, P, SZ, P, P, P,
+                                        P, SZ, P], ctypes.c_int),
+            "rbffd_assemble_csr_workspace_size": ([I64, PSZ], ctypes.c_int),
+            "rbffd_assemble_csr": ([I64, P, I32, P, I32, P, P, P, P, P, P, I64, P, SZ, P],
+                                   ctypes.c_int),
+            "rbffd_spmv": ([I64, P, P, P, P, P, P, P], ctypes.c_int),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = lib
+        return lib
+
+
+def library_path() -> str:
+    _load()
+    return LIB_PATH
+
+
+def error_string(code: int) -> str:
+    return _load().rbffd_error_string(code).decode()
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise RbffdError(f"{what} failed: {rc} ({error_string(rc)})")
+
+
+def _dev(t: torch.Tensor, dtype, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise RbffdError(f"{name} must be a GPU tensor (the library has no CPU path)")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    return t.contiguous()
+
+
+def _p(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _size(fn, *args) -> int:
+    out = ctypes.c_size_t(0)
+    _check(fn(*args, ctypes.byref(out)), fn.__name__)
+    return int(out.value)
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+
+
+def _n_for_order(n_for_order):
+    arr = (ctypes.c_int32 * 3)(*[int(v) for v in n_for_order])
+    return arr
+
+
+def n_monomials(m: int) -> int:
+    return (m + 1) * (m + 2) // 2
+
+
+# ---------------------------------------------------------------------------
+def rbffd_knn(x: torch.Tensor, y: torch.Tensor, k: int) -> torch.Tensor:
+    """k nearest nodes of every node, ascending by (d^2, index): int32 [N, k]."""
+    lib = _load()
+    x = _dev(x, torch.float64, "x")
+    y = _dev(y, torch.float64, "y")
+    N = x.numel()
+    ws = _workspace(_size(lib.rbffd_knn_workspace_size, N, k), x.device)
+    nbr = torch.empty((N, k), dtype=torch.int32, device=x.device)
+    _check(lib.rbffd_knn(_p(x), _p(y), N, k, _p(nbr), _p(ws), ws.numel(), _stream(x.device)),
+           "rbffd_knn")
+    return nbr
+
+
+def _order_args(order, m, n, n_for_order):
+    if order is None:
+        if m is None or n is None:
+            raise ValueError("give (m, n) or a per-node order")
+        return None, int(m), int(n), None, n + n_monomials(m)
+    kmax = max(nv + n_monomials(mv) for mv, nv in zip((2, 4, 6), n_for_order))
+    return _dev(order, torch.int8, "order"), -1, -1, _n_for_order(n_for_order), kmax
+
+
+def rbffd_weights(x, y, nbr, m=None, n=None, order=None, n_for_order=DEFAULT_N_FOR_ORDER,
+                  precision: int = FP64, save: bool = False, out=None, status=None):
+    """Laplacian stencil weights w [N, k_stride] (FP64) and status [N] int32.
+
+    Returns (w, status, save_buffer or None).  nbr is [N, k_stride] int32.
+    """
+    lib = _load()
+    x = _dev(x, torch.float64, "x")
+    y = _dev(y, torch.float64, "y")
+    nbr = _dev(nbr, torch.int32, "nbr")
+    N, ks = nbr.shape
+    o, m_, n_, nfo, kmax = _order_args(order, m, n, n_for_order)
+    w = out if out is not None else torch.empty((N, ks), dtype=torch.float64, device=x.device)
+    st = status if status is not None else torch.empty(N, dtype=torch.int32, device=x.device)
+    sv = None
+    if save:
+        sv = _workspace(_size(lib.rbffd_weights_save_size, N, kmax), x.device)
+    ws = _workspace(_size(lib.rbffd_weights_workspace_size, N, int(o is not None), precision),
+                    x.device)
+    _check(lib.rbffd_weights(_p(x), _p(y), N, _p(nbr), ks, _p(o), m_, n_, nfo, precision,
+                             _p(w), _p(st), _p(sv), 0 if sv is None else sv.numel(), _p(ws),
+                             ws.numel(), _stream(x.device)), "rbffd_weights")
+    return w, st, sv
+
+
+def rbffd_weights_backward(x, y, nbr, grad_w, save, status=None, m=None, n=None, order=None,
+                           n_for_order=DEFAULT_N_FOR_ORDER):
+    """dL/dx, dL/dy [N] from dL/dw, reusing the factors saved by rbffd_weights."""
+    lib = _load()
+    x = _dev(x, torch.float64, "x")
+    y = _dev(y, torch.float64, "y")
+    nbr = _dev(nbr, torch.int32, "nbr")
+    grad_w = _dev(grad_w, torch.float64, "grad_w")
+    N, ks = nbr.shape
+    o, m_, n_, nfo, _ = _order_args(order, m, n, n_for_order)
+    gx = torch.empty(N, dtype=torch.float64, device=x.device)
+    gy = torch.empty(N, dtype=torch.float64, device=x.device)
+    ws = _workspace(_size(lib.rbffd_weights_backward_workspace_size, N, ks), x.device)
+    st = None if status is None else _dev(status, torch.int32, "status")
+    _check(lib.rbffd_weights_backward(_p(x), _p(y), N, _p(nbr), ks, _p(o), m_, n_, nfo,
+                                      _p(grad_w), _p(save), save.numel(), _p(st), _p(gx), _p(gy),
+                                      _p(ws), ws.numel(), _stream(x.device)),
+           "rbffd_weights_backward")
+    return gx, gy
+
+
+def rbffd_assemble_csr(nbr, w, n=None, order=None, n_for_order=DEFAULT_N_FOR_ORDER,
+                       is_boundary=None):
+    """CSR operator: (row_ptr int64 [N+1], col int32 [cap], val f64 [cap]).
+
+    col/val have capacity N * max n; the first row_ptr[N] entries are valid.
+    """
+    lib = _load()
+    nbr = _dev(nbr, torch.int32, "nbr")
+    w = _dev(w, torch.float64, "w")
+    N, ks = nbr.shape
+    if order is None:
+        o, nfo, nmax = None, None, int(n)
+    else:
+        o, nfo, nmax = _dev(order, torch.int8, "order"), _n_for_order(n_for_order), max(n_for_order)
+    b = None if is_boundary is None else _dev(is_boundary, torch.uint8, "is_boundary")
+    cap = N * nmax
+    row_ptr = torch.empty(N + 1, dtype=torch.int64, device=nbr.device)
+    col = torch.empty(cap, dtype=torch.int32, device=nbr.device)
+    val = torch.empty(cap, dtype=torch.float64, device=nbr.device)
+    ws = _workspace(_size(lib.rbffd_assemble_csr_workspace_size, N), nbr.device)
+    _check(lib.rbffd_assemble_csr(N, _p(nbr), ks, _p(o), -1 if n is None else int(n), nfo,
+                                  _p(w), _p(b), _p(row_ptr), _p(col), _p(val), cap, _p(ws),
+                                  ws.numel(), _stream(nbr.device)), "rbffd_assemble_csr")
+    return row_ptr, col, val
+
+
+def rbffd_spmv(row_ptr, col, val, u, f=None, out=None):
+    """y = W u - f (f optional) for a CSR matrix."""
+    lib = _load()
+    row_ptr = _dev(row_ptr, torch.int64, "row_ptr")
+    col = _dev(col, torch.int32, "col")
+    val = _dev(val, torch.float64, "val")
+    u = _dev(u, torch.float64, "u")
+    fz = None if f is None else _dev(f, torch.float64, "f")
+    n = row_ptr.numel() - 1
+    y = out if out is not None else torch.empty(n, dtype=torch.float64, device=u.device)
+    _check(lib.rbffd_spmv(n, _p(row_ptr), _p(col), _p(val), _p(u), _p(fz), _p(y),
+                          _stream(u.device)), "rbffd_spmv")
+    return y
