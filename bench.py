@@ -1,0 +1,258 @@
+"""Benchmark of the RBF-FD Laplacian hot path on one MI355X.
+
+One step = one pass of the whole path over the unit-disk workload (about
+100k jittered interior nodes plus 1000 boundary nodes, m = 4, n = 30):
+kNN supports -> FP64 stencil weights -> CSR operator with Dirichlet rows ->
+residual W u - f.  Inputs are resident in HBM before the timed region.
+
+Printed: one JSON line with whole-step throughput (stencils/s), the
+roofline position of the dominant kernel (the weights kernel, timed live
+with HIP events on the stream it runs on), the oracle's CPU throughput on a
+bounded sample of the same workload, and per-order / mixed-order weights
+throughputs on the 1M-node square as extra fields.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6      # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+HBM_PEAK_GBS = 8000.0
+
+
+def n_monomials(m: int) -> int:
+    return (m + 1) * (m + 2) // 2
+
+
+def weights_flops(m: int, n: int) -> int:
+    """Algorithmic FP64 flops of one stencil: LU of the K x K system, the two
+    triangular solves and the assembly (pivot search and swaps not counted,
+    a square root counts as one)."""
+    M = n_monomials(m)
+    K = n + M
+    lu = (K - 1) * K // 2 + (K - 1) * K * (2 * K - 1) // 3
+    solves = 2 * K * (K - 1) + K
+    assembly = 4 * n * (n - 1) + 12 * (n - 1) + n * (M - 1) + n
+    return lu + solves + assembly
+
+
+def source_digest(paths) -> str:
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+WEIGHTS_SOURCES = ["paper_2107_03632_amd/csrc/weights_kernel.h",
+                   "paper_2107_03632_amd/csrc/weights_k45.hip"]
+
+
+def read_traffic(kernel_tag: str):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary, or
+    None when the kernel source changed after the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_tag}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha") != source_digest(WEIGHTS_SOURCES):
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(ns, m, n, stride):
+    """The oracle, single-threaded, on every stride-th node: brute-force kNN,
+    weights, CSR rows and SpMV rows for those stencils."""
+    import oracle
+    from paper_2107_03632_amd.nodes import manufactured
+    rows = np.arange(0, ns.n_nodes, stride)
+    t0 = time.perf_counter()
+    nb = oracle.knn(ns.x, ns.y, n, queries=rows)
+    t1 = time.perf_counter()
+    full = np.zeros((ns.n_nodes, n), dtype=np.int32)
+    full[rows] = nb
+    w, st = oracle.weights(ns.x, ns.y, full, m=m, n=n, rows=rows)
+    t2 = time.perf_counter()
+    rp, col, val = oracle.csr(nb, w, n=n, is_boundary=ns.is_boundary[rows])
+    u, f = manufactured(ns.x, ns.y)
+    oracle.spmv(rp, col, val, u, f[rows])
+    t3 = time.perf_counter()
+    return {"value": len(rows) / (t3 - t0), "unit": "stencils/s", "cores": 1, "kind": "oracle",
+            "sample": f"{len(rows)} of {ns.n_nodes} stencils (every {stride}th node): "
+                      f"brute-force kNN {t1 - t0:.2f} s, weights {t2 - t1:.2f} s, "
+                      f"CSR+SpMV {t3 - t2:.2f} s, one thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the per-order and mixed-order 1M-node measurements")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one plain device copy of known size first (for --pmc scaling)")
+    ap.add_argument("--cpu-stride", type=int, default=7)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, "
+              f"WORLD_SIZE={world}); stencils are independent, the multi-GPU "
+              f"sharding is described in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2107_03632_amd import binding as rb
+    from paper_2107_03632_amd import nodes
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    if args.copy_calibration:
+        nbytes = 1 << 30
+        a = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"copy calibration: {nbytes} bytes read, {nbytes} bytes written", file=sys.stderr)
+        del a, b
+
+    m, n = 4, 30
+    ns = nodes.workload("disk_100k_m4")
+    N = ns.n_nodes
+    X = torch.as_tensor(ns.x, device=dev)
+    Y = torch.as_tensor(ns.y, device=dev)
+    B = torch.as_tensor(ns.is_boundary, device=dev)
+    u_h, f_h = nodes.manufactured(ns.x, ns.y)
+    U = torch.as_tensor(u_h, device=dev)
+    F = torch.as_tensor(f_h, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    ev = []
+
+    def step(record):
+        nbr = rb.rbffd_knn(X, Y, n)
+        if record:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+        w, st, _ = rb.rbffd_weights(X, Y, nbr, m=m, n=n)
+        if record:
+            e1.record(stream)
+            ev.append((e0, e1))
+        rp, col, val = rb.rbffd_assemble_csr(nbr, w, n=n, is_boundary=B)
+        r = rb.rbffd_spmv(rp, col, val, U, F)
+        return r, st
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r, st = step(True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_step = 1e3 * elapsed / args.steps
+    w_ms = [a.elapsed_time(b) for a, b in ev]
+    w_ms_avg = float(np.mean(w_ms))
+    bad = int((st != 0).sum().item())
+    resid = r[B == 0].abs().max().item()
+
+    flops_launch = weights_flops(m, n) * N
+    achieved = flops_launch / (w_ms_avg * 1e-3) / 1e12
+    traffic = read_traffic("weights_k45_disk100k")
+    out = {
+        "metric": "RBF-FD Laplacian stencils/s (kNN + FP64 weights + CSR + residual), "
+                  "unit disk ~100k nodes, m=4, n=30",
+        "value": N / (ms_step * 1e-3),
+        "unit": "stencils/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded jittered lattice on the unit disk)",
+        "config": {"workload": "unit disk, 100k jittered lattice nodes + 1000 boundary, "
+                               "m=4, n=30, FP64: kNN -> weights -> CSR -> W u - f",
+                   "n_nodes": N, "m": m, "n": n, "global_batch": N, "parallelism": "none"},
+        "roofline": {"bound": "alu", "kernel": "weights_fp64_kernel<45,64,30,4>",
+                     "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
+                     "flops_per_stencil": weights_flops(m, n), "launch_ms": w_ms_avg},
+        "weights_stencils_per_s": N / (w_ms_avg * 1e-3),
+        "failed_stencils": bad,
+        "residual_max_interior": resid,
+    }
+
+    if not args.no_extras:
+        out["per_order_1M_square"] = extras_per_order(torch, rb, nodes, dev, stream)
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(ns, m, n, args.cpu_stride)
+
+    print(json.dumps(out), flush=True)
+
+
+def timed(torch, stream, fn, reps=3):
+    fn()
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts))
+
+
+def extras_per_order(torch, rb, nodes, dev, stream):
+    """Weights-kernel throughput on the 1M-node cell-centred square at m = 2,
+    4, 6 (uniform) and for the per-node {2,4,6} mixed batch."""
+    ns = nodes.workload("square_1m_mixed")
+    X = torch.as_tensor(ns.x, device=dev)
+    Y = torch.as_tensor(ns.y, device=dev)
+    nbr = rb.rbffd_knn(X, Y, 56)
+    N = ns.n_nodes
+    res = {"n_nodes": N}
+    for m, n in ((2, 12), (4, 30), (6, 56)):
+        ms = timed(torch, stream, lambda: rb.rbffd_weights(X, Y, nbr, m=m, n=n))
+        res[f"m{m}_n{n}"] = {"stencils_per_s": N / (ms * 1e-3), "ms": ms,
+                             "frac_fp64_peak": weights_flops(m, n) * N / (ms * 1e-3) / 1e12
+                             / FP64_PEAK_TFLOPS}
+    O = torch.as_tensor(ns.order, device=dev)
+    ms = timed(torch, stream, lambda: rb.rbffd_weights(X, Y, nbr, order=O))
+    counts = {mm: int((ns.order == mm).sum()) for mm in (2, 4, 6)}
+    fl = sum(counts[mm] * weights_flops(mm, nn) for mm, nn in ((2, 12), (4, 30), (6, 56)))
+    res["mixed_order"] = {"stencils_per_s": N / (ms * 1e-3), "ms": ms,
+                          "frac_fp64_peak": fl / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS}
+    ms_knn = timed(torch, stream, lambda: rb.rbffd_knn(X, Y, 56))
+    res["knn_k56_ms"] = ms_knn
+    return res
+
+
+if __name__ == "__main__":
+    main()
