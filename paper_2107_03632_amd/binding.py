@@ -223,3 +223,34 @@ def rbffd_spmv(row_ptr, col, val, u, f=None, out=None):
     _check(lib.rbffd_spmv(n, _p(row_ptr), _p(col), _p(val), _p(u), _p(fz), _p(y),
                           _stream(u.device)), "rbffd_spmv")
     return y
+
+
+class _WeightsFn(torch.autograd.Function):
+    """w = weights(x, y) with the adjoint kernel as backward (supports fixed)."""
+
+    @staticmethod
+    def forward(ctx, x, y, nbr, m, n, order, n_for_order):
+        w, st, sv = rbffd_weights(x, y, nbr, m=m, n=n, order=order, n_for_order=n_for_order,
+                                  save=True)
+        ctx.save_for_backward(x, y, nbr, st, sv, order if order is not None else torch.empty(0))
+        ctx.has_order = order is not None
+        ctx.mn = (m, n, tuple(n_for_order))
+        ctx.mark_non_differentiable(st)
+        return w, st
+
+    @staticmethod
+    def backward(ctx, gw, _gst):
+        x, y, nbr, st, sv, order = ctx.saved_tensors
+        m, n, nfo = ctx.mn
+        gx, gy = rbffd_weights_backward(x, y, nbr, gw.contiguous(), sv, status=st, m=m, n=n,
+                                        order=order if ctx.has_order else None, n_for_order=nfo)
+        return gx, gy, None, None, None, None, None
+
+
+def weights(x, y, nbr, m=None, n=None, order=None, n_for_order=DEFAULT_N_FOR_ORDER):
+    """Differentiable weights: (w, status).  When x or y requires grad, the
+    forward stores its LU factors and backward runs rbffd_weights_backward."""
+    if x.requires_grad or y.requires_grad:
+        return _WeightsFn.apply(x, y, nbr, m, n, order, n_for_order)
+    w, st, _ = rbffd_weights(x, y, nbr, m=m, n=n, order=order, n_for_order=n_for_order)
+    return w, st

@@ -175,17 +175,3 @@ extern "C" int rbffd_weights(const double *x, const double *y, int64_t n_nodes,
     }
     return RBFFD_SUCCESS;
 }
-
-extern "C" int rbffd_weights_backward_workspace_size(int64_t n_nodes, int32_t k_stride,
-                                                     size_t *bytes) {
-    if (!bytes || n_nodes < 1 || k_stride < 1) return RBFFD_ERR_ARG;
-    *bytes = 256;
-    return RBFFD_SUCCESS;
-}
-
-extern "C" int rbffd_weights_backward(const double *, const double *, int64_t, const int32_t *,
-                                      int32_t, const int8_t *, int32_t, int32_t, const int32_t *,
-                                      const double *, const void *, size_t, const int32_t *,
-                                      double *, double *, void *, size_t, void *) {
-    return RBFFD_ERR_UNSUPPORTED;
-}

@@ -1,8 +1,18 @@
-// FP64 weights kernel instance: KP = 45 rows padded, 64 lanes per stencil.
-#include "weights_kernel.h"
+// FP64 weights kernel instance: K = 45 (m = 4, n = 30), 32 lanes x 2 rows per stencil, 2 stencils per wave.
+#include "weights_ms.h"
+
+#ifndef RBFFD_SEG_K45
+#define RBFFD_SEG_K45 32
+#endif
+#ifndef RBFFD_SL_K45
+#define RBFFD_SL_K45 2
+#endif
+#ifndef RBFFD_OCC_K45
+#define RBFFD_OCC_K45 0
+#endif
 
 namespace rbffd {
 int weights_fp64_k45(const double *x, const double *y, int64_t n_nodes, const int32_t *nbr, int32_t k_stride, const int32_t *rows, const int32_t *n_rows_dev, int64_t n_rows, int n, int m, double *w, int32_t *status, const wk::SaveView &sv, hipStream_t stream) {
-    return wk::launch_fp64<45, 64, 30, 4>(x, y, n_nodes, nbr, k_stride, rows, n_rows_dev, n_rows, n, m, w, status, sv, stream);
+    return wk::launch_ms<45, RBFFD_SEG_K45, RBFFD_SL_K45, 30, 4, RBFFD_OCC_K45>(x, y, n_nodes, nbr, k_stride, rows, n_rows_dev, n_rows, n, m, w, status, sv, stream);
 }
 }  // namespace rbffd

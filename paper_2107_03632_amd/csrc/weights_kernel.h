@@ -12,20 +12,29 @@
 //     of the augmented matrix [M | rhs], held in registers (a[0..KP), yv).
 //     K = n + M(m) real rows; rows K..KP-1 are identity padding, which leaves
 //     every operation on the real rows unchanged.
+//   * Assembly is divergence-free: every lane evaluates the r^3 entries of
+//     its row; the monomials of each support node are tabulated once in LDS
+//     and read back both as the P block (support rows) and as P^T
+//     (polynomial rows).
 //   * Partial pivoting is logical: rows stay in their lanes and carry their
 //     current position `pos`.  Column c's pivot is the active row with the
 //     largest |a[c]|, ties to the lowest position -- exactly the row a
-//     physical row-swapping elimination would pick.  The search is a
-//     butterfly over (|a| high word, |a| low word, position) keys.
-//   * The pivot row is broadcast through LDS (double-buffered by step parity,
-//     so one barrier per step), and every other active lane applies
-//     l = a[c] * (1/pivot), a[q] = fma(-l, u[q], a[q]) to its own row.
-//   * Back substitution walks the columns from the last, one LDS broadcast of
-//     z_c per step.  Each lane ends with z at its position.
+//     physical row-swapping elimination picks.  The search takes the maximum
+//     of the high words of |a[c]| with a DPP row_shr/row_bcast reduction and
+//     a ballot; only when that maximum is not unique does it fall back to a
+//     butterfly over the full (|a|, position) key.
+//   * The pivot row is broadcast through LDS (double-buffered by step
+//     parity).  Every row applies l = a[c] * (1/pivot),
+//     a[q] = fma(-l, u[q], a[q]); rows already pivoted use l = 0, which
+//     leaves their values unchanged (up to the sign of an exact zero), so the
+//     update needs no divergent branch.
+//   * Back substitution walks the columns from the last; z_c is read from the
+//     lane holding position c with readlane (one wave) or through LDS (a group
+//     spanning two waves).
 // The sequence of IEEE operations equals that of the FP64 reference
 // definition (same divisions, square roots, products and fused updates in the
-// same order), so results agree to the last bit where the compiler keeps
-// that order (no contraction: built with -ffp-contract=off).
+// same order), so the values agree exactly (no contraction: built with
+// -ffp-contract=off).
 
 #include "common.h"
 
@@ -50,13 +59,6 @@ __host__ __device__ constexpr int mono_deg(int j) {
 __host__ __device__ constexpr int mono_b(int j) { return j - mono_deg(j) * (mono_deg(j) + 1) / 2; }
 __host__ __device__ constexpr int mono_a(int j) { return mono_deg(j) - mono_b(j); }
 
-// u^a by repeated multiplication starting from 1
-__device__ __forceinline__ double rep_pow(double u, int a) {
-    double p = 1.0;
-    for (int t = 0; t < a; ++t) p = p * u;
-    return p;
-}
-
 template <int W>
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
@@ -77,6 +79,7 @@ __device__ __forceinline__ bool key_better(uint32_t h1, uint32_t l1, int p1, uin
     return h1 > h2 || (h1 == h2 && (l1 > l2 || (l1 == l2 && p1 < p2)));
 }
 
+// full-key butterfly over the W-lane segment (the rare tie path)
 template <int W>
 __device__ __forceinline__ void wave_argmax(uint32_t &kh, uint32_t &kl, int &kp) {
 #pragma unroll
@@ -92,6 +95,87 @@ __device__ __forceinline__ void wave_argmax(uint32_t &kh, uint32_t &kl, int &kp)
     }
 }
 
+// one DPP step of an unsigned max (lanes without a source read 0)
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ uint32_t umax_dpp(uint32_t v) {
+    const uint32_t o = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWMASK, 0xf, true);
+    return v > o ? v : o;
+}
+
+// Maximum over each W-lane segment (W = 32 or 64), returned to every lane of
+// the segment.  row_shr 1/2/4/8 leave each 16-lane row's maximum in its
+// last lane; row_bcast:15 folds rows pairwise (lanes 31 and 63), row_bcast:31
+// folds the two halves (lane 63).
+template <int W>
+__device__ __forceinline__ uint32_t seg_umax(uint32_t v, int lane) {
+    v = umax_dpp<0x111, 0xf>(v);  // row_shr:1
+    v = umax_dpp<0x112, 0xf>(v);  // row_shr:2
+    v = umax_dpp<0x114, 0xf>(v);  // row_shr:4
+    v = umax_dpp<0x118, 0xf>(v);  // row_shr:8
+    v = umax_dpp<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    if constexpr (W == 64) {
+        v = umax_dpp<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+        return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+    } else {
+        const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)v, 31);
+        const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+        return lane < 32 ? a : b;
+    }
+}
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// First set lane of a ballot inside the caller's W-lane segment, or -1.
+template <int W>
+__device__ __forceinline__ int seg_first(uint64_t mask, int lane) {
+    if constexpr (W == 64) {
+        return mask ? __ffsll((unsigned long long)mask) - 1 : -1;
+    } else {
+        const uint32_t lo = (uint32_t)mask, hi = (uint32_t)(mask >> 32);
+        const int a = lo ? __ffs(lo) - 1 : -1;
+        const int b = hi ? __ffs(hi) + 31 : -1;
+        return lane < 32 ? a : b;
+    }
+}
+
+// Every W-lane segment of the ballot has at most one bit set.
+template <int W>
+__device__ __forceinline__ bool seg_at_most_one(uint64_t mask) {
+    if constexpr (W == 64) {
+        return __popcll((unsigned long long)mask) <= 1;
+    } else {
+        return __popc((uint32_t)mask) <= 1 && __popc((uint32_t)(mask >> 32)) <= 1;
+    }
+}
+
+// readlane of an int from the segment's lane L (uniform per segment)
+template <int W>
+__device__ __forceinline__ int seg_read_i(int v, int L0, int L1, int lane) {
+    if constexpr (W == 64) {
+        return __builtin_amdgcn_readlane(v, L0);
+    } else {
+        const int a = __builtin_amdgcn_readlane(v, L0 < 0 ? 0 : L0);
+        const int b = __builtin_amdgcn_readlane(v, L1 < 0 ? 32 : L1);
+        return lane < 32 ? a : b;
+    }
+}
+
+template <int W>
+__device__ __forceinline__ double seg_read_d(double v, int L0, int L1, int lane) {
+    if constexpr (W == 64) {
+        return readlane_d(v, L0);
+    } else {
+        const double a = readlane_d(v, L0 < 0 ? 0 : L0);
+        const double b = readlane_d(v, L1 < 0 ? 32 : L1);
+        return lane < 32 ? a : b;
+    }
+}
+
 __host__ __device__ constexpr int block_threads(int G) { return G < kWave ? kWave : G; }
 
 template <int KP, int G>
@@ -101,10 +185,14 @@ struct Shape {
     static constexpr int kW = G < kWave ? G : kWave;      // group lanes per wave
     static constexpr int kNW = G / kW;                    // waves per group
     static_assert(KP <= G, "one row per lane");
+    static_assert(kW == 32 || kW == 64, "segments of 32 or 64 lanes");
 };
 
-template <int KP, int G, int NFIX, int MFIX>
-__global__ __launch_bounds__(block_threads(G)) void weights_fp64_kernel(
+// OCC: minimum waves per SIMD the register allocation must allow (0: the
+// compiler's choice).
+template <int KP, int G, int NFIX, int MFIX, int OCC>
+__global__ __launch_bounds__(block_threads(G))
+__attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1))) void weights_fp64_kernel(
     const double *__restrict__ x, const double *__restrict__ y, int64_t n_nodes,
     const int32_t *__restrict__ nbr, int32_t k_stride, const int32_t *__restrict__ rows,
     const int32_t *__restrict__ n_rows_dev, int64_t n_rows, int32_t n_arg, int32_t m_arg,
@@ -115,12 +203,15 @@ __global__ __launch_bounds__(block_threads(G)) void weights_fp64_kernel(
     constexpr int GPB = S::kGroups;
     constexpr int W = S::kW;
     constexpr int NW = S::kNW;
+    constexpr int MM = MFIX ? (MFIX + 1) * (MFIX + 2) / 2 : 28;  // monomial table width
     const int n = NFIX ? NFIX : n_arg;
     const int m = MFIX ? MFIX : m_arg;
-    const int K = n + (m + 1) * (m + 2) / 2;
+    const int NM = (m + 1) * (m + 2) / 2;
+    const int K = n + NM;
 
     __shared__ double s_ux[GPB][KP];
     __shared__ double s_uy[GPB][KP];
+    __shared__ double s_P[GPB][KP][MM];
     __shared__ double s_row[2][GPB][NW][KP + 1];
     __shared__ uint32_t s_key[2][GPB][NW][4];
     __shared__ double s_z[GPB][KP];
@@ -128,9 +219,10 @@ __global__ __launch_bounds__(block_threads(G)) void weights_fp64_kernel(
     __shared__ uint32_t s_flg[GPB][NW];
 
     const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
     const int g = tid / G;
-    const int r = tid % G;              // row owned by this lane
-    const int wv = (tid % G) / W;       // wave of the group this lane sits in
+    const int r = tid % G;         // row owned by this lane
+    const int wv = (tid % G) / W;  // wave of the group this lane sits in
     const bool wave_leader = (tid % W) == 0;
     if (n_rows_dev) n_rows = *n_rows_dev;
     if ((int64_t)blockIdx.x * GPB >= n_rows) return;  // whole block idle: no barrier reached
@@ -167,48 +259,58 @@ __global__ __launch_bounds__(block_threads(G)) void weights_fp64_kernel(
     const double s = sqrt(d2max);
     if (s == 0.0) flags |= F_DUP;
 
-    // ---- scale -----------------------------------------------------------
+    // ---- scale; monomials of each support node ---------------------------
+    const bool prow = r < n;             // support (r^3) row
+    const bool qrow = r >= n && r < K;   // polynomial row
+    const int jr = qrow ? r - n : 0;     // its monomial index
     double ux = 0.0, uy = 0.0;
-    if (r < n) {
+    if (prow) {
         ux = dx / s;
         uy = dy / s;
         s_ux[g][r] = ux;
         s_uy[g][r] = uy;
+        double px[7], py[7];
+        px[0] = 1.0;
+        py[0] = 1.0;
+#pragma unroll
+        for (int e = 1; e < 7; ++e) {
+            px[e] = px[e - 1] * ux;
+            py[e] = py[e - 1] * uy;
+        }
+#pragma unroll
+        for (int j = 0; j < MM; ++j)
+            if (j < NM) s_P[g][r][j] = px[mono_a(j)] * py[mono_b(j)];
     }
     __syncthreads();
 
     // ---- assemble row r of [A P; P^T 0 | rhs] ---------------------------
     double a[KP];
-    double yv = 0.0;
-    if (r < n) {
 #pragma unroll
-        for (int l = 0; l < KP; ++l) {
-            if (l < n) {
-                const double ex = ux - s_ux[g][l];
-                const double ey = uy - s_uy[g][l];
-                const double rr = ex * ex + ey * ey;
-                if (l != r && rr == 0.0) flags |= F_DUP;
-                a[l] = rr * sqrt(rr);
-            } else if (l < K) {
-                const int j = l - n;
-                a[l] = rep_pow(ux, mono_a(j)) * rep_pow(uy, mono_b(j));
-            } else {
-                a[l] = 0.0;
-            }
+    for (int l = 0; l < KP; ++l) {
+        if (l < n) {
+            const double ex = ux - s_ux[g][l];
+            const double ey = uy - s_uy[g][l];
+            const double rr = ex * ex + ey * ey;
+            if (prow && l != r && rr == 0.0) flags |= F_DUP;
+            const double phs = rr * sqrt(rr);
+            const double pt = s_P[g][l][jr];
+            a[l] = prow ? phs : (qrow ? pt : 0.0);
+        } else if (l < K) {
+            a[l] = prow ? s_P[g][r < KP ? r : 0][l - n] : 0.0;
+        } else {
+            a[l] = (l == r) ? 1.0 : 0.0;
         }
-        const double r0 = ux * ux + uy * uy;
-        yv = 9.0 * sqrt(r0);
-    } else if (r < K) {
-        const int j = r - n;
-        const int ea = mono_a(j), eb = mono_b(j);
-#pragma unroll
-        for (int l = 0; l < KP; ++l)
-            a[l] = (l < n) ? rep_pow(s_ux[g][l], ea) * rep_pow(s_uy[g][l], eb) : 0.0;
-        yv = ((ea == 2 && eb == 0) || (ea == 0 && eb == 2)) ? 2.0 : 0.0;
-    } else {
-#pragma unroll
-        for (int l = 0; l < KP; ++l) a[l] = (l == r) ? 1.0 : 0.0;
     }
+    double yv;
+    {
+        const double r0 = ux * ux + uy * uy;
+        const double rb = 9.0 * sqrt(r0);
+        yv = prow ? rb : ((qrow && (jr == 3 || jr == 5)) ? 2.0 : 0.0);
+    }
+
+    // materialise the flags here: otherwise the duplicate checks sink to the
+    // end of the kernel and keep every squared distance alive through the LU
+    asm volatile("" : "+v"(flags));
 
     // ---- LU with partial pivoting, right-looking, rhs carried along ------
     int pos = r;
@@ -219,41 +321,65 @@ __global__ __launch_bounds__(block_threads(G)) void weights_fp64_kernel(
     for (int c = 0; c < KP; ++c) {
         const int buf = c & 1;
         const uint64_t bits = (uint64_t)__double_as_longlong(a[c]) & 0x7fffffffffffffffull;
-        uint32_t kh = done ? 0u : (uint32_t)(bits >> 32) + 1u;
-        uint32_t kl = done ? 0u : (uint32_t)bits;
-        int kp = done ? 0x7fffffff : pos;
-        wave_argmax<W>(kh, kl, kp);
-        // the wave-local winner publishes its row, the wave leader its key
-        if (!done && pos == kp) {
+        const uint32_t kh = done ? 0u : (uint32_t)(bits >> 32) + 1u;
+        // winner lane of this wave's segment (uniform per segment), -1 if none
+        int win;
+        {
+            const uint32_t mh = seg_umax<W>(kh, lane);
+            const uint64_t cand = __ballot(!done && kh == mh);
+            if (__builtin_expect(seg_at_most_one<W>(cand), 1)) {
+                win = seg_first<W>(cand, lane);
+            } else {
+                uint32_t h2 = kh, l2 = done ? 0u : (uint32_t)bits;
+                int p2 = done ? 0x7fffffff : pos;
+                wave_argmax<W>(h2, l2, p2);
+                win = seg_first<W>(__ballot(!done && pos == p2), lane);
+            }
+        }
+        // segment winners as scalars (for readlane)
+        int w0, w1;
+        if constexpr (W == 64) {
+            w0 = __builtin_amdgcn_readfirstlane(win);
+            w1 = w0;
+        } else {
+            w0 = __builtin_amdgcn_readlane(win, 0);
+            w1 = __builtin_amdgcn_readlane(win, 32);
+        }
+        const bool local_piv = (lane == win);
+        if (local_piv) {
 #pragma unroll
             for (int q = c; q < KP; ++q) s_row[buf][g][wv][q] = a[q];
             s_row[buf][g][wv][KP] = yv;
         }
+        int kp = seg_read_i<W>(pos, w0, w1, lane);
+        int src = 0;
         if constexpr (NW > 1) {
             if (wave_leader) {
-                s_key[buf][g][wv][0] = kh;
-                s_key[buf][g][wv][1] = kl;
-                s_key[buf][g][wv][2] = (uint32_t)kp;
+                const bool any = w0 >= 0;
+                s_key[buf][g][wv][0] = any ? (uint32_t)__builtin_amdgcn_readlane((int)kh, w0) : 0u;
+                s_key[buf][g][wv][1] =
+                    any ? (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)bits, w0) : 0u;
+                s_key[buf][g][wv][2] = any ? (uint32_t)kp : 0x7fffffffu;
             }
         }
         __syncthreads();
-        int src = 0;
         if constexpr (NW > 1) {
-            kh = s_key[buf][g][0][0];
-            kl = s_key[buf][g][0][1];
-            kp = (int)s_key[buf][g][0][2];
+            uint32_t bh = s_key[buf][g][0][0], bl = s_key[buf][g][0][1];
+            int bp = (int)s_key[buf][g][0][2];
 #pragma unroll
             for (int v = 1; v < NW; ++v) {
                 const uint32_t oh = s_key[buf][g][v][0], ol = s_key[buf][g][v][1];
                 const int op = (int)s_key[buf][g][v][2];
-                if (key_better(oh, ol, op, kh, kl, kp)) {
-                    kh = oh;
-                    kl = ol;
-                    kp = op;
+                if (key_better(oh, ol, op, bh, bl, bp)) {
+                    bh = oh;
+                    bl = ol;
+                    bp = op;
                     src = v;
                 }
             }
+            kp = bp;
         }
+        const bool is_piv = local_piv && (wv == src);
         const double *u = s_row[buf][g][src];
         const double piv = u[c];
         const double inv = 1.0 / piv;
@@ -261,32 +387,42 @@ __global__ __launch_bounds__(block_threads(G)) void weights_fp64_kernel(
             if (!isfinite(piv)) luflag = L_NONFIN;
             else if (piv == 0.0) luflag = L_SING;
         }
-        if (!done) {
-            if (pos == kp) {
-                done = true;
-                myinv = inv;
-                pos = c;
-            } else {
-                if (pos == c) pos = kp;  // the row at position c takes the pivot's place
-                const double l = a[c] * inv;
-                a[c] = l;
+        const bool upd = !done && !is_piv;
+        const double l = upd ? a[c] * inv : 0.0;
+        a[c] = upd ? l : a[c];
 #pragma unroll
-                for (int q = c + 1; q < KP; ++q) a[q] = fma(-l, u[q], a[q]);
-                yv = fma(-l, u[KP], yv);
-            }
-        }
+        for (int q = c + 1; q < KP; ++q) a[q] = fma(-l, u[q], a[q]);
+        yv = fma(-l, u[KP], yv);
+        // the row at position c takes the pivot's old place
+        pos = is_piv ? c : ((!done && pos == c) ? kp : pos);
+        myinv = is_piv ? inv : myinv;
+        done = done || is_piv;
     }
 
     // ---- back substitution: z_c = y_c / U_cc, from the last column -------
     double zmine = 0.0;
 #pragma unroll
     for (int c = KP - 1; c >= 0; --c) {
-        if (pos == c) {
-            zmine = yv * myinv;
-            s_z[g][c] = zmine;
+        const double zc = yv * myinv;
+        double z;
+        if constexpr (NW == 1) {
+            const int L = seg_first<W>(__ballot(pos == c), lane);
+            int L0, L1;
+            if constexpr (W == 64) {
+                L0 = __builtin_amdgcn_readfirstlane(L);
+                L1 = L0;
+            } else {
+                L0 = __builtin_amdgcn_readlane(L, 0);
+                L1 = __builtin_amdgcn_readlane(L, 32);
+            }
+            z = seg_read_d<W>(zc, L0, L1, lane);
+        } else {
+            if (pos == c) s_z[g][c] = zc;
+            __syncthreads();
+            z = s_z[g][c];
         }
-        __syncthreads();
-        if (pos < c) yv = fma(-a[c], s_z[g][c], yv);
+        zmine = (pos == c) ? zc : zmine;
+        yv = (pos < c) ? fma(-a[c], z, yv) : yv;
     }
 
     // ---- status ----------------------------------------------------------
@@ -323,23 +459,22 @@ __global__ __launch_bounds__(block_threads(G)) void weights_fp64_kernel(
     }
 }
 
-
 struct SaveView {
     double *lu = nullptr, *z = nullptr, *s = nullptr;
     uint8_t *perm = nullptr;
     int32_t kmax = 0;
 };
 
-template <int KP, int G, int NFIX, int MFIX>
+template <int KP, int G, int NFIX, int MFIX, int OCC = 0>
 inline int launch_fp64(const double *x, const double *y, int64_t n_nodes, const int32_t *nbr,
-                int32_t k_stride, const int32_t *rows, const int32_t *n_rows_dev,
-                int64_t n_rows, int n, int m, double *w, int32_t *status, const SaveView &sv,
-                hipStream_t stream) {
+                       int32_t k_stride, const int32_t *rows, const int32_t *n_rows_dev,
+                       int64_t n_rows, int n, int m, double *w, int32_t *status,
+                       const SaveView &sv, hipStream_t stream) {
     using S = Shape<KP, G>;
     if (n_rows <= 0) return RBFFD_SUCCESS;
     const int64_t blocks = ceil_div(n_rows, S::kGroups);
     if (blocks > 0x7fffffff) return RBFFD_ERR_UNSUPPORTED;
-    hipLaunchKernelGGL((weights_fp64_kernel<KP, G, NFIX, MFIX>), dim3((unsigned)blocks),
+    hipLaunchKernelGGL((weights_fp64_kernel<KP, G, NFIX, MFIX, OCC>), dim3((unsigned)blocks),
                        dim3(S::kBlock), 0, stream, x, y, n_nodes, nbr, k_stride, rows,
                        n_rows_dev, n_rows, n, m, w, status, sv.lu, sv.z, sv.s, sv.perm,
                        sv.kmax);

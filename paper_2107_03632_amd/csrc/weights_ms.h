@@ -1,0 +1,424 @@
+#pragma once
+// RBF-FD Laplacian stencil weights, FP64: several stencils per wavefront,
+// several matrix rows per lane.
+//
+// Same arithmetic as weights_kernel.h (the sequence of IEEE operations of
+// the reference definition: shift, scale, r^3 + monomial assembly, LU with
+// partial pivoting using pivot reciprocals and fma(-l, u, a) updates,
+// forward elimination of the right-hand side, back substitution, w = z/s^2),
+// laid out so that the per-column overhead of the elimination (pivot search,
+// reciprocal, bookkeeping) is shared by 64/SEG stencils:
+//   * a segment of SEG consecutive lanes (8, 16, 32 or 64) owns one stencil;
+//     lane l of the segment holds rows l, l+SEG, ..., l+(SL-1)*SEG ("slots")
+//     of the augmented matrix in registers; slots past the last row are empty;
+//   * reductions inside a segment use DPP: for SEG <= 16 an all-reduce made
+//     of row_mirror / row_half_mirror / quad_perm exchanges (every lane gets
+//     the result, no LDS and no scalar round trip); wider segments finish
+//     with row_bcast and readlane;
+//   * the pivot search first compares the slots of a lane exactly (full
+//     |a| bits, then position), then takes the segment maximum of the high
+//     words; a ballot decides whether that maximum is unique, otherwise a
+//     butterfly over the full keys (|a| bits, position) settles ties;
+//   * the winning lane writes its pivot row, its right-hand side and its
+//     position to LDS; one LDS read of each pivot entry feeds the fused
+//     updates of all SL slots of a lane.
+// One block is one wavefront, so LDS ordering needs no barrier instruction.
+
+#include "common.h"
+#include "weights_kernel.h"
+
+namespace rbffd {
+namespace wk {
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, false);
+}
+
+struct OpMax {
+    __device__ static uint32_t f(uint32_t a, uint32_t b) { return a > b ? a : b; }
+};
+struct OpOr {
+    __device__ static uint32_t f(uint32_t a, uint32_t b) { return a | b; }
+};
+
+// All-reduce over each SEG-lane segment; every lane receives the result.
+template <int SEG, class Op>
+__device__ __forceinline__ uint32_t seg_all(uint32_t v, int lane) {
+    static_assert(SEG == 8 || SEG == 16 || SEG == 32 || SEG == 64, "segment width");
+    if constexpr (SEG >= 16) v = Op::f(v, dpp_u32<0x140>(v));  // row_mirror
+    v = Op::f(v, dpp_u32<0x141>(v));                           // row_half_mirror
+    v = Op::f(v, dpp_u32<0x4E>(v));                            // quad_perm [2,3,0,1]
+    v = Op::f(v, dpp_u32<0xB1>(v));                            // quad_perm [1,0,3,2]
+    if constexpr (SEG == 32) {
+        const uint32_t o = (uint32_t)__shfl_xor((int)v, 16, 64);
+        v = Op::f(v, o);
+    } else if constexpr (SEG == 64) {
+        v = Op::f(v, (uint32_t)__shfl_xor((int)v, 16, 64));
+        v = Op::f(v, (uint32_t)__shfl_xor((int)v, 32, 64));
+    }
+    return v;
+}
+
+template <int SEG>
+__device__ __forceinline__ double seg_all_max_d(double v, int lane) {
+    // values are >= 0, so their bit patterns order like the values
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    uint32_t hi = (uint32_t)(b >> 32), lo = (uint32_t)b;
+    const uint32_t mh = seg_all<SEG, OpMax>(hi, lane);
+    lo = (hi == mh) ? lo : 0u;
+    const uint32_t ml = seg_all<SEG, OpMax>(lo, lane);
+    return __longlong_as_double((long long)(((uint64_t)mh << 32) | ml));
+}
+
+template <int SEG>
+__device__ __forceinline__ double seg_all_or_d(double v, int lane) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t hi = seg_all<SEG, OpOr>((uint32_t)(b >> 32), lane);
+    const uint32_t lo = seg_all<SEG, OpOr>((uint32_t)b, lane);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// full (|a| bits, position) key butterfly inside a segment (ties only)
+template <int SEG>
+__device__ __forceinline__ void seg_argmax_full(uint32_t &kh, uint32_t &kl, int &kp) {
+#pragma unroll
+    for (int o = SEG / 2; o > 0; o >>= 1) {
+        const uint32_t oh = (uint32_t)__shfl_xor((int)kh, o, SEG);
+        const uint32_t ol = (uint32_t)__shfl_xor((int)kl, o, SEG);
+        const int op = __shfl_xor(kp, o, SEG);
+        if (key_better(oh, ol, op, kh, kl, kp)) {
+            kh = oh;
+            kl = ol;
+            kp = op;
+        }
+    }
+}
+
+template <int KP, int SEG, int SL, int MM>
+struct MsLds {
+    static constexpr int GPB = kWave / SEG;
+    static constexpr int PSZ = GPB * KP * MM;            // monomial table (assembly)
+    // pivot rows (elimination); entries 16 bytes apart so that stores are
+    // never merged into 128-bit writes that would need contiguous registers
+    static constexpr int RSZ = 2 * GPB * 2 * (KP + 1);
+    static constexpr int USZ = PSZ > RSZ ? PSZ : RSZ;
+};
+
+template <int KP, int SEG, int SL, int NFIX, int MFIX, int OCC>
+__global__ __launch_bounds__(kWave)
+__attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1))) void weights_ms_kernel(
+    const double *__restrict__ x, const double *__restrict__ y, int64_t n_nodes,
+    const int32_t *__restrict__ nbr, int32_t k_stride, const int32_t *__restrict__ rows,
+    const int32_t *__restrict__ n_rows_dev, int64_t n_rows, int32_t n_arg, int32_t m_arg,
+    double *__restrict__ w, int32_t *__restrict__ status, double *__restrict__ sv_lu,
+    double *__restrict__ sv_z, double *__restrict__ sv_s, uint8_t *__restrict__ sv_perm,
+    int32_t sv_kmax) {
+    static_assert(SEG * SL >= KP, "slots must cover the system");
+    constexpr int GPB = kWave / SEG;
+    constexpr int MM = MFIX ? (MFIX + 1) * (MFIX + 2) / 2 : 28;
+    using L = MsLds<KP, SEG, SL, MM>;
+    const int n = NFIX ? NFIX : n_arg;
+    const int m = MFIX ? MFIX : m_arg;
+    const int NM = (m + 1) * (m + 2) / 2;
+    const int K = n + NM;
+
+    __shared__ double s_ux[GPB][KP];
+    __shared__ double s_uy[GPB][KP];
+    __shared__ double s_u[L::USZ];     // monomial table, then pivot rows
+    __shared__ int32_t s_pos[2][GPB];  // position of the pivot row
+    double(*s_P)[MM] = reinterpret_cast<double(*)[MM]>(s_u);  // [GPB*KP][MM]
+    double(*s_row)[GPB][2 * (KP + 1)] = reinterpret_cast<double(*)[GPB][2 * (KP + 1)]>(s_u);
+
+    const int lane = threadIdx.x;
+    const int g = lane / SEG;
+    const int l0 = lane % SEG;
+    if (n_rows_dev) n_rows = *n_rows_dev;
+    if ((int64_t)blockIdx.x * GPB >= n_rows) return;  // whole wave idle
+    const int64_t t = (int64_t)blockIdx.x * GPB + g;
+    const bool valid = t < n_rows;
+    const int64_t i = valid ? (rows ? (int64_t)rows[t] : t) : 0;
+
+    // ---- shift: offsets of the support nodes ------------------------------
+    uint32_t flags = 0;
+    double dx[SL], dy[SL];
+    double d2m = 0.0;
+    const double xi = x[i], yi = y[i];
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+        const int r = l0 + SEG * s;
+        dx[s] = 0.0;
+        dy[s] = 0.0;
+        if (valid && r < n) {
+            const int32_t j = nbr[i * (int64_t)k_stride + r];
+            if (j < 0 || (int64_t)j >= n_nodes) {
+                flags |= F_BADIDX;
+            } else {
+                const double ddx = x[j] - xi, ddy = y[j] - yi;
+                if (!isfinite(ddx) || !isfinite(ddy)) {
+                    flags |= F_NONFIN;
+                } else {
+                    dx[s] = ddx;
+                    dy[s] = ddy;
+                    const double d2 = ddx * ddx + ddy * ddy;
+                    d2m = fmax(d2m, d2);
+                }
+            }
+        }
+    }
+    const double sc = sqrt(seg_all_max_d<SEG>(d2m, lane));
+    if (sc == 0.0) flags |= F_DUP;
+
+    // ---- scale; monomial table --------------------------------------------
+    double ux[SL], uy[SL];
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+        const int r = l0 + SEG * s;
+        ux[s] = 0.0;
+        uy[s] = 0.0;
+        if (r < n) {
+            ux[s] = dx[s] / sc;
+            uy[s] = dy[s] / sc;
+            s_ux[g][r] = ux[s];
+            s_uy[g][r] = uy[s];
+            double px[7], py[7];
+            px[0] = 1.0;
+            py[0] = 1.0;
+#pragma unroll
+            for (int e = 1; e < 7; ++e) {
+                px[e] = px[e - 1] * ux[s];
+                py[e] = py[e - 1] * uy[s];
+            }
+#pragma unroll
+            for (int j = 0; j < MM; ++j)
+                if (j < NM) s_P[g * KP + r][j] = px[mono_a(j)] * py[mono_b(j)];
+        }
+    }
+    __syncthreads();
+
+    // ---- assemble the rows of every slot -----------------------------------
+    double a[SL][KP];
+    double yv[SL];
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+        const int r = l0 + SEG * s;
+        const bool prow = r < n;
+        const bool qrow = r >= n && r < K;
+        const int jr = qrow ? r - n : 0;
+        // slots whose rows all lie past the support rows skip the r^3 block
+        const bool any_p = !NFIX || SEG * s < NFIX;
+#pragma unroll
+        for (int l = 0; l < KP; ++l) {
+            if (l < n) {
+                double phs = 0.0;
+                if (any_p) {
+                    const double ex = ux[s] - s_ux[g][l];
+                    const double ey = uy[s] - s_uy[g][l];
+                    const double rr = ex * ex + ey * ey;
+                    if (prow && l != r && rr == 0.0) flags |= F_DUP;
+                    phs = rr * sqrt(rr);
+                }
+                const double pt = s_P[g * KP + l][jr];
+                a[s][l] = prow ? phs : (qrow ? pt : 0.0);
+            } else if (l < K) {
+                a[s][l] = prow ? s_P[g * KP + (r < KP ? r : 0)][l - n] : 0.0;
+            } else {
+                a[s][l] = (l == r) ? 1.0 : 0.0;
+            }
+            if ((l & 1) == 1) __builtin_amdgcn_sched_barrier(0);
+        }
+        const double r0 = ux[s] * ux[s] + uy[s] * uy[s];
+        const double rb = 9.0 * sqrt(r0);
+        yv[s] = prow ? rb : ((qrow && (jr == 3 || jr == 5)) ? 2.0 : 0.0);
+    }
+    // materialise the flags here: otherwise the duplicate checks sink to the
+    // end of the kernel and keep every squared distance alive through the LU
+    asm volatile("" : "+v"(flags));
+    __syncthreads();  // the monomial table's space becomes the pivot rows
+
+    // ---- LU with partial pivoting, right-looking, rhs carried along --------
+    int pos[SL];
+    bool done[SL];
+    double minv[SL];
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+        pos[s] = l0 + SEG * s;
+        done[s] = pos[s] >= KP;
+        minv[s] = 0.0;
+    }
+    uint32_t luflag = 0;
+    const uint64_t segmask = SEG == 64 ? ~0ull : ((1ull << SEG) - 1ull);
+    const int segbase = g * SEG;
+#pragma unroll
+    for (int c = 0; c < KP; ++c) {
+        const int buf = c & 1;
+        // best slot of this lane: exact key (|a| bits, position)
+        uint64_t bb = 0;
+        int bp = 0x7fffffff, bs = 0;
+        bool ba = false;
+#pragma unroll
+        for (int s = 0; s < SL; ++s) {
+            const uint64_t bits = (uint64_t)__double_as_longlong(a[s][c]) & 0x7fffffffffffffffull;
+            const bool take = !done[s] && (!ba || bits > bb || (bits == bb && pos[s] < bp));
+            bb = take ? bits : bb;
+            bp = take ? pos[s] : bp;
+            bs = take ? s : bs;
+            ba = ba || !done[s];
+        }
+        const uint32_t kh = ba ? (uint32_t)(bb >> 32) + 1u : 0u;
+        const uint32_t mh = seg_all<SEG, OpMax>(kh, lane);
+        uint64_t chunk = (__ballot(ba && kh == mh) >> segbase) & segmask;
+        const bool uniq = (chunk & (chunk - 1ull)) == 0ull;
+        if (__builtin_expect(__ballot(!uniq) != 0ull, 0)) {
+            uint32_t h2 = kh, l2 = ba ? (uint32_t)bb : 0u;
+            int p2 = ba ? bp : 0x7fffffff;
+            seg_argmax_full<SEG>(h2, l2, p2);
+            chunk = (__ballot(ba && bp == p2) >> segbase) & segmask;
+        }
+        const int win = __ffsll((unsigned long long)chunk) - 1;
+        const bool is_win = (l0 == win);
+#pragma unroll
+        for (int s = 0; s < SL; ++s) {
+            if (is_win && bs == s) {
+#pragma unroll
+                for (int q = c; q < KP; ++q) s_row[buf][g][2 * q] = a[s][q];
+                s_row[buf][g][2 * KP] = yv[s];
+                s_pos[buf][g] = pos[s];
+            }
+        }
+        __syncthreads();
+        const double *u = s_row[buf][g];  // entry q at u[2q]
+        const double piv = u[2 * c];
+        const int kp = s_pos[buf][g];
+        const double inv = 1.0 / piv;
+        if (luflag == 0) {
+            if (!isfinite(piv)) luflag = L_NONFIN;
+            else if (piv == 0.0) luflag = L_SING;
+        }
+        double lm[SL];
+#pragma unroll
+        for (int s = 0; s < SL; ++s) {
+            const bool upd = !done[s] && !(is_win && bs == s);
+            lm[s] = upd ? a[s][c] * inv : 0.0;
+            a[s][c] = upd ? lm[s] : a[s][c];
+        }
+        // Columns c+1 .. KP (KP: the right-hand side) in chunks of CH.  The
+        // reads of chunk k go through an offset (always 0) that an empty asm
+        // ties to an update result of chunk k-2: the reads cannot be hoisted
+        // further ahead, which bounds the registers they occupy while still
+        // overlapping them with two chunks of updates.
+        {
+            constexpr int CH = 4;
+            int off = 0;
+            double dep0 = 0.0, dep1 = 0.0;
+#pragma unroll
+            for (int q0 = c + 1; q0 <= KP; q0 += CH) {
+                asm volatile("" : "+v"(off) : "v"(dep0));
+                double uq[CH];
+#pragma unroll
+                for (int j = 0; j < CH; ++j)
+                    if (q0 + j <= KP) uq[j] = u[2 * (q0 + j) + off];
+#pragma unroll
+                for (int j = 0; j < CH; ++j) {
+                    const int q = q0 + j;
+                    if (q < KP) {
+#pragma unroll
+                        for (int s = 0; s < SL; ++s) a[s][q] = fma(-lm[s], uq[j], a[s][q]);
+                    } else if (q == KP) {
+#pragma unroll
+                        for (int s = 0; s < SL; ++s) yv[s] = fma(-lm[s], uq[j], yv[s]);
+                    }
+                }
+                dep0 = dep1;
+                dep1 = (q0 < KP) ? a[0][q0] : yv[0];
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < SL; ++s) {
+            const bool isp = is_win && bs == s;
+            pos[s] = isp ? c : ((!done[s] && pos[s] == c) ? kp : pos[s]);
+            minv[s] = isp ? inv : minv[s];
+            done[s] = done[s] || isp;
+            // opaque to the optimiser: keeps it from folding each step's
+            // comparisons back through the select chain of all earlier steps
+            // (no instruction is emitted)
+            int dn = done[s] ? 1 : 0;
+            asm volatile("" : "+v"(pos[s]), "+v"(dn));
+            done[s] = dn != 0;
+        }
+        asm volatile("" : "+v"(luflag));
+    }
+
+    // ---- back substitution ------------------------------------------------
+    double zm[SL];
+#pragma unroll
+    for (int s = 0; s < SL; ++s) zm[s] = 0.0;
+#pragma unroll
+    for (int c = KP - 1; c >= 0; --c) {
+        double zl = 0.0;
+#pragma unroll
+        for (int s = 0; s < SL; ++s) {
+            const double zc = yv[s] * minv[s];
+            zm[s] = (pos[s] == c) ? zc : zm[s];
+            zl = (pos[s] == c) ? zc : zl;
+        }
+        const double z = seg_all_or_d<SEG>(zl, lane);  // exactly one slot holds position c
+#pragma unroll
+        for (int s = 0; s < SL; ++s) yv[s] = (pos[s] < c) ? fma(-a[s][c], z, yv[s]) : yv[s];
+    }
+
+    // ---- status and outputs -----------------------------------------------
+#pragma unroll
+    for (int s = 0; s < SL; ++s)
+        if (pos[s] < K && !isfinite(zm[s])) flags |= F_ZBAD;
+    flags = seg_all<SEG, OpOr>(flags, lane);
+    int st = RBFFD_OK;
+    if (flags & F_BADIDX) st = RBFFD_BAD_INDEX;
+    else if (flags & F_NONFIN) st = RBFFD_NONFINITE;
+    else if (flags & F_DUP) st = RBFFD_DUPLICATE;
+    else if (luflag == L_NONFIN) st = RBFFD_NONFINITE;
+    else if (luflag == L_SING) st = RBFFD_SINGULAR;
+    else if (flags & F_ZBAD) st = RBFFD_NONFINITE;
+
+    if (!valid) return;
+    double *wi = w + i * (int64_t)k_stride;
+    const double s2 = sc * sc;
+#pragma unroll
+    for (int s = 0; s < SL; ++s)
+        if (pos[s] < n) wi[pos[s]] = (st == RBFFD_OK) ? zm[s] / s2 : __builtin_nan("");
+    for (int q = n + l0; q < k_stride; q += SEG) wi[q] = 0.0;
+    if (l0 == 0 && status) status[i] = st;
+    if (sv_lu) {
+        const int64_t kk = (int64_t)sv_kmax * sv_kmax;
+#pragma unroll
+        for (int s = 0; s < SL; ++s) {
+            if (pos[s] < K) {
+                double *dst = sv_lu + i * kk + (int64_t)pos[s] * K;
+#pragma unroll
+                for (int q = 0; q < KP; ++q)
+                    if (q < K) dst[q] = a[s][q];
+                sv_z[i * (int64_t)sv_kmax + pos[s]] = zm[s];
+                sv_perm[i * (int64_t)sv_kmax + pos[s]] = (uint8_t)(l0 + SEG * s);
+                if (pos[s] == 0) sv_s[i] = sc;
+            }
+        }
+    }
+}
+
+template <int KP, int SEG, int SL, int NFIX, int MFIX, int OCC = 0>
+inline int launch_ms(const double *x, const double *y, int64_t n_nodes, const int32_t *nbr,
+                     int32_t k_stride, const int32_t *rows, const int32_t *n_rows_dev,
+                     int64_t n_rows, int n, int m, double *w, int32_t *status,
+                     const SaveView &sv, hipStream_t stream) {
+    constexpr int GPB = kWave / SEG;
+    if (n_rows <= 0) return RBFFD_SUCCESS;
+    const int64_t blocks = ceil_div(n_rows, GPB);
+    if (blocks > 0x7fffffff) return RBFFD_ERR_UNSUPPORTED;
+    hipLaunchKernelGGL((weights_ms_kernel<KP, SEG, SL, NFIX, MFIX, OCC>), dim3((unsigned)blocks),
+                       dim3(kWave), 0, stream, x, y, n_nodes, nbr, k_stride, rows, n_rows_dev,
+                       n_rows, n, m, w, status, sv.lu, sv.z, sv.s, sv.perm, sv.kmax);
+    return last_launch_rc();
+}
+
+}  // namespace wk
+}  // namespace rbffd

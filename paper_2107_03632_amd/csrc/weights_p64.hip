@@ -1,8 +1,18 @@
-// FP64 weights kernel instance: KP = 64 rows padded, 64 lanes per stencil.
-#include "weights_kernel.h"
+// FP64 weights kernel instance: systems padded to 64 rows, 32 lanes x 2 rows per stencil.
+#include "weights_ms.h"
+
+#ifndef RBFFD_SEG_P64
+#define RBFFD_SEG_P64 32
+#endif
+#ifndef RBFFD_SL_P64
+#define RBFFD_SL_P64 2
+#endif
+#ifndef RBFFD_OCC_P64
+#define RBFFD_OCC_P64 0
+#endif
 
 namespace rbffd {
 int weights_fp64_p64(const double *x, const double *y, int64_t n_nodes, const int32_t *nbr, int32_t k_stride, const int32_t *rows, const int32_t *n_rows_dev, int64_t n_rows, int n, int m, double *w, int32_t *status, const wk::SaveView &sv, hipStream_t stream) {
-    return wk::launch_fp64<64, 64, 0, 0>(x, y, n_nodes, nbr, k_stride, rows, n_rows_dev, n_rows, n, m, w, status, sv, stream);
+    return wk::launch_ms<64, RBFFD_SEG_P64, RBFFD_SL_P64, 0, 0, RBFFD_OCC_P64>(x, y, n_nodes, nbr, k_stride, rows, n_rows_dev, n_rows, n, m, w, status, sv, stream);
 }
 }  // namespace rbffd
