@@ -66,6 +66,8 @@ def _load():
             lib.oracle_lu_solve.restype = None
             lib.oracle_weights.argtypes = [I64, P, P, P, I32, P, I32, I32, P,
                                            P, I64, P, P]
+            lib.oracle_weights_mixed.argtypes = [I64, P, P, P, I32, P, I32, I32, P,
+                                                 P, I64, P, P, P]
             lib.oracle_adjoint.argtypes = [I64, P, P, P, I32, P, I32, I32, P,
                                            P, P, P]
             lib.oracle_csr.argtypes = [I64, P, I32, P, I32, P, P, P, P, P, P]
@@ -158,6 +160,28 @@ def weights(x, y, nbr, m: int | None = None, n: int | None = None, order=None,
     if rc != 0:
         raise ValueError(f"oracle_weights: error {rc}")
     return w, st
+
+
+def weights_mixed(x, y, nbr, m: int | None = None, n: int | None = None, order=None,
+                  n_for_m=(12, 30, 56), rows=None, k_stride: int | None = None):
+    """Mixed-precision weights: FP32 LU of the FP64-assembled system + FP64
+    refinement, FP64 fallback.  Returns (w, status, corrections)."""
+    lib = _load()
+    x, y, nbr = _f64(x), _f64(y), _i32(nbr)
+    N = x.shape[0]
+    ks = nbr.shape[1] if k_stride is None else k_stride
+    o = None if order is None else np.ascontiguousarray(order, dtype=np.int8)
+    r = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    nr = N if r is None else r.shape[0]
+    w = np.empty((nr, ks))
+    st = np.empty(nr, dtype=np.int32)
+    it = np.empty(nr, dtype=np.int32)
+    rc = lib.oracle_weights_mixed(N, _p(x), _p(y), _p(nbr), ks, _p(o),
+                                  -1 if m is None else m, -1 if n is None else n,
+                                  _p(_i32(n_for_m)), _p(r), nr, _p(w), _p(st), _p(it))
+    if rc != 0:
+        raise ValueError(f"oracle_weights_mixed: error {rc}")
+    return w, st, it
 
 
 def adjoint(x, y, nbr, G, m: int | None = None, n: int | None = None, order=None,

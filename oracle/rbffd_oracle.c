@@ -28,6 +28,15 @@
  *   oracle_weights    w of eq. (1): w_k = z_k / s^2 for the n support nodes.
  *   oracle_adjoint    dL/dx, dL/dy for all nodes from dL/dw (reverse mode of the
  *                     map above, with the scale s held fixed).
+ *   oracle_weights_mixed  the same weights from an FP32 factorisation of the
+ *                     FP64-assembled system, refined in FP64: residual
+ *                     rhs - M z in FP64 (fused, columns ascending), FP32
+ *                     correction solve, z += dz; converged when
+ *                     |dz|_inf <= 1e-12 |z|_inf; an FP32 zero or non-finite
+ *                     pivot, a correction above half the previous one (the
+ *                     first is compared with the initial solve), a non-finite
+ *                     value or 10 corrections without convergence send the
+ *                     stencil to the FP64 path (status OR_FELL_BACK).
  *   oracle_csr        the discrete operator of eq. (1) as a CSR matrix, with the
  *                     Dirichlet rows of section IV replaced by identity rows.
  *   oracle_spmv       y = W u - f, a sequential row sum in CSR order.
@@ -411,6 +420,201 @@ int oracle_weights(int64_t n_nodes, const double *x, const double *y,
             status[t] = st;
     }
     free(M); free(z); free(dinv); free(perm);
+    return rc;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Mixed precision: FP32 factorisation, FP64 iterative refinement          */
+/* ---------------------------------------------------------------------- */
+
+/* oracle_lu in single precision (fabsf, 1.0f / pivot, fmaf updates). */
+static int lu32(int K, float *M, int32_t *perm, float *dinv)
+{
+    for (int c = 0; c < K; ++c) {
+        int p = c;
+        float best = fabsf(M[c * K + c]);
+        for (int r = c + 1; r < K; ++r) {
+            float v = fabsf(M[r * K + c]);
+            if (v > best) {
+                best = v;
+                p = r;
+            }
+        }
+        if (!isfinite(best))
+            return OR_NONFINITE;
+        if (best == 0.0f)
+            return OR_SINGULAR;
+        perm[c] = p;
+        if (p != c)
+            for (int q = 0; q < K; ++q) {
+                float t = M[c * K + q];
+                M[c * K + q] = M[p * K + q];
+                M[p * K + q] = t;
+            }
+        float inv = 1.0f / M[c * K + c];
+        dinv[c] = inv;
+        for (int r = c + 1; r < K; ++r)
+            M[r * K + c] = M[r * K + c] * inv;
+        for (int r = c + 1; r < K; ++r) {
+            float l = M[r * K + c];
+            for (int q = c + 1; q < K; ++q)
+                M[r * K + q] = fmaf(-l, M[c * K + q], M[r * K + q]);
+        }
+    }
+    return OR_OK;
+}
+
+static void lu32_solve(int K, const float *LU, const int32_t *perm, const float *dinv, float *b)
+{
+    for (int c = 0; c < K; ++c) {
+        int p = perm[c];
+        float t = b[c];
+        b[c] = b[p];
+        b[p] = t;
+    }
+    for (int c = 0; c < K; ++c)
+        for (int r = c + 1; r < K; ++r)
+            b[r] = fmaf(-LU[r * K + c], b[c], b[r]);
+    for (int c = K - 1; c >= 0; --c) {
+        b[c] = b[c] * dinv[c];
+        for (int r = 0; r < c; ++r)
+            b[r] = fmaf(-LU[r * K + c], b[c], b[r]);
+    }
+}
+
+#define MIXED_MAX_CORRECTIONS 10
+#define MIXED_TOL 1e-12
+
+/* One stencil, mixed precision.  Returns the status; *iters = number of
+ * corrections applied (0 when the stencil fell back or failed early). */
+static int stencil_solve_mixed(int64_t n_nodes, const double *x, const double *y,
+                               int64_t i, const int32_t *idx, int n, int m,
+                               double *M, double *z, float *M32, float *d32,
+                               int32_t *perm, float *dinv32, double *dinv, double *rhs,
+                               double *s, int *iters)
+{
+    const int K = n + n_monomials(m);
+    *iters = 0;
+    int st = oracle_assemble(n_nodes, x, y, i, idx, n, m, M, rhs, s);
+    if (st != OR_OK)
+        return st;
+    for (int e = 0; e < K * K; ++e)
+        M32[e] = (float)M[e];
+    int ok = lu32(K, M32, perm, dinv32) == OR_OK;
+    if (ok) {
+        for (int q = 0; q < K; ++q)
+            d32[q] = (float)rhs[q];
+        lu32_solve(K, M32, perm, dinv32, d32);
+        double prev = 0.0;
+        for (int q = 0; q < K; ++q) {
+            z[q] = (double)d32[q];
+            if (fabs(z[q]) > prev)
+                prev = fabs(z[q]);
+        }
+        int converged = 0;
+        for (int it = 1; it <= MIXED_MAX_CORRECTIONS && ok; ++it) {
+            for (int r = 0; r < K; ++r) {
+                double acc = rhs[r];
+                for (int c = 0; c < K; ++c)
+                    acc = fma(-M[r * K + c], z[c], acc);
+                d32[r] = (float)acc;
+            }
+            lu32_solve(K, M32, perm, dinv32, d32);
+            double dn = 0.0, zn = 0.0;
+            for (int q = 0; q < K; ++q) {
+                z[q] = z[q] + (double)d32[q];
+                double a = fabs((double)d32[q]);
+                if (!(a <= dn))
+                    dn = a;
+                if (!(fabs(z[q]) <= zn))
+                    zn = fabs(z[q]);
+            }
+            *iters = it;
+            if (!isfinite(dn) || !isfinite(zn))
+                ok = 0;
+            else if (dn <= MIXED_TOL * zn)
+                converged = 1;
+            else if (dn > 0.5 * prev)
+                ok = 0;
+            prev = dn;
+            if (converged)
+                break;
+        }
+        if (!converged)
+            ok = 0;
+    }
+    if (ok)
+        return OR_OK;
+    *iters = 0;
+    /* FP64 path from scratch */
+    st = stencil_solve(n_nodes, x, y, i, idx, n, m, M, z, perm, dinv, s);
+    return st == OR_OK ? OR_FELL_BACK : st;
+}
+
+/* As oracle_weights, mixed precision.  iters (may be NULL) receives the
+ * number of FP64 refinement corrections per listed node. */
+int oracle_weights_mixed(int64_t n_nodes, const double *x, const double *y,
+                         const int32_t *nbr, int32_t k_stride,
+                         const int8_t *order, int32_t m_uniform, int32_t n_uniform,
+                         const int32_t *n_for_m, const int64_t *rows, int64_t n_rows,
+                         double *w, int32_t *status, int32_t *iters)
+{
+    int kmax = 0;
+    if (order) {
+        for (int q = 0; q < 3; ++q) {
+            int K = n_for_m[q] + n_monomials(2 * q + 2);
+            if (n_for_m[q] < n_monomials(2 * q + 2) || n_for_m[q] > k_stride)
+                return OR_EARG;
+            if (K > kmax)
+                kmax = K;
+        }
+    } else {
+        if (m_uniform < 0 || m_uniform > 12 || n_uniform < n_monomials(m_uniform) ||
+            n_uniform > k_stride)
+            return OR_EARG;
+        kmax = n_uniform + n_monomials(m_uniform);
+    }
+    size_t kk = (size_t)kmax * (size_t)kmax;
+    double *M = (double *)malloc(sizeof(double) * kk);
+    float *M32 = (float *)malloc(sizeof(float) * kk);
+    double *z = (double *)malloc(sizeof(double) * (size_t)kmax * 3);
+    double *dinv = z + kmax, *rhs = z + 2 * kmax;
+    float *d32 = (float *)malloc(sizeof(float) * (size_t)kmax * 2);
+    float *dinv32 = d32 + kmax;
+    int32_t *perm = (int32_t *)malloc(sizeof(int32_t) * (size_t)kmax);
+    if (!M || !M32 || !z || !d32 || !perm) {
+        free(M); free(M32); free(z); free(d32); free(perm);
+        return OR_ENOMEM;
+    }
+    int rc = 0;
+    for (int64_t t = 0; t < n_rows; ++t) {
+        int64_t i = rows ? rows[t] : t;
+        int m, n, it = 0;
+        if (i < 0 || i >= n_nodes ||
+            support_of(order, m_uniform, n_uniform, n_for_m, i, &m, &n) != 0) {
+            rc = OR_EARG;
+            break;
+        }
+        double s = 0.0;
+        int st = stencil_solve_mixed(n_nodes, x, y, i, nbr + i * (int64_t)k_stride, n, m,
+                                     M, z, M32, d32, perm, dinv32, dinv, rhs, &s, &it);
+        double *wr = w + t * (int64_t)k_stride;
+        if (st == OR_OK || st == OR_FELL_BACK) {
+            double s2 = s * s;
+            for (int k = 0; k < n; ++k)
+                wr[k] = z[k] / s2;
+        } else {
+            for (int k = 0; k < n; ++k)
+                wr[k] = NAN;
+        }
+        for (int k = n; k < k_stride; ++k)
+            wr[k] = 0.0;
+        if (status)
+            status[t] = st;
+        if (iters)
+            iters[t] = it;
+    }
+    free(M); free(M32); free(z); free(d32); free(perm);
     return rc;
 }
 
