@@ -521,16 +521,19 @@ static int stencil_solve_mixed(int64_t n_nodes, const double *x, const double *y
             }
             lu32_solve(K, M32, perm, dinv32, d32);
             double dn = 0.0, zn = 0.0;
+            int bad = 0;
             for (int q = 0; q < K; ++q) {
                 z[q] = z[q] + (double)d32[q];
                 double a = fabs((double)d32[q]);
-                if (!(a <= dn))
+                if (!isfinite(a) || !isfinite(z[q]))
+                    bad = 1;
+                if (a > dn)
                     dn = a;
-                if (!(fabs(z[q]) <= zn))
+                if (fabs(z[q]) > zn)
                     zn = fabs(z[q]);
             }
             *iters = it;
-            if (!isfinite(dn) || !isfinite(zn))
+            if (bad)
                 ok = 0;
             else if (dn <= MIXED_TOL * zn)
                 converged = 1;
