@@ -231,7 +231,10 @@ def timed(torch, stream, fn, reps=3):
 
 def extras_per_order(torch, rb, nodes, dev, stream):
     """Weights-kernel throughput on the 1M-node cell-centred square at m = 2,
-    4, 6 (uniform) and for the per-node {2,4,6} mixed batch."""
+    4, 6 (uniform), FP64 and mixed precision (FP32 factorisation + FP64
+    refinement), and for the per-node {2,4,6} mixed-order batch.  The mixed
+    weights' error is taken against the FP64 weights of the same call
+    sequence (the FP64 path reproduces the oracle bit for bit)."""
     ns = nodes.workload("square_1m_mixed")
     X = torch.as_tensor(ns.x, device=dev)
     Y = torch.as_tensor(ns.y, device=dev)
@@ -239,18 +242,37 @@ def extras_per_order(torch, rb, nodes, dev, stream):
     N = ns.n_nodes
     res = {"n_nodes": N}
     for m, n in ((2, 12), (4, 30), (6, 56)):
-        ms = timed(torch, stream, lambda: rb.rbffd_weights(X, Y, nbr, m=m, n=n))
-        res[f"m{m}_n{n}"] = {"stencils_per_s": N / (ms * 1e-3), "ms": ms,
-                             "frac_fp64_peak": weights_flops(m, n) * N / (ms * 1e-3) / 1e12
-                             / FP64_PEAK_TFLOPS}
+        nb = nbr[:, :n].contiguous()
+        ms = timed(torch, stream, lambda: rb.rbffd_weights(X, Y, nb, m=m, n=n))
+        w64, st64, _ = rb.rbffd_weights(X, Y, nb, m=m, n=n)
+        it = torch.zeros(N, dtype=torch.int32, device=dev)
+        ms_mx = timed(torch, stream,
+                      lambda: rb.rbffd_weights(X, Y, nb, m=m, n=n, precision=rb.MIXED))
+        wmx, stmx, _ = rb.rbffd_weights(X, Y, nb, m=m, n=n, precision=rb.MIXED, refine_steps=it)
+        ok = (stmx == 0)
+        err = ((wmx - w64).abs().amax(1) / w64.abs().amax(1)).max().item()
+        fl = weights_flops(m, n) * N / 1e12
+        res[f"m{m}_n{n}"] = {
+            "fp64": {"stencils_per_s": N / (ms * 1e-3), "ms": ms,
+                     "frac_fp64_peak": fl / (ms * 1e-3) / FP64_PEAK_TFLOPS,
+                     "failed": int((st64 != 0).sum().item())},
+            "mixed": {"stencils_per_s": N / (ms_mx * 1e-3), "ms": ms_mx,
+                      "speedup_vs_fp64": ms / ms_mx,
+                      "mean_corrections": it[ok].double().mean().item() if ok.any() else None,
+                      "fell_back": int((stmx == rb.FELL_BACK_FP64).sum().item()),
+                      "failed": int(((stmx != 0) & (stmx != rb.FELL_BACK_FP64)).sum().item()),
+                      "max_rel_err_vs_fp64": err},
+        }
     O = torch.as_tensor(ns.order, device=dev)
     ms = timed(torch, stream, lambda: rb.rbffd_weights(X, Y, nbr, order=O))
+    ms_mx = timed(torch, stream, lambda: rb.rbffd_weights(X, Y, nbr, order=O, precision=rb.MIXED))
     counts = {mm: int((ns.order == mm).sum()) for mm in (2, 4, 6)}
     fl = sum(counts[mm] * weights_flops(mm, nn) for mm, nn in ((2, 12), (4, 30), (6, 56)))
-    res["mixed_order"] = {"stencils_per_s": N / (ms * 1e-3), "ms": ms,
-                          "frac_fp64_peak": fl / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS}
-    ms_knn = timed(torch, stream, lambda: rb.rbffd_knn(X, Y, 56))
-    res["knn_k56_ms"] = ms_knn
+    res["mixed_order"] = {"fp64": {"stencils_per_s": N / (ms * 1e-3), "ms": ms,
+                                   "frac_fp64_peak": fl / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS},
+                          "mixed": {"stencils_per_s": N / (ms_mx * 1e-3), "ms": ms_mx,
+                                    "speedup_vs_fp64": ms / ms_mx}}
+    res["knn_k56_ms"] = timed(torch, stream, lambda: rb.rbffd_knn(X, Y, 56))
     return res
 
 

@@ -21,7 +21,8 @@
  *   - Numerical trouble is reported per stencil in a status array (values
  *     RBFFD_OK ... RBFFD_DUPLICATE below) and the failed stencil's weights
  *     are NaN, so it cannot be used silently.
- *   - Calls on different streams are independent (no global mutable state).
+ *   - Calls on different streams are independent; the only process-wide
+ *     state is the batch tuning table (rbffd_batch_tuning_set).
  */
 #ifndef RBFFD_H
 #define RBFFD_H
@@ -98,8 +99,18 @@ int rbffd_knn(const double *x, const double *y, int64_t n_nodes, int32_t k,
  *        order != NULL -> order[i] (int8, device, [n_nodes]) in {2,4,6}
  *        selects m per node and n = n_for_order[m/2 - 1] (host, [3]); nodes
  *        are bucketed by system size inside the call.
- * precision: RBFFD_FP64 or RBFFD_MIXED.
+ * precision: RBFFD_FP64, or RBFFD_MIXED (standard supports (m, n) = (2, 12),
+ *   (4, 30), (6, 56) only; RBFFD_ERR_UNSUPPORTED otherwise): the same M and
+ *   rhs, factorised in FP32 (same pivoting rule, fmaf updates), then refined:
+ *   r = rhs - M z in FP64 (fused, columns ascending), d = FP32 solve of
+ *   (float) r, z += d, converged when max|d| <= 1e-12 max|z|.  An FP32 zero
+ *   or non-finite pivot, a correction above half the previous one (the first
+ *   is compared with max|z| of the initial solve), a non-finite value or 10
+ *   corrections without convergence redo the stencil in FP64; its status is
+ *   then RBFFD_FELL_BACK_FP64 (weights valid).
  * w: [n_nodes][k_stride] FP64 out.  status: [n_nodes] int32 out (may be NULL).
+ * refine_steps: [n_nodes] int32 out (may be NULL; mixed only): corrections
+ * applied, 0 for stencils that fell back or failed.
  * save (may be NULL): factors for rbffd_weights_backward; see
  * rbffd_weights_save_size.  Only with RBFFD_FP64.
  * ======================================================================== */
@@ -113,9 +124,27 @@ int rbffd_weights(const double *x, const double *y, int64_t n_nodes,
                   const int8_t *order, int32_t m, int32_t n,
                   const int32_t *n_for_order /* host [3] or NULL */,
                   int32_t precision,
-                  double *w, int32_t *status,
+                  double *w, int32_t *status, int32_t *refine_steps,
                   void *save, size_t save_bytes,
                   void *workspace, size_t workspace_bytes, void *stream);
+
+/* ==========================================================================
+ * Tuning of the mixed-order batch (rbffd_weights with a per-node order and
+ * the standard supports n = 12/30/56, FP64), which runs as one persistent
+ * launch: blocks_per_cu blocks of 128 threads per compute unit pull tiles
+ * from a work queue, largest systems first; groups_per_tile[q] sets the tile
+ * size of order m = 2q+2 (in stencils for m = 6, in 2-stencil / 8-stencil
+ * wavefront groups for m = 4 / m = 2).  The values only change speed, never
+ * results.  This table is the library's only process-wide state; set it
+ * before launching (e.g. from the autotuner's saved choice).  NULL restores
+ * the defaults {2, {1, 1, 1}}.
+ * ======================================================================== */
+typedef struct rbffd_batch_tuning {
+    int32_t blocks_per_cu;       /* 1..64 */
+    int32_t groups_per_tile[3];  /* 1..64 each, for m = 2, 4, 6 */
+} rbffd_batch_tuning;
+int rbffd_batch_tuning_set(const rbffd_batch_tuning *tuning /* host, or NULL */);
+int rbffd_batch_tuning_get(rbffd_batch_tuning *tuning /* host */);
 
 /* ==========================================================================
  * Adjoint of rbffd_weights (FP64): given G = dL/dw ([n_nodes][k_stride]),

@@ -1,0 +1,84 @@
+"""Autotuner for the persistent mixed-order weights launch.
+
+Times every candidate (blocks per compute unit, tile size per order) of the
+one-launch mixed-order batch on a given node set and keeps the fastest.  The
+tuning only changes speed, never results.  The choice is saved to
+batch_tuning.json next to the library, which the binding applies whenever
+the library is loaded.
+
+    python -m paper_2107_03632_amd.autotune          # 1M-node {2,4,6} batch
+"""
+
+from __future__ import annotations
+
+import itertools
+import json
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import binding as rb
+from . import nodes
+
+CANDIDATES = {
+    "blocks_per_cu": [1, 2, 3, 4],
+    "gpt2": [1, 2, 4],
+    "gpt4": [1, 2],
+    "gpt6": [1, 2],
+}
+
+
+def _time_ms(fn, reps: int) -> float:
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts))
+
+
+def tune_batch(x, y, nbr, order, reps: int = 3, candidates=CANDIDATES) -> dict:
+    """Time each candidate setting; apply and return the fastest."""
+    table = []
+    keys = list(candidates)
+    for vals in itertools.product(*(candidates[k] for k in keys)):
+        c = dict(zip(keys, vals))
+        rb.batch_tuning_set(c["blocks_per_cu"], [c["gpt2"], c["gpt4"], c["gpt6"]])
+        ms = _time_ms(lambda: rb.rbffd_weights(x, y, nbr, order=order), reps)
+        table.append({**c, "ms": ms})
+    best = min(table, key=lambda r: r["ms"])
+    choice = {"blocks_per_cu": best["blocks_per_cu"],
+              "groups_per_tile": [best["gpt2"], best["gpt4"], best["gpt6"]]}
+    rb.batch_tuning_set(choice["blocks_per_cu"], choice["groups_per_tile"])
+    return {"choice": choice, "ms": best["ms"], "table": table}
+
+
+def main(argv=None) -> int:
+    dev = torch.device("cuda:0")
+    ns = nodes.workload("square_1m_mixed")
+    X = torch.as_tensor(ns.x, device=dev)
+    Y = torch.as_tensor(ns.y, device=dev)
+    O = torch.as_tensor(ns.order, device=dev)
+    nbr = rb.rbffd_knn(X, Y, 56)
+    t0 = time.time()
+    res = tune_batch(X, Y, nbr, O)
+    res["workload"] = "1M-node square, per-node order uniform on {2,4,6}, n = 12/30/56"
+    res["device"] = torch.cuda.get_device_name(dev)
+    res["seconds"] = time.time() - t0
+    out = argv[0] if argv else rb.TUNING_PATH
+    with open(out, "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps({"choice": res["choice"], "ms": res["ms"]}))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main(sys.argv[1:]))

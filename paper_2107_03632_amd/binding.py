@@ -46,8 +46,8 @@ def _load():
             "rbffd_knn": ([P, P, I64, I32, P, P, SZ, P], ctypes.c_int),
             "rbffd_weights_workspace_size": ([I64, I32, I32, PSZ], ctypes.c_int),
             "rbffd_weights_save_size": ([I64, I32, PSZ], ctypes.c_int),
-            "rbffd_weights": ([P, P, I64, P, I32, P, I32, I32, P, I32, P, P, P, SZ, P, SZ, P],
-                              ctypes.c_int),
+            "rbffd_weights": ([P, P, I64, P, I32, P, I32, I32, P, I32, P, P, P, P, SZ, P, SZ,
+                               P], ctypes.c_int),
             "rbffd_weights_backward_workspace_size": ([I64, I32, PSZ], ctypes.c_int),
             "rbffd_weights_backward": ([P, P, I64, P, I32, P, I32, I32, P, P, P, SZ, P, P, P,
                                         P, SZ, P], ctypes.c_int),
@@ -55,13 +55,47 @@ def _load():
             "rbffd_assemble_csr": ([I64, P, I32, P, I32, P, P, P, P, P, P, I64, P, SZ, P],
                                    ctypes.c_int),
             "rbffd_spmv": ([I64, P, P, P, P, P, P, P], ctypes.c_int),
+            "rbffd_batch_tuning_set": ([P], ctypes.c_int),
+            "rbffd_batch_tuning_get": ([P], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
             fn.argtypes = args
             fn.restype = res
         _lib = lib
-        return lib
+    _apply_saved_tuning()
+    return lib
+
+
+class BatchTuning(ctypes.Structure):
+    _fields_ = [("blocks_per_cu", ctypes.c_int32), ("groups_per_tile", ctypes.c_int32 * 3)]
+
+
+TUNING_PATH = os.path.join(_HERE, "batch_tuning.json")
+
+
+def batch_tuning_set(blocks_per_cu: int, groups_per_tile) -> None:
+    """Set the persistent mixed-order launch's grid and tile sizes."""
+    t = BatchTuning(int(blocks_per_cu), (ctypes.c_int32 * 3)(*[int(v) for v in groups_per_tile]))
+    _check(_load().rbffd_batch_tuning_set(ctypes.byref(t)), "rbffd_batch_tuning_set")
+
+
+def batch_tuning_get() -> dict:
+    t = BatchTuning()
+    _check(_load().rbffd_batch_tuning_get(ctypes.byref(t)), "rbffd_batch_tuning_get")
+    return {"blocks_per_cu": t.blocks_per_cu, "groups_per_tile": list(t.groups_per_tile)}
+
+
+def _apply_saved_tuning():
+    """Apply the autotuner's saved choice (batch_tuning.json), if any."""
+    if not os.path.exists(TUNING_PATH):
+        return
+    import json
+    with open(TUNING_PATH) as f:
+        cfg = json.load(f)["choice"]
+    t = BatchTuning(int(cfg["blocks_per_cu"]),
+                    (ctypes.c_int32 * 3)(*[int(v) for v in cfg["groups_per_tile"]]))
+    _check(_lib.rbffd_batch_tuning_set(ctypes.byref(t)), "rbffd_batch_tuning_set")
 
 
 def library_path() -> str:
@@ -139,10 +173,13 @@ def _order_args(order, m, n, n_for_order):
 
 
 def rbffd_weights(x, y, nbr, m=None, n=None, order=None, n_for_order=DEFAULT_N_FOR_ORDER,
-                  precision: int = FP64, save: bool = False, out=None, status=None):
+                  precision: int = FP64, save: bool = False, out=None, status=None,
+                  refine_steps=None):
     """Laplacian stencil weights w [N, k_stride] (FP64) and status [N] int32.
 
     Returns (w, status, save_buffer or None).  nbr is [N, k_stride] int32.
+    precision=MIXED: FP32 factorisation + FP64 refinement; refine_steps (an
+    int32 [N] tensor, optional) receives the corrections per stencil.
     """
     lib = _load()
     x = _dev(x, torch.float64, "x")
@@ -157,9 +194,10 @@ def rbffd_weights(x, y, nbr, m=None, n=None, order=None, n_for_order=DEFAULT_N_F
         sv = _workspace(_size(lib.rbffd_weights_save_size, N, kmax), x.device)
     ws = _workspace(_size(lib.rbffd_weights_workspace_size, N, int(o is not None), precision),
                     x.device)
+    rs = None if refine_steps is None else _dev(refine_steps, torch.int32, "refine_steps")
     _check(lib.rbffd_weights(_p(x), _p(y), N, _p(nbr), ks, _p(o), m_, n_, nfo, precision,
-                             _p(w), _p(st), _p(sv), 0 if sv is None else sv.numel(), _p(ws),
-                             ws.numel(), _stream(x.device)), "rbffd_weights")
+                             _p(w), _p(st), _p(rs), _p(sv), 0 if sv is None else sv.numel(),
+                             _p(ws), ws.numel(), _stream(x.device)), "rbffd_weights")
     return w, st, sv
 
 

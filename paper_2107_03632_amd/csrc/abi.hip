@@ -9,11 +9,55 @@ int weights_fp64_class(const double *x, const double *y, int64_t n_nodes, const 
                        int32_t k_stride, const int32_t *rows, const int32_t *n_rows_dev,
                        int64_t n_rows, int n, int m, double *w, int32_t *status,
                        double *sv_lu, double *sv_z, double *sv_s, uint8_t *sv_perm,
-                       int32_t sv_kmax, hipStream_t stream);
+                       int32_t sv_kmax, int32_t ok_code, hipStream_t stream);
+
+int weights_fp64_batch(const double *x, const double *y, int64_t n_nodes, const int32_t *nbr,
+                       int32_t k_stride, const int32_t *lists, const int32_t *counts,
+                       int32_t *queue, double *w, int32_t *status, double *sv_lu, double *sv_z,
+                       double *sv_s, uint8_t *sv_perm, int32_t sv_kmax, hipStream_t stream);
+
+#define RBFFD_MX_DECL(name)                                                                    \
+    size_t weights_mx_##name##_scratch(int64_t n_rows);                                         \
+    int weights_mx_##name(const double *x, const double *y, int64_t n_nodes, const int32_t *nbr, \
+                          int32_t k_stride, const int32_t *rows, const int32_t *n_rows_dev,      \
+                          int64_t n_rows, double *w, int32_t *status, int32_t *iters,            \
+                          double *scratch, int32_t *fb_count, int32_t *fb_list,                  \
+                          hipStream_t stream);
+RBFFD_MX_DECL(k18)
+RBFFD_MX_DECL(k45)
+RBFFD_MX_DECL(k84)
+#undef RBFFD_MX_DECL
 
 namespace {
 
 constexpr int kThreads = 256;
+
+// mixed-precision instances exist for the standard supports only
+int mixed_class(int m, int n) {
+    if (m == 2 && n == 12) return 0;
+    if (m == 4 && n == 30) return 1;
+    if (m == 6 && n == 56) return 2;
+    return -1;
+}
+
+size_t mixed_scratch(int cls, int64_t n_rows) {
+    return cls == 0 ? weights_mx_k18_scratch(n_rows)
+                    : cls == 1 ? weights_mx_k45_scratch(n_rows) : weights_mx_k84_scratch(n_rows);
+}
+
+int mixed_run(int cls, const double *x, const double *y, int64_t n_nodes, const int32_t *nbr,
+              int32_t k_stride, const int32_t *rows, const int32_t *n_rows_dev, int64_t n_rows,
+              double *w, int32_t *status, int32_t *iters, double *scratch, int32_t *fb_count,
+              int32_t *fb_list, hipStream_t s) {
+    if (cls == 0)
+        return weights_mx_k18(x, y, n_nodes, nbr, k_stride, rows, n_rows_dev, n_rows, w, status,
+                              iters, scratch, fb_count, fb_list, s);
+    if (cls == 1)
+        return weights_mx_k45(x, y, n_nodes, nbr, k_stride, rows, n_rows_dev, n_rows, w, status,
+                              iters, scratch, fb_count, fb_list, s);
+    return weights_mx_k84(x, y, n_nodes, nbr, k_stride, rows, n_rows_dev, n_rows, w, status,
+                          iters, scratch, fb_count, fb_list, s);
+}
 
 // Bucket the nodes by order: node i goes to list b = m/2 - 1.  Nodes with an
 // order outside {2,4,6} get NaN weights and status RBFFD_BAD_ORDER here.
@@ -63,15 +107,29 @@ SaveLayout carve_save(void *base, int64_t n_nodes, int32_t kmax) {
 
 struct OrderWs {
     int32_t *counts;
+    int32_t *queue;  // work queue of the persistent batch launch
     int32_t *lists;
+    int32_t *fb_count;  // mixed precision: stencils sent to the FP64 path
+    int32_t *fb_list;
+    double *scratch;
     size_t bytes;
 };
 
-OrderWs carve_order(void *base, int64_t n_nodes) {
+// order lists when has_order; the mixed-precision scratch and fallback list
+// when mixed (scratch sized for the largest standard class)
+OrderWs carve_order(void *base, int64_t n_nodes, bool has_order, bool mixed) {
     Carver c(base);
-    OrderWs o;
+    OrderWs o = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0};
     o.counts = c.take<int32_t>(64);
-    o.lists = c.take<int32_t>((size_t)3 * n_nodes);
+    o.queue = c.take<int32_t>(64);
+    if (has_order) o.lists = c.take<int32_t>((size_t)3 * n_nodes);
+    if (mixed) {
+        o.fb_count = c.take<int32_t>(64);
+        o.fb_list = c.take<int32_t>((size_t)n_nodes);
+        size_t sb = 0;
+        for (int q = 0; q < 3; ++q) sb = mixed_scratch(q, n_nodes) > sb ? mixed_scratch(q, n_nodes) : sb;
+        o.scratch = c.take<double>(sb / sizeof(double) + 1);
+    }
     o.bytes = c.bytes();
     return o;
 }
@@ -107,7 +165,7 @@ extern "C" int rbffd_weights_workspace_size(int64_t n_nodes, int32_t has_order, 
                                             size_t *bytes) {
     if (!bytes || n_nodes < 1 || (precision != RBFFD_FP64 && precision != RBFFD_MIXED))
         return RBFFD_ERR_ARG;
-    *bytes = has_order ? carve_order(nullptr, n_nodes).bytes : 256;
+    *bytes = carve_order(nullptr, n_nodes, has_order != 0, precision == RBFFD_MIXED).bytes;
     return RBFFD_SUCCESS;
 }
 
@@ -120,12 +178,12 @@ extern "C" int rbffd_weights_save_size(int64_t n_nodes, int32_t kmax, size_t *by
 extern "C" int rbffd_weights(const double *x, const double *y, int64_t n_nodes,
                              const int32_t *nbr, int32_t k_stride, const int8_t *order, int32_t m,
                              int32_t n, const int32_t *n_for_order, int32_t precision, double *w,
-                             int32_t *status, void *save, size_t save_bytes, void *workspace,
-                             size_t workspace_bytes, void *stream) {
+                             int32_t *status, int32_t *refine_steps, void *save, size_t save_bytes,
+                             void *workspace, size_t workspace_bytes, void *stream) {
     if (!x || !y || !nbr || !w || n_nodes < 1 || n_nodes >= INT32_MAX || k_stride < 1)
         return RBFFD_ERR_ARG;
     if (precision != RBFFD_FP64 && precision != RBFFD_MIXED) return RBFFD_ERR_ARG;
-    if (precision == RBFFD_MIXED) return RBFFD_ERR_UNSUPPORTED;
+    const bool mixed = precision == RBFFD_MIXED;
     int ms[3], ns[3], nclass;
     if (order) {
         if (!n_for_order) return RBFFD_ERR_ARG;
@@ -147,6 +205,11 @@ extern "C" int rbffd_weights(const double *x, const double *y, int64_t n_nodes,
         if (K > 96) return RBFFD_ERR_UNSUPPORTED;
         kmax = K > kmax ? K : kmax;
     }
+    if (mixed) {
+        if (save) return RBFFD_ERR_ARG;  // the adjoint uses FP64 factors
+        for (int q = 0; q < nclass; ++q)
+            if (mixed_class(ms[q], ns[q]) < 0) return RBFFD_ERR_UNSUPPORTED;
+    }
     SaveLayout sv = {nullptr, nullptr, nullptr, nullptr, 0};
     if (save) {
         sv = carve_save(nullptr, n_nodes, kmax);
@@ -154,23 +217,44 @@ extern "C" int rbffd_weights(const double *x, const double *y, int64_t n_nodes,
         sv = carve_save(save, n_nodes, kmax);
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (!order)
+    if (!order && !mixed)
         return weights_fp64_class(x, y, n_nodes, nbr, k_stride, nullptr, nullptr, n_nodes, n, m, w,
-                                  status, sv.lu, sv.z, sv.s, sv.perm, kmax, s);
-    OrderWs ow = carve_order(nullptr, n_nodes);
+                                  status, sv.lu, sv.z, sv.s, sv.perm, kmax, RBFFD_OK, s);
+    OrderWs ow = carve_order(nullptr, n_nodes, order != nullptr, mixed);
     if (!workspace || workspace_bytes < ow.bytes) return RBFFD_ERR_WORKSPACE;
-    ow = carve_order(workspace, n_nodes);
-    int rc = fill_i32(ow.counts, 0, 64, s);
-    if (rc) return rc;
-    hipLaunchKernelGGL(bucket_by_order, dim3((unsigned)ceil_div(n_nodes, kThreads)),
-                       dim3(kThreads), 0, s, order, n_nodes, k_stride, ow.counts, ow.lists, w,
-                       status);
-    if ((rc = last_launch_rc())) return rc;
-    // largest systems first so the long-running blocks start early
-    for (int q = 2; q >= 0; --q) {
-        rc = weights_fp64_class(x, y, n_nodes, nbr, k_stride, ow.lists + (int64_t)q * n_nodes,
-                                ow.counts + q, n_nodes, ns[q], ms[q], w, status, sv.lu, sv.z,
-                                sv.s, sv.perm, kmax, s);
+    ow = carve_order(workspace, n_nodes, order != nullptr, mixed);
+    int rc;
+    if (order) {
+        if ((rc = fill_i32(ow.counts, 0, 64, s))) return rc;
+        hipLaunchKernelGGL(bucket_by_order, dim3((unsigned)ceil_div(n_nodes, kThreads)),
+                           dim3(kThreads), 0, s, order, n_nodes, k_stride, ow.counts, ow.lists, w,
+                           status);
+        if ((rc = last_launch_rc())) return rc;
+    }
+    // the standard mixed-order batch: one persistent launch over all classes
+    if (order && !mixed && mixed_class(ms[0], ns[0]) == 0 && mixed_class(ms[1], ns[1]) == 1 &&
+        mixed_class(ms[2], ns[2]) == 2)
+        return weights_fp64_batch(x, y, n_nodes, nbr, k_stride, ow.lists, ow.counts, ow.queue, w,
+                                  status, sv.lu, sv.z, sv.s, sv.perm, kmax, s);
+    // otherwise one launch per class, largest systems first
+    for (int q = nclass - 1; q >= 0; --q) {
+        const int32_t *rows = order ? ow.lists + (int64_t)q * n_nodes : nullptr;
+        const int32_t *cnt = order ? ow.counts + q : nullptr;
+        if (!mixed) {
+            rc = weights_fp64_class(x, y, n_nodes, nbr, k_stride, rows, cnt, n_nodes, ns[q], ms[q],
+                                    w, status, sv.lu, sv.z, sv.s, sv.perm, kmax, RBFFD_OK, s);
+            if (rc) return rc;
+            continue;
+        }
+        // mixed: FP32 factorisation + FP64 refinement, then the FP64 kernel on
+        // the stencils it could not refine
+        if ((rc = fill_i32(ow.fb_count, 0, 1, s))) return rc;
+        rc = mixed_run(mixed_class(ms[q], ns[q]), x, y, n_nodes, nbr, k_stride, rows, cnt, n_nodes,
+                       w, status, refine_steps, ow.scratch, ow.fb_count, ow.fb_list, s);
+        if (rc) return rc;
+        rc = weights_fp64_class(x, y, n_nodes, nbr, k_stride, ow.fb_list, ow.fb_count, n_nodes,
+                                ns[q], ms[q], w, status, nullptr, nullptr, nullptr, nullptr, 0,
+                                RBFFD_FELL_BACK_FP64, s);
         if (rc) return rc;
     }
     return RBFFD_SUCCESS;

@@ -31,7 +31,7 @@ inline int last_launch_rc() { return hip_rc(hipGetLastError()); }
 
 inline int n_monomials(int m) { return (m + 1) * (m + 2) / 2; }
 
-inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // Exclusive prefix sum over n int32 or int64 values (device, stream-ordered).
 // out may alias in.  Workspace from scan_workspace_elems().

@@ -10,7 +10,7 @@ namespace rbffd {
     int weights_fp64_##name(const double *x, const double *y, int64_t n_nodes,                 \
                             const int32_t *nbr, int32_t k_stride, const int32_t *rows,         \
                             const int32_t *n_rows_dev, int64_t n_rows, int n, int m, double *w, \
-                            int32_t *status, const wk::SaveView &sv, hipStream_t stream);
+                            int32_t *status, const wk::SaveView &sv, int32_t ok_code, hipStream_t stream);
 RBFFD_WEIGHTS_INSTANCE(k18)
 RBFFD_WEIGHTS_INSTANCE(k45)
 RBFFD_WEIGHTS_INSTANCE(k84)
@@ -22,12 +22,12 @@ RBFFD_WEIGHTS_INSTANCE(p96)
 // Launch the FP64 weights kernel for one (m, n) class over n_rows stencils
 // (rows == nullptr: stencil t is node t; otherwise node rows[t]; when
 // n_rows_dev is given the row count is read on the device, n_rows being an
-// upper bound used for the grid).
+// upper bound used for the grid).  Successful stencils get status ok_code.
 int weights_fp64_class(const double *x, const double *y, int64_t n_nodes, const int32_t *nbr,
                        int32_t k_stride, const int32_t *rows, const int32_t *n_rows_dev,
                        int64_t n_rows, int n, int m, double *w, int32_t *status,
                        double *sv_lu, double *sv_z, double *sv_s, uint8_t *sv_perm,
-                       int32_t sv_kmax, hipStream_t stream) {
+                       int32_t sv_kmax, int32_t ok_code, hipStream_t stream) {
     wk::SaveView sv;
     sv.lu = sv_lu;
     sv.z = sv_z;
@@ -36,7 +36,7 @@ int weights_fp64_class(const double *x, const double *y, int64_t n_nodes, const 
     sv.kmax = sv_kmax;
     const int K = n + n_monomials(m);
 #define GO(name) \
-    return weights_fp64_##name(x, y, n_nodes, nbr, k_stride, rows, n_rows_dev, n_rows, n, m, w, status, sv, stream)
+    return weights_fp64_##name(x, y, n_nodes, nbr, k_stride, rows, n_rows_dev, n_rows, n, m, w, status, sv, ok_code, stream)
     if (m == 2 && n == 12) GO(k18);
     if (m == 4 && n == 30) GO(k45);
     if (m == 6 && n == 56) GO(k84);

@@ -1,0 +1,118 @@
+// Mixed-order batch of FP64 stencils in one persistent launch.
+//
+// The nodes have been bucketed by order (m = 2, 4, 6 -> system sizes 18, 45,
+// 84).  A fixed grid of 128-thread blocks pulls tiles from an atomic work
+// queue, largest systems first so the long tiles start early and the short
+// ones fill the tail:
+//   * an order-6 tile is gpt[2] stencils, each spread over both wavefronts
+//     of the block (one matrix row per lane, 84 rows);
+//   * an order-4 tile gives each wavefront gpt[1] groups of 2 stencils
+//     (32 lanes x 2 rows per stencil);
+//   * an order-2 tile gives each wavefront gpt[0] groups of 8 stencils
+//     (8 lanes x 3 rows per stencil).
+// Tile sizes and the grid size (blocks per compute unit) are runtime
+// parameters chosen by the autotuner (rbffd_batch_tuning_set).
+// The arithmetic is that of the per-order kernels, so the weights are the
+// same bits as the single-order path.
+
+#include <atomic>
+
+#include "weights_ms.h"
+
+namespace rbffd {
+namespace {
+
+constexpr int kPB = 128;
+constexpr int kG18 = kWave / 8;   // stencils per wavefront group, K = 18
+constexpr int kG45 = kWave / 32;  // K = 45
+
+__global__ __launch_bounds__(kPB) void weights_batch_kernel(
+    const double *__restrict__ x, const double *__restrict__ y, int64_t n_nodes,
+    const int32_t *__restrict__ nbr, int32_t k_stride, const int32_t *__restrict__ lists,
+    const int32_t *__restrict__ counts, int32_t *__restrict__ queue, int32_t gpt2, int32_t gpt4,
+    int32_t gpt6, double *__restrict__ w, int32_t *__restrict__ status,
+    double *__restrict__ sv_lu, double *__restrict__ sv_z, double *__restrict__ sv_s,
+    uint8_t *__restrict__ sv_perm, int32_t sv_kmax) {
+    __shared__ int32_t s_tile;
+    const int64_t c2 = counts[0], c4 = counts[1], c6 = counts[2];
+    const int64_t T6 = ceil_div(c6, gpt6);
+    const int64_t T4 = ceil_div(c4, 2 * (int64_t)gpt4 * kG45);
+    const int64_t T2 = ceil_div(c2, 2 * (int64_t)gpt2 * kG18);
+    const int64_t total = T6 + T4 + T2;
+    const int wave = threadIdx.x >> 6;
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = atomicAdd(queue, 1);
+        __syncthreads();
+        const int64_t tile = s_tile;
+        __syncthreads();
+        if (tile >= total) break;
+        if (tile < T6) {
+            for (int q = 0; q < gpt6; ++q)
+                wk::weights_fp64_body<84, 128, 56, 6>(
+                    x, y, n_nodes, nbr, k_stride, lists + 2 * n_nodes, c6, 56, 6, w, status, sv_lu,
+                    sv_z, sv_s, sv_perm, sv_kmax, RBFFD_OK, tile * gpt6 + q);
+        } else if (tile < T6 + T4) {
+            const int64_t base = (tile - T6) * 2 * gpt4;
+            for (int q = 0; q < gpt4; ++q)
+                wk::weights_ms_body<45, 32, 2, 30, 4, 2>(
+                    x, y, n_nodes, nbr, k_stride, lists + n_nodes, c4, 30, 4, w, status, sv_lu,
+                    sv_z, sv_s, sv_perm, sv_kmax, RBFFD_OK, base + 2 * q + wave, wave);
+        } else {
+            const int64_t base = (tile - T6 - T4) * 2 * gpt2;
+            for (int q = 0; q < gpt2; ++q)
+                wk::weights_ms_body<18, 8, 3, 12, 2, 2>(
+                    x, y, n_nodes, nbr, k_stride, lists, c2, 12, 2, w, status, sv_lu, sv_z, sv_s,
+                    sv_perm, sv_kmax, RBFFD_OK, base + 2 * q + wave, wave);
+        }
+    }
+}
+
+// the process-wide tuning table (the library's only mutable state)
+std::atomic<int32_t> g_blocks_per_cu{2};
+std::atomic<int32_t> g_gpt[3] = {{1}, {1}, {1}};
+
+}  // namespace
+
+// Persistent launch over the three standard classes (m, n) = (2,12), (4,30),
+// (6,56); lists holds 3 x n_nodes node ids, counts the 3 list lengths and
+// queue one int32 that this call zeroes.
+int weights_fp64_batch(const double *x, const double *y, int64_t n_nodes, const int32_t *nbr,
+                       int32_t k_stride, const int32_t *lists, const int32_t *counts,
+                       int32_t *queue, double *w, int32_t *status, double *sv_lu, double *sv_z,
+                       double *sv_s, uint8_t *sv_perm, int32_t sv_kmax, hipStream_t stream) {
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_rc(e);
+    int rc = fill_i32(queue, 0, 1, stream);
+    if (rc) return rc;
+    const int64_t blocks = (int64_t)g_blocks_per_cu.load() * cus;
+    hipLaunchKernelGGL(weights_batch_kernel, dim3((unsigned)blocks), dim3(kPB), 0, stream, x, y,
+                       n_nodes, nbr, k_stride, lists, counts, queue, g_gpt[0].load(),
+                       g_gpt[1].load(), g_gpt[2].load(), w, status, sv_lu, sv_z, sv_s, sv_perm,
+                       sv_kmax);
+    return last_launch_rc();
+}
+
+}  // namespace rbffd
+
+extern "C" int rbffd_batch_tuning_set(const rbffd_batch_tuning *t) {
+    if (!t) {
+        rbffd::g_blocks_per_cu = 2;
+        for (auto &v : rbffd::g_gpt) v = 1;
+        return RBFFD_SUCCESS;
+    }
+    if (t->blocks_per_cu < 1 || t->blocks_per_cu > 64) return RBFFD_ERR_ARG;
+    for (int q = 0; q < 3; ++q)
+        if (t->groups_per_tile[q] < 1 || t->groups_per_tile[q] > 64) return RBFFD_ERR_ARG;
+    rbffd::g_blocks_per_cu = t->blocks_per_cu;
+    for (int q = 0; q < 3; ++q) rbffd::g_gpt[q] = t->groups_per_tile[q];
+    return RBFFD_SUCCESS;
+}
+
+extern "C" int rbffd_batch_tuning_get(rbffd_batch_tuning *t) {
+    if (!t) return RBFFD_ERR_ARG;
+    t->blocks_per_cu = rbffd::g_blocks_per_cu.load();
+    for (int q = 0; q < 3; ++q) t->groups_per_tile[q] = rbffd::g_gpt[q].load();
+    return RBFFD_SUCCESS;
+}

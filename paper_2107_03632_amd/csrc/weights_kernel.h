@@ -188,17 +188,16 @@ struct Shape {
     static_assert(kW == 32 || kW == 64, "segments of 32 or 64 lanes");
 };
 
-// OCC: minimum waves per SIMD the register allocation must allow (0: the
-// compiler's choice).
-template <int KP, int G, int NFIX, int MFIX, int OCC>
-__global__ __launch_bounds__(block_threads(G))
-__attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1))) void weights_fp64_kernel(
+// One block (G/64 wavefronts, or one wavefront holding 64/G groups) computes
+// the stencils of block-group `grp` of the row list.
+template <int KP, int G, int NFIX, int MFIX>
+__device__ __forceinline__ void weights_fp64_body(
     const double *__restrict__ x, const double *__restrict__ y, int64_t n_nodes,
     const int32_t *__restrict__ nbr, int32_t k_stride, const int32_t *__restrict__ rows,
-    const int32_t *__restrict__ n_rows_dev, int64_t n_rows, int32_t n_arg, int32_t m_arg,
-    double *__restrict__ w, int32_t *__restrict__ status, double *__restrict__ sv_lu,
-    double *__restrict__ sv_z, double *__restrict__ sv_s, uint8_t *__restrict__ sv_perm,
-    int32_t sv_kmax) {
+    int64_t n_rows, int32_t n_arg, int32_t m_arg, double *__restrict__ w,
+    int32_t *__restrict__ status, double *__restrict__ sv_lu, double *__restrict__ sv_z,
+    double *__restrict__ sv_s, uint8_t *__restrict__ sv_perm, int32_t sv_kmax, int32_t ok_code,
+    int64_t grp) {
     using S = Shape<KP, G>;
     constexpr int GPB = S::kGroups;
     constexpr int W = S::kW;
@@ -224,9 +223,8 @@ __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1))) void weights_fp64_kernel
     const int r = tid % G;         // row owned by this lane
     const int wv = (tid % G) / W;  // wave of the group this lane sits in
     const bool wave_leader = (tid % W) == 0;
-    if (n_rows_dev) n_rows = *n_rows_dev;
-    if ((int64_t)blockIdx.x * GPB >= n_rows) return;  // whole block idle: no barrier reached
-    const int64_t t = (int64_t)blockIdx.x * GPB + g;
+    if (grp * GPB >= n_rows) return;  // whole block idle: no barrier reached
+    const int64_t t = grp * GPB + g;
     const bool valid = t < n_rows;
     const int64_t i = valid ? (rows ? (int64_t)rows[t] : t) : 0;
 
@@ -444,9 +442,10 @@ __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1))) void weights_fp64_kernel
 
     if (!valid) return;
     double *wi = w + i * (int64_t)k_stride;
-    if (pos < n) wi[pos] = (st == RBFFD_OK) ? zmine / (s * s) : __builtin_nan("");
+    const bool good = st == RBFFD_OK;
+    if (pos < n) wi[pos] = good ? zmine / (s * s) : __builtin_nan("");
     for (int q = n + r; q < k_stride; q += G) wi[q] = 0.0;
-    if (r == 0 && status) status[i] = st;
+    if (r == 0 && status) status[i] = good ? ok_code : st;
     if (sv_lu && r < KP && pos < K) {
         const int64_t kk = (int64_t)sv_kmax * sv_kmax;
         double *dst = sv_lu + i * kk + (int64_t)pos * K;
@@ -459,6 +458,23 @@ __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1))) void weights_fp64_kernel
     }
 }
 
+// OCC: minimum waves per SIMD the register allocation must allow (0: the
+// compiler's choice).
+template <int KP, int G, int NFIX, int MFIX, int OCC>
+__global__ __launch_bounds__(block_threads(G))
+__attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1))) void weights_fp64_kernel(
+    const double *__restrict__ x, const double *__restrict__ y, int64_t n_nodes,
+    const int32_t *__restrict__ nbr, int32_t k_stride, const int32_t *__restrict__ rows,
+    const int32_t *__restrict__ n_rows_dev, int64_t n_rows, int32_t n_arg, int32_t m_arg,
+    double *__restrict__ w, int32_t *__restrict__ status, double *__restrict__ sv_lu,
+    double *__restrict__ sv_z, double *__restrict__ sv_s, uint8_t *__restrict__ sv_perm,
+    int32_t sv_kmax, int32_t ok_code) {
+    if (n_rows_dev) n_rows = *n_rows_dev;
+    weights_fp64_body<KP, G, NFIX, MFIX>(x, y, n_nodes, nbr, k_stride, rows, n_rows, n_arg, m_arg,
+                                         w, status, sv_lu, sv_z, sv_s, sv_perm, sv_kmax, ok_code,
+                                         (int64_t)blockIdx.x);
+}
+
 struct SaveView {
     double *lu = nullptr, *z = nullptr, *s = nullptr;
     uint8_t *perm = nullptr;
@@ -469,7 +485,7 @@ template <int KP, int G, int NFIX, int MFIX, int OCC = 0>
 inline int launch_fp64(const double *x, const double *y, int64_t n_nodes, const int32_t *nbr,
                        int32_t k_stride, const int32_t *rows, const int32_t *n_rows_dev,
                        int64_t n_rows, int n, int m, double *w, int32_t *status,
-                       const SaveView &sv, hipStream_t stream) {
+                       const SaveView &sv, int32_t ok_code, hipStream_t stream) {
     using S = Shape<KP, G>;
     if (n_rows <= 0) return RBFFD_SUCCESS;
     const int64_t blocks = ceil_div(n_rows, S::kGroups);
@@ -477,7 +493,7 @@ inline int launch_fp64(const double *x, const double *y, int64_t n_nodes, const 
     hipLaunchKernelGGL((weights_fp64_kernel<KP, G, NFIX, MFIX, OCC>), dim3((unsigned)blocks),
                        dim3(S::kBlock), 0, stream, x, y, n_nodes, nbr, k_stride, rows,
                        n_rows_dev, n_rows, n, m, w, status, sv.lu, sv.z, sv.s, sv.perm,
-                       sv.kmax);
+                       sv.kmax, ok_code);
     return last_launch_rc();
 }
 

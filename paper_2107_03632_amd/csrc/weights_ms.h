@@ -45,9 +45,9 @@ struct OpOr {
 // All-reduce over each SEG-lane segment; every lane receives the result.
 template <int SEG, class Op>
 __device__ __forceinline__ uint32_t seg_all(uint32_t v, int lane) {
-    static_assert(SEG == 8 || SEG == 16 || SEG == 32 || SEG == 64, "segment width");
+    static_assert(SEG == 4 || SEG == 8 || SEG == 16 || SEG == 32 || SEG == 64, "segment width");
     if constexpr (SEG >= 16) v = Op::f(v, dpp_u32<0x140>(v));  // row_mirror
-    v = Op::f(v, dpp_u32<0x141>(v));                           // row_half_mirror
+    if constexpr (SEG >= 8) v = Op::f(v, dpp_u32<0x141>(v));   // row_half_mirror
     v = Op::f(v, dpp_u32<0x4E>(v));                            // quad_perm [2,3,0,1]
     v = Op::f(v, dpp_u32<0xB1>(v));                            // quad_perm [1,0,3,2]
     if constexpr (SEG == 32) {
@@ -105,15 +105,25 @@ struct MsLds {
     static constexpr int USZ = PSZ > RSZ ? PSZ : RSZ;
 };
 
-template <int KP, int SEG, int SL, int NFIX, int MFIX, int OCC>
-__global__ __launch_bounds__(kWave)
-__attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1))) void weights_ms_kernel(
+// LDS ordering inside one wavefront: this wave's earlier LDS writes are
+// complete and visible to its later reads (no barrier with other waves).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// One wavefront computes the stencils of group `grp` (stencils
+// grp*GPB .. grp*GPB+GPB-1 of the row list).  WPB wavefronts of a block run
+// independent groups; `wave` selects this wavefront's LDS.
+template <int KP, int SEG, int SL, int NFIX, int MFIX, int WPB>
+__device__ __forceinline__ void weights_ms_body(
     const double *__restrict__ x, const double *__restrict__ y, int64_t n_nodes,
     const int32_t *__restrict__ nbr, int32_t k_stride, const int32_t *__restrict__ rows,
-    const int32_t *__restrict__ n_rows_dev, int64_t n_rows, int32_t n_arg, int32_t m_arg,
-    double *__restrict__ w, int32_t *__restrict__ status, double *__restrict__ sv_lu,
-    double *__restrict__ sv_z, double *__restrict__ sv_s, uint8_t *__restrict__ sv_perm,
-    int32_t sv_kmax) {
+    int64_t n_rows, int32_t n_arg, int32_t m_arg, double *__restrict__ w,
+    int32_t *__restrict__ status, double *__restrict__ sv_lu, double *__restrict__ sv_z,
+    double *__restrict__ sv_s, uint8_t *__restrict__ sv_perm, int32_t sv_kmax, int32_t ok_code,
+    int64_t grp, int wave) {
     static_assert(SEG * SL >= KP, "slots must cover the system");
     constexpr int GPB = kWave / SEG;
     constexpr int MM = MFIX ? (MFIX + 1) * (MFIX + 2) / 2 : 28;
@@ -123,19 +133,22 @@ __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1))) void weights_ms_kernel(
     const int NM = (m + 1) * (m + 2) / 2;
     const int K = n + NM;
 
-    __shared__ double s_ux[GPB][KP];
-    __shared__ double s_uy[GPB][KP];
-    __shared__ double s_u[L::USZ];     // monomial table, then pivot rows
-    __shared__ int32_t s_pos[2][GPB];  // position of the pivot row
+    __shared__ double s_ux_b[WPB][GPB][KP];
+    __shared__ double s_uy_b[WPB][GPB][KP];
+    __shared__ double s_u_b[WPB][L::USZ];     // monomial table, then pivot rows
+    __shared__ int32_t s_pos_b[WPB][2][GPB];  // position of the pivot row
+    double(*s_ux)[KP] = s_ux_b[wave];
+    double(*s_uy)[KP] = s_uy_b[wave];
+    double *s_u = s_u_b[wave];
+    int32_t(*s_pos)[GPB] = s_pos_b[wave];
     double(*s_P)[MM] = reinterpret_cast<double(*)[MM]>(s_u);  // [GPB*KP][MM]
     double(*s_row)[GPB][2 * (KP + 1)] = reinterpret_cast<double(*)[GPB][2 * (KP + 1)]>(s_u);
 
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & (kWave - 1);
     const int g = lane / SEG;
     const int l0 = lane % SEG;
-    if (n_rows_dev) n_rows = *n_rows_dev;
-    if ((int64_t)blockIdx.x * GPB >= n_rows) return;  // whole wave idle
-    const int64_t t = (int64_t)blockIdx.x * GPB + g;
+    if (grp * GPB >= n_rows) return;  // whole wave idle
+    const int64_t t = grp * GPB + g;
     const bool valid = t < n_rows;
     const int64_t i = valid ? (rows ? (int64_t)rows[t] : t) : 0;
 
@@ -194,7 +207,7 @@ __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1))) void weights_ms_kernel(
                 if (j < NM) s_P[g * KP + r][j] = px[mono_a(j)] * py[mono_b(j)];
         }
     }
-    __syncthreads();
+    wave_sync();
 
     // ---- assemble the rows of every slot -----------------------------------
     double a[SL][KP];
@@ -234,7 +247,7 @@ __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1))) void weights_ms_kernel(
     // materialise the flags here: otherwise the duplicate checks sink to the
     // end of the kernel and keep every squared distance alive through the LU
     asm volatile("" : "+v"(flags));
-    __syncthreads();  // the monomial table's space becomes the pivot rows
+    wave_sync();  // the monomial table's space becomes the pivot rows
 
     // ---- LU with partial pivoting, right-looking, rhs carried along --------
     int pos[SL];
@@ -286,7 +299,7 @@ __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1))) void weights_ms_kernel(
                 s_pos[buf][g] = pos[s];
             }
         }
-        __syncthreads();
+        wave_sync();
         const double *u = s_row[buf][g];  // entry q at u[2q]
         const double piv = u[2 * c];
         const int kp = s_pos[buf][g];
@@ -383,11 +396,12 @@ __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1))) void weights_ms_kernel(
     if (!valid) return;
     double *wi = w + i * (int64_t)k_stride;
     const double s2 = sc * sc;
+    const bool good = st == RBFFD_OK;
 #pragma unroll
     for (int s = 0; s < SL; ++s)
-        if (pos[s] < n) wi[pos[s]] = (st == RBFFD_OK) ? zm[s] / s2 : __builtin_nan("");
+        if (pos[s] < n) wi[pos[s]] = good ? zm[s] / s2 : __builtin_nan("");
     for (int q = n + l0; q < k_stride; q += SEG) wi[q] = 0.0;
-    if (l0 == 0 && status) status[i] = st;
+    if (l0 == 0 && status) status[i] = good ? ok_code : st;
     if (sv_lu) {
         const int64_t kk = (int64_t)sv_kmax * sv_kmax;
 #pragma unroll
@@ -405,18 +419,33 @@ __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1))) void weights_ms_kernel(
     }
 }
 
+template <int KP, int SEG, int SL, int NFIX, int MFIX, int OCC>
+__global__ __launch_bounds__(kWave)
+__attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1))) void weights_ms_kernel(
+    const double *__restrict__ x, const double *__restrict__ y, int64_t n_nodes,
+    const int32_t *__restrict__ nbr, int32_t k_stride, const int32_t *__restrict__ rows,
+    const int32_t *__restrict__ n_rows_dev, int64_t n_rows, int32_t n_arg, int32_t m_arg,
+    double *__restrict__ w, int32_t *__restrict__ status, double *__restrict__ sv_lu,
+    double *__restrict__ sv_z, double *__restrict__ sv_s, uint8_t *__restrict__ sv_perm,
+    int32_t sv_kmax, int32_t ok_code) {
+    if (n_rows_dev) n_rows = *n_rows_dev;
+    weights_ms_body<KP, SEG, SL, NFIX, MFIX, 1>(x, y, n_nodes, nbr, k_stride, rows, n_rows, n_arg,
+                                                m_arg, w, status, sv_lu, sv_z, sv_s, sv_perm,
+                                                sv_kmax, ok_code, (int64_t)blockIdx.x, 0);
+}
+
 template <int KP, int SEG, int SL, int NFIX, int MFIX, int OCC = 0>
 inline int launch_ms(const double *x, const double *y, int64_t n_nodes, const int32_t *nbr,
                      int32_t k_stride, const int32_t *rows, const int32_t *n_rows_dev,
                      int64_t n_rows, int n, int m, double *w, int32_t *status,
-                     const SaveView &sv, hipStream_t stream) {
+                     const SaveView &sv, int32_t ok_code, hipStream_t stream) {
     constexpr int GPB = kWave / SEG;
     if (n_rows <= 0) return RBFFD_SUCCESS;
     const int64_t blocks = ceil_div(n_rows, GPB);
     if (blocks > 0x7fffffff) return RBFFD_ERR_UNSUPPORTED;
     hipLaunchKernelGGL((weights_ms_kernel<KP, SEG, SL, NFIX, MFIX, OCC>), dim3((unsigned)blocks),
                        dim3(kWave), 0, stream, x, y, n_nodes, nbr, k_stride, rows, n_rows_dev,
-                       n_rows, n, m, w, status, sv.lu, sv.z, sv.s, sv.perm, sv.kmax);
+                       n_rows, n, m, w, status, sv.lu, sv.z, sv.s, sv.perm, sv.kmax, ok_code);
     return last_launch_rc();
 }
 

@@ -12,7 +12,7 @@
 #endif
 
 namespace rbffd {
-int weights_fp64_p64(const double *x, const double *y, int64_t n_nodes, const int32_t *nbr, int32_t k_stride, const int32_t *rows, const int32_t *n_rows_dev, int64_t n_rows, int n, int m, double *w, int32_t *status, const wk::SaveView &sv, hipStream_t stream) {
-    return wk::launch_ms<64, RBFFD_SEG_P64, RBFFD_SL_P64, 0, 0, RBFFD_OCC_P64>(x, y, n_nodes, nbr, k_stride, rows, n_rows_dev, n_rows, n, m, w, status, sv, stream);
+int weights_fp64_p64(const double *x, const double *y, int64_t n_nodes, const int32_t *nbr, int32_t k_stride, const int32_t *rows, const int32_t *n_rows_dev, int64_t n_rows, int n, int m, double *w, int32_t *status, const wk::SaveView &sv, int32_t ok_code, hipStream_t stream) {
+    return wk::launch_ms<64, RBFFD_SEG_P64, RBFFD_SL_P64, 0, 0, RBFFD_OCC_P64>(x, y, n_nodes, nbr, k_stride, rows, n_rows_dev, n_rows, n, m, w, status, sv, ok_code, stream);
 }
 }  // namespace rbffd

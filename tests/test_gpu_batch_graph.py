@@ -1,0 +1,101 @@
+"""Mixed-order batch: the persistent one-launch path, its tuning knobs, and
+the whole pipeline (kNN -> weights -> CSR -> W u - f) captured in a graph.
+
+Every tuning setting must give the same bits (tuning changes speed only);
+graph replays, interleaved with eager work, must reproduce the eager outputs
+bit for bit.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2107_03632_amd import binding as rb
+from paper_2107_03632_amd import nodes
+
+pytestmark = pytest.mark.gpu
+NFM = {2: 12, 4: 30, 6: 56}
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible GPU")
+    rb.library_path()
+
+
+def test_batch_tuning_changes_nothing_but_speed():
+    ns = nodes.cell_centred_square(80, seed=3, order_seed=33)
+    nbr = oracle.knn(ns.x, ns.y, 56)
+    X, Y, NB, O = dev(ns.x), dev(ns.y), dev(nbr), dev(ns.order)
+    saved = rb.batch_tuning_get()
+    outs = []
+    try:
+        for bpc, gpt in [(1, [1, 1, 1]), (2, [4, 2, 2]), (4, [2, 1, 2]), (3, [1, 2, 1])]:
+            rb.batch_tuning_set(bpc, gpt)
+            assert rb.batch_tuning_get() == {"blocks_per_cu": bpc, "groups_per_tile": gpt}
+            w, st, _ = rb.rbffd_weights(X, Y, NB, order=O)
+            torch.cuda.synchronize()
+            outs.append((w.cpu().numpy(), st.cpu().numpy()))
+    finally:
+        rb.batch_tuning_set(saved["blocks_per_cu"], saved["groups_per_tile"])
+    for w, st in outs[1:]:
+        assert np.array_equal(w, outs[0][0]) and np.array_equal(st, outs[0][1])
+    w_ref, st_ref = oracle.weights(ns.x, ns.y, nbr, order=ns.order)
+    assert np.array_equal(outs[0][1], st_ref)
+    for m in (2, 4, 6):
+        sel = ns.order == m
+        e = np.abs(outs[0][0][sel] - w_ref[sel]).max(1) / np.abs(w_ref[sel]).max(1)
+        assert e.max() <= 1e-11
+    with pytest.raises(rb.RbffdError):
+        rb.batch_tuning_set(0, [1, 1, 1])
+
+
+def test_pipeline_graph_capture_and_replay():
+    ns = nodes.cell_centred_square(100, seed=3, order_seed=33)
+    X, Y, O = dev(ns.x), dev(ns.y), dev(ns.order)
+    B = dev((np.arange(ns.n_nodes) % 23 == 0).astype(np.uint8))
+    u, f = nodes.manufactured(ns.x, ns.y)
+    U, F = dev(u), dev(f)
+
+    def pipeline():
+        nbr = rb.rbffd_knn(X, Y, 56)
+        w, st, _ = rb.rbffd_weights(X, Y, nbr, order=O)
+        rp, col, val = rb.rbffd_assemble_csr(nbr, w, order=O, is_boundary=B)
+        r = rb.rbffd_spmv(rp, col, val, U, F)
+        return nbr, w, st, rp, col, val, r
+
+    eager = [t.clone() for t in pipeline()]
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        pipeline()  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        captured = pipeline()
+    names = ("nbr", "w", "status", "row_ptr", "col", "val", "residual")
+    nnz = int(eager[3][-1])
+
+    def same(got, ref):
+        # col/val have capacity N * max n; only the first row_ptr[N] are defined
+        for name, a, b in zip(names, got, ref):
+            if name in ("col", "val"):
+                a, b = a[:nnz], b[:nnz]
+            assert torch.equal(a, b), name
+    for rep in range(3):
+        other = pipeline()  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        same(captured, eager)
+        same(other, eager)
