@@ -6,8 +6,8 @@
 // ones fill the tail:
 //   * an order-6 tile is gpt[2] stencils, each spread over both wavefronts
 //     of the block (one matrix row per lane, 84 rows);
-//   * an order-4 tile gives each wavefront gpt[1] groups of 2 stencils
-//     (32 lanes x 2 rows per stencil);
+//   * an order-4 tile gives each wavefront gpt[1] stencils (one row per
+//     lane);
 //   * an order-2 tile gives each wavefront gpt[0] groups of 8 stencils
 //     (8 lanes x 3 rows per stencil).
 // Tile sizes and the grid size (blocks per compute unit) are runtime
@@ -23,9 +23,14 @@ namespace rbffd {
 namespace {
 
 constexpr int kPB = 128;
-constexpr int kG18 = kWave / 8;   // stencils per wavefront group, K = 18
-constexpr int kG45 = kWave / 32;  // K = 45
+// per-wavefront layouts of the K = 18 and K = 45 bodies (segment width, rows
+// per lane): the same as the single-order kernels
+constexpr int kSeg18 = 8, kSl18 = 3;
+constexpr int kSeg45 = 64, kSl45 = 1;
+constexpr int kG18 = kWave / kSeg18;  // stencils per wavefront group, K = 18
+constexpr int kG45 = kWave / kSeg45;  // K = 45
 
+template <bool SAVE>
 __global__ __launch_bounds__(kPB) void weights_batch_kernel(
     const double *__restrict__ x, const double *__restrict__ y, int64_t n_nodes,
     const int32_t *__restrict__ nbr, int32_t k_stride, const int32_t *__restrict__ lists,
@@ -54,13 +59,13 @@ __global__ __launch_bounds__(kPB) void weights_batch_kernel(
         } else if (tile < T6 + T4) {
             const int64_t base = (tile - T6) * 2 * gpt4;
             for (int q = 0; q < gpt4; ++q)
-                wk::weights_ms_body<45, 32, 2, 30, 4, 2>(
+                wk::weights_ms_body<45, kSeg45, kSl45, 30, 4, 2, SAVE>(
                     x, y, n_nodes, nbr, k_stride, lists + n_nodes, c4, 30, 4, w, status, sv_lu,
                     sv_z, sv_s, sv_perm, sv_kmax, RBFFD_OK, base + 2 * q + wave, wave);
         } else {
             const int64_t base = (tile - T6 - T4) * 2 * gpt2;
             for (int q = 0; q < gpt2; ++q)
-                wk::weights_ms_body<18, 8, 3, 12, 2, 2>(
+                wk::weights_ms_body<18, kSeg18, kSl18, 12, 2, 2, SAVE>(
                     x, y, n_nodes, nbr, k_stride, lists, c2, 12, 2, w, status, sv_lu, sv_z, sv_s,
                     sv_perm, sv_kmax, RBFFD_OK, base + 2 * q + wave, wave);
         }
@@ -87,10 +92,16 @@ int weights_fp64_batch(const double *x, const double *y, int64_t n_nodes, const 
     int rc = fill_i32(queue, 0, 1, stream);
     if (rc) return rc;
     const int64_t blocks = (int64_t)g_blocks_per_cu.load() * cus;
-    hipLaunchKernelGGL(weights_batch_kernel, dim3((unsigned)blocks), dim3(kPB), 0, stream, x, y,
-                       n_nodes, nbr, k_stride, lists, counts, queue, g_gpt[0].load(),
-                       g_gpt[1].load(), g_gpt[2].load(), w, status, sv_lu, sv_z, sv_s, sv_perm,
-                       sv_kmax);
+    if (sv_lu)
+        hipLaunchKernelGGL(weights_batch_kernel<true>, dim3((unsigned)blocks), dim3(kPB), 0, stream,
+                           x, y, n_nodes, nbr, k_stride, lists, counts, queue, g_gpt[0].load(),
+                           g_gpt[1].load(), g_gpt[2].load(), w, status, sv_lu, sv_z, sv_s, sv_perm,
+                           sv_kmax);
+    else
+        hipLaunchKernelGGL(weights_batch_kernel<false>, dim3((unsigned)blocks), dim3(kPB), 0,
+                           stream, x, y, n_nodes, nbr, k_stride, lists, counts, queue,
+                           g_gpt[0].load(), g_gpt[1].load(), g_gpt[2].load(), w, status, nullptr,
+                           nullptr, nullptr, nullptr, 0);
     return last_launch_rc();
 }
 

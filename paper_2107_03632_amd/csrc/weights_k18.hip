@@ -8,7 +8,7 @@
 #define RBFFD_SL_K18 3
 #endif
 #ifndef RBFFD_OCC_K18
-#define RBFFD_OCC_K18 2
+#define RBFFD_OCC_K18 3
 #endif
 
 namespace rbffd {

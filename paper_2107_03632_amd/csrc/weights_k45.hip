@@ -1,14 +1,14 @@
-// FP64 weights kernel instance: K = 45 (m = 4, n = 30), 32 lanes x 2 rows per stencil, 2 stencils per wave.
+// FP64 weights kernel instance: K = 45 (m = 4, n = 30), one stencil per wave, one row per lane.
 #include "weights_ms.h"
 
 #ifndef RBFFD_SEG_K45
-#define RBFFD_SEG_K45 32
+#define RBFFD_SEG_K45 64
 #endif
 #ifndef RBFFD_SL_K45
-#define RBFFD_SL_K45 2
+#define RBFFD_SL_K45 1
 #endif
 #ifndef RBFFD_OCC_K45
-#define RBFFD_OCC_K45 0
+#define RBFFD_OCC_K45 3
 #endif
 
 namespace rbffd {

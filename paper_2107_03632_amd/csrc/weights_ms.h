@@ -30,9 +30,16 @@
 namespace rbffd {
 namespace wk {
 
+using lds_f64 = __attribute__((address_space(3))) double;
+
 template <int CTRL>
 __device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, false);
+}
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_mov(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xf, 0xf, false);
 }
 
 struct OpMax {
@@ -43,21 +50,53 @@ struct OpOr {
 };
 
 // All-reduce over each SEG-lane segment; every lane receives the result.
+// Inside a 16-lane row: DPP exchanges; across rows: permlane16_swap (rows
+// 2k <-> 2k+1) and permlane32_swap (halves), all in the VALU (no LDS).
 template <int SEG, class Op>
-__device__ __forceinline__ uint32_t seg_all(uint32_t v, int lane) {
+__device__ __forceinline__ uint32_t seg_all(uint32_t v, int /*lane*/) {
     static_assert(SEG == 4 || SEG == 8 || SEG == 16 || SEG == 32 || SEG == 64, "segment width");
     if constexpr (SEG >= 16) v = Op::f(v, dpp_u32<0x140>(v));  // row_mirror
     if constexpr (SEG >= 8) v = Op::f(v, dpp_u32<0x141>(v));   // row_half_mirror
     v = Op::f(v, dpp_u32<0x4E>(v));                            // quad_perm [2,3,0,1]
     v = Op::f(v, dpp_u32<0xB1>(v));                            // quad_perm [1,0,3,2]
-    if constexpr (SEG == 32) {
-        const uint32_t o = (uint32_t)__shfl_xor((int)v, 16, 64);
-        v = Op::f(v, o);
-    } else if constexpr (SEG == 64) {
-        v = Op::f(v, (uint32_t)__shfl_xor((int)v, 16, 64));
-        v = Op::f(v, (uint32_t)__shfl_xor((int)v, 32, 64));
+    if constexpr (SEG >= 32) {
+        const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        v = Op::f(r[0], r[1]);
+    }
+    if constexpr (SEG == 64) {
+        const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        v = Op::f(r[0], r[1]);
     }
     return v;
+}
+
+// Lane SRC of each SEG-lane segment, delivered to every lane of the segment.
+template <int SEG, int SRC>
+__device__ __forceinline__ uint32_t seg_bcast_u32(uint32_t v, bool upper8) {
+    static_assert(SRC >= 0 && SRC < SEG, "source lane");
+    if constexpr (SEG == 4) {
+        return dpp_mov<SRC | (SRC << 2) | (SRC << 4) | (SRC << 6)>(v);  // quad_perm
+    } else if constexpr (SEG == 8) {
+        const uint32_t a = dpp_mov<0x150 + SRC>(v);  // row_newbcast
+        const uint32_t b = dpp_mov<0x158 + SRC>(v);
+        return upper8 ? b : a;
+    } else if constexpr (SEG == 16) {
+        return dpp_mov<0x150 + SRC>(v);
+    } else if constexpr (SEG == 32) {
+        const uint32_t t = dpp_mov<0x150 + (SRC & 15)>(v);
+        const auto r = __builtin_amdgcn_permlane16_swap(t, t, false, false);
+        return (SRC < 16) ? r[0] : r[1];
+    } else {
+        return (uint32_t)__builtin_amdgcn_readlane((int)v, SRC);
+    }
+}
+
+template <int SEG, int SRC>
+__device__ __forceinline__ double seg_bcast_d(double v, bool upper8) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t hi = seg_bcast_u32<SEG, SRC>((uint32_t)(b >> 32), upper8);
+    const uint32_t lo = seg_bcast_u32<SEG, SRC>((uint32_t)b, upper8);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
 template <int SEG>
@@ -95,14 +134,23 @@ __device__ __forceinline__ void seg_argmax_full(uint32_t &kh, uint32_t &kl, int 
     }
 }
 
-template <int KP, int SEG, int SL, int MM>
+// LDS of one stencil.  During assembly: the scaled offsets and the monomial
+// table.  From the elimination on: the rows of U with their right-hand side,
+// in pivot order (row c holds columns c..KP-1 and, at KP, the eliminated
+// right-hand side).  Rows 2p and 2p+1 share one region, interleaved, so the
+// entries of one row lie 16 bytes apart: a row is stored with 64-bit writes
+// that never merge into 128-bit ones (which would need contiguous registers).
+template <int KP, int MM>
 struct MsLds {
-    static constexpr int GPB = kWave / SEG;
-    static constexpr int PSZ = GPB * KP * MM;            // monomial table (assembly)
-    // pivot rows (elimination); entries 16 bytes apart so that stores are
-    // never merged into 128-bit writes that would need contiguous registers
-    static constexpr int RSZ = 2 * GPB * 2 * (KP + 1);
-    static constexpr int USZ = PSZ > RSZ ? PSZ : RSZ;
+    // start of the region of rows 2p, 2p+1
+    __host__ __device__ static constexpr int region(int p) { return 2 * p * (KP + 2 - p); }
+    // entry q of row r sits at ubase(r) + 2 q
+    __host__ __device__ static constexpr int ubase(int r) {
+        return region(r / 2) - 4 * (r / 2) + (r & 1);
+    }
+    static constexpr int USZ = region((KP + 1) / 2);
+    static constexpr int ASZ = KP * (MM + 2);  // ux, uy, monomials
+    static constexpr int SZ = ((USZ > ASZ ? USZ : ASZ) + 1) & ~1;
 };
 
 // LDS ordering inside one wavefront: this wave's earlier LDS writes are
@@ -113,10 +161,34 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+// One column of the back substitution (column C, then C-1, ... down to 0):
+// the source lane of the broadcast must be a compile-time constant.
+// PRE: the lane's rows of U were copied to registers ur[s][q] (row-major,
+// stride KP) beforehand.
+template <int KP, int SEG, int SL, int C, bool PRE>
+__device__ __forceinline__ void bc_step(const double *sU, const int *ub, const double *ur,
+                                        double *yb, const double *mb, double *zm, int l0,
+                                        bool upper8) {
+    if constexpr (C >= 0) {
+        constexpr int S = C / SEG, LC = C % SEG;
+        const double zl = yb[S] * mb[S];  // z_C, meaningful in lane LC
+        const double z = seg_bcast_d<SEG, LC>(zl, upper8);
+        zm[S] = (l0 == LC) ? z : zm[S];
+#pragma unroll
+        for (int s = 0; s < SL; ++s)
+            if (SEG * s < C) {
+                const double uc = PRE ? ur[s * KP + C] : sU[ub[s] + 2 * C];
+                yb[s] = fma(-uc, z, yb[s]);
+            }
+        bc_step<KP, SEG, SL, C - 1, PRE>(sU, ub, ur, yb, mb, zm, l0, upper8);
+    }
+}
+
 // One wavefront computes the stencils of group `grp` (stencils
 // grp*GPB .. grp*GPB+GPB-1 of the row list).  WPB wavefronts of a block run
-// independent groups; `wave` selects this wavefront's LDS.
-template <int KP, int SEG, int SL, int NFIX, int MFIX, int WPB>
+// independent groups; `wave` selects this wavefront's LDS.  SAVE keeps the
+// multipliers of L in registers and writes the factors for the adjoint.
+template <int KP, int SEG, int SL, int NFIX, int MFIX, int WPB, bool SAVE>
 __device__ __forceinline__ void weights_ms_body(
     const double *__restrict__ x, const double *__restrict__ y, int64_t n_nodes,
     const int32_t *__restrict__ nbr, int32_t k_stride, const int32_t *__restrict__ rows,
@@ -127,26 +199,24 @@ __device__ __forceinline__ void weights_ms_body(
     static_assert(SEG * SL >= KP, "slots must cover the system");
     constexpr int GPB = kWave / SEG;
     constexpr int MM = MFIX ? (MFIX + 1) * (MFIX + 2) / 2 : 28;
-    using L = MsLds<KP, SEG, SL, MM>;
+    using L = MsLds<KP, MM>;
     const int n = NFIX ? NFIX : n_arg;
     const int m = MFIX ? MFIX : m_arg;
     const int NM = (m + 1) * (m + 2) / 2;
     const int K = n + NM;
 
-    __shared__ double s_ux_b[WPB][GPB][KP];
-    __shared__ double s_uy_b[WPB][GPB][KP];
-    __shared__ double s_u_b[WPB][L::USZ];     // monomial table, then pivot rows
+    __shared__ double s_lds[WPB][GPB][L::SZ];
     __shared__ int32_t s_pos_b[WPB][2][GPB];  // position of the pivot row
-    double(*s_ux)[KP] = s_ux_b[wave];
-    double(*s_uy)[KP] = s_uy_b[wave];
-    double *s_u = s_u_b[wave];
-    int32_t(*s_pos)[GPB] = s_pos_b[wave];
-    double(*s_P)[MM] = reinterpret_cast<double(*)[MM]>(s_u);  // [GPB*KP][MM]
-    double(*s_row)[GPB][2 * (KP + 1)] = reinterpret_cast<double(*)[GPB][2 * (KP + 1)]>(s_u);
 
     const int lane = threadIdx.x & (kWave - 1);
     const int g = lane / SEG;
     const int l0 = lane % SEG;
+    double *sU = s_lds[wave][g];
+    double *s_ux = sU;                                          // [KP]
+    double *s_uy = sU + KP;                                     // [KP]
+    double(*s_P)[MM] = reinterpret_cast<double(*)[MM]>(sU + 2 * KP);  // [KP][MM]
+    int32_t(*s_pos)[GPB] = s_pos_b[wave];
+
     if (grp * GPB >= n_rows) return;  // whole wave idle
     const int64_t t = grp * GPB + g;
     const bool valid = t < n_rows;
@@ -192,8 +262,8 @@ __device__ __forceinline__ void weights_ms_body(
         if (r < n) {
             ux[s] = dx[s] / sc;
             uy[s] = dy[s] / sc;
-            s_ux[g][r] = ux[s];
-            s_uy[g][r] = uy[s];
+            s_ux[r] = ux[s];
+            s_uy[r] = uy[s];
             double px[7], py[7];
             px[0] = 1.0;
             py[0] = 1.0;
@@ -204,7 +274,7 @@ __device__ __forceinline__ void weights_ms_body(
             }
 #pragma unroll
             for (int j = 0; j < MM; ++j)
-                if (j < NM) s_P[g * KP + r][j] = px[mono_a(j)] * py[mono_b(j)];
+                if (j < NM) s_P[r][j] = px[mono_a(j)] * py[mono_b(j)];
         }
     }
     wave_sync();
@@ -225,16 +295,16 @@ __device__ __forceinline__ void weights_ms_body(
             if (l < n) {
                 double phs = 0.0;
                 if (any_p) {
-                    const double ex = ux[s] - s_ux[g][l];
-                    const double ey = uy[s] - s_uy[g][l];
+                    const double ex = ux[s] - s_ux[l];
+                    const double ey = uy[s] - s_uy[l];
                     const double rr = ex * ex + ey * ey;
                     if (prow && l != r && rr == 0.0) flags |= F_DUP;
                     phs = rr * sqrt(rr);
                 }
-                const double pt = s_P[g * KP + l][jr];
+                const double pt = s_P[l][jr];
                 a[s][l] = prow ? phs : (qrow ? pt : 0.0);
             } else if (l < K) {
-                a[s][l] = prow ? s_P[g * KP + (r < KP ? r : 0)][l - n] : 0.0;
+                a[s][l] = prow ? s_P[r < KP ? r : 0][l - n] : 0.0;
             } else {
                 a[s][l] = (l == r) ? 1.0 : 0.0;
             }
@@ -247,19 +317,16 @@ __device__ __forceinline__ void weights_ms_body(
     // materialise the flags here: otherwise the duplicate checks sink to the
     // end of the kernel and keep every squared distance alive through the LU
     asm volatile("" : "+v"(flags));
-    wave_sync();  // the monomial table's space becomes the pivot rows
+    wave_sync();  // the assembly tables' space becomes the rows of U
 
     // ---- LU with partial pivoting, right-looking, rhs carried along --------
     int pos[SL];
     bool done[SL];
-    double minv[SL];
 #pragma unroll
     for (int s = 0; s < SL; ++s) {
         pos[s] = l0 + SEG * s;
         done[s] = pos[s] >= KP;
-        minv[s] = 0.0;
     }
-    uint32_t luflag = 0;
     const uint64_t segmask = SEG == 64 ? ~0ull : ((1ull << SEG) - 1ull);
     const int segbase = g * SEG;
 #pragma unroll
@@ -268,6 +335,7 @@ __device__ __forceinline__ void weights_ms_body(
         // best slot of this lane: exact key (|a| bits, position)
         uint64_t bb = 0;
         int bp = 0x7fffffff, bs = 0;
+        double bv = 0.0;
         bool ba = false;
 #pragma unroll
         for (int s = 0; s < SL; ++s) {
@@ -276,61 +344,84 @@ __device__ __forceinline__ void weights_ms_body(
             bb = take ? bits : bb;
             bp = take ? pos[s] : bp;
             bs = take ? s : bs;
+            bv = take ? a[s][c] : bv;
             ba = ba || !done[s];
         }
         const uint32_t kh = ba ? (uint32_t)(bb >> 32) + 1u : 0u;
         const uint32_t mh = seg_all<SEG, OpMax>(kh, lane);
-        uint64_t chunk = (__ballot(ba && kh == mh) >> segbase) & segmask;
-        const bool uniq = (chunk & (chunk - 1ull)) == 0ull;
-        if (__builtin_expect(__ballot(!uniq) != 0ull, 0)) {
-            uint32_t h2 = kh, l2 = ba ? (uint32_t)bb : 0u;
-            int p2 = ba ? bp : 0x7fffffff;
-            seg_argmax_full<SEG>(h2, l2, p2);
-            chunk = (__ballot(ba && bp == p2) >> segbase) & segmask;
+        int win;
+        if constexpr (GPB == 1) {
+            // one stencil per wavefront: the ballot is the segment's mask
+            uint64_t chunk = __ballot(ba && kh == mh);
+            if (__builtin_expect((chunk & (chunk - 1ull)) != 0ull, 0)) {
+                uint32_t h2 = kh, l2 = ba ? (uint32_t)bb : 0u;
+                int p2 = ba ? bp : 0x7fffffff;
+                seg_argmax_full<SEG>(h2, l2, p2);
+                chunk = __ballot(ba && bp == p2);
+            }
+            win = __ffsll((unsigned long long)chunk) - 1;
+        } else {
+            uint64_t chunk = (__ballot(ba && kh == mh) >> segbase) & segmask;
+            const bool uniq = (chunk & (chunk - 1ull)) == 0ull;
+            if (__builtin_expect(__ballot(!uniq) != 0ull, 0)) {
+                uint32_t h2 = kh, l2 = ba ? (uint32_t)bb : 0u;
+                int p2 = ba ? bp : 0x7fffffff;
+                seg_argmax_full<SEG>(h2, l2, p2);
+                chunk = (__ballot(ba && bp == p2) >> segbase) & segmask;
+            }
+            win = __ffsll((unsigned long long)chunk) - 1;
         }
-        const int win = __ffsll((unsigned long long)chunk) - 1;
         const bool is_win = (l0 == win);
+        double *u = sU + L::ubase(c);  // row c of U: entry q at u[2q]
 #pragma unroll
         for (int s = 0; s < SL; ++s) {
             if (is_win && bs == s) {
 #pragma unroll
-                for (int q = c; q < KP; ++q) s_row[buf][g][2 * q] = a[s][q];
-                s_row[buf][g][2 * KP] = yv[s];
-                s_pos[buf][g] = pos[s];
+                for (int q = c; q < KP; ++q) u[2 * q] = a[s][q];
+                u[2 * KP] = yv[s];
+                if constexpr (GPB > 1) s_pos[buf][g] = pos[s];
             }
         }
-        wave_sync();
-        const double *u = s_row[buf][g];  // entry q at u[2q]
-        const double piv = u[2 * c];
-        const int kp = s_pos[buf][g];
-        const double inv = 1.0 / piv;
-        if (luflag == 0) {
-            if (!isfinite(piv)) luflag = L_NONFIN;
-            else if (piv == 0.0) luflag = L_SING;
+        double piv;
+        int kp;
+        if constexpr (GPB == 1) {
+            // the pivot and its position straight from the winning lane
+            const uint64_t pb = (uint64_t)__double_as_longlong(bv);
+            const uint32_t ph = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(pb >> 32), win);
+            const uint32_t pl = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)pb, win);
+            piv = __longlong_as_double((long long)(((uint64_t)ph << 32) | pl));
+            kp = __builtin_amdgcn_readlane(bp, win);
+            wave_sync();
+        } else {
+            wave_sync();
+            piv = u[2 * c];
+            kp = s_pos[buf][g];
         }
+        const double inv = 1.0 / piv;
         double lm[SL];
 #pragma unroll
         for (int s = 0; s < SL; ++s) {
             const bool upd = !done[s] && !(is_win && bs == s);
             lm[s] = upd ? a[s][c] * inv : 0.0;
-            a[s][c] = upd ? lm[s] : a[s][c];
+            if constexpr (SAVE) a[s][c] = upd ? lm[s] : a[s][c];
         }
         // Columns c+1 .. KP (KP: the right-hand side) in chunks of CH.  The
-        // reads of chunk k go through an offset (always 0) that an empty asm
+        // reads of chunk k go through the row pointer, which an empty asm
         // ties to an update result of chunk k-2: the reads cannot be hoisted
         // further ahead, which bounds the registers they occupy while still
-        // overlapping them with two chunks of updates.
+        // overlapping them with two chunks of updates (no instruction is
+        // emitted for the tie).
         {
             constexpr int CH = 4;
-            int off = 0;
+            lds_f64 *up = (lds_f64 *)u;
             double dep0 = 0.0, dep1 = 0.0;
 #pragma unroll
             for (int q0 = c + 1; q0 <= KP; q0 += CH) {
-                asm volatile("" : "+v"(off) : "v"(dep0));
+                asm volatile("" : "+v"(up) : "v"(dep0));
                 double uq[CH];
 #pragma unroll
                 for (int j = 0; j < CH; ++j)
-                    if (q0 + j <= KP) uq[j] = u[2 * (q0 + j) + off];
+                    if (q0 + j <= KP) uq[j] = up[2 * (q0 + j)];
 #pragma unroll
                 for (int j = 0; j < CH; ++j) {
                     const int q = q0 + j;
@@ -350,7 +441,6 @@ __device__ __forceinline__ void weights_ms_body(
         for (int s = 0; s < SL; ++s) {
             const bool isp = is_win && bs == s;
             pos[s] = isp ? c : ((!done[s] && pos[s] == c) ? kp : pos[s]);
-            minv[s] = isp ? inv : minv[s];
             done[s] = done[s] || isp;
             // opaque to the optimiser: keeps it from folding each step's
             // comparisons back through the select chain of all earlier steps
@@ -359,31 +449,47 @@ __device__ __forceinline__ void weights_ms_body(
             asm volatile("" : "+v"(pos[s]), "+v"(dn));
             done[s] = dn != 0;
         }
-        asm volatile("" : "+v"(luflag));
     }
+    wave_sync();  // the last row of U is visible
 
-    // ---- back substitution ------------------------------------------------
-    double zm[SL];
+    // ---- back substitution over the rows of U in LDS -----------------------
+    // Lane l0 takes positions l0 + SEG*s.  z_c = y_c / U_cc is formed in the
+    // lane holding position c and broadcast inside the segment; every row
+    // then subtracts U_rc z_c (rows at or past c only change values that are
+    // no longer read).
+    // 8-lane segments: odd segments are the upper halves of 16-lane rows
+    const bool upper8 = SEG == 8 && (lane & 8) != 0;
+    // The pivots are the diagonal of U; the first zero or non-finite one
+    // (lowest column) decides the status.
+    constexpr bool PRE = SL * KP <= 64;  // rows of U held in registers
+    int ub[SL];
+    double yb[SL], mb[SL], zm[SL];
+    double ur[PRE ? SL : 1][PRE ? KP : 1];
+    uint32_t lukey = 0;
 #pragma unroll
-    for (int s = 0; s < SL; ++s) zm[s] = 0.0;
+    for (int s = 0; s < SL; ++s) {
+        const int r0 = l0 + SEG * s;
+        const int r = r0 < KP ? r0 : KP - 1;
+        ub[s] = L::ubase(r);
+        yb[s] = sU[ub[s] + 2 * KP];
+        const double d = sU[ub[s] + 2 * r];
+        mb[s] = 1.0 / d;
+        zm[s] = 0.0;
+        const uint32_t f = !isfinite(d) ? L_NONFIN : (d == 0.0 ? L_SING : 0u);
+        const uint32_t key = ((uint32_t)(KP - r0) << 2) | f;  // lower column, larger key
+        if (r0 < KP && f && key > lukey) lukey = key;
+        if constexpr (PRE) {
 #pragma unroll
-    for (int c = KP - 1; c >= 0; --c) {
-        double zl = 0.0;
-#pragma unroll
-        for (int s = 0; s < SL; ++s) {
-            const double zc = yv[s] * minv[s];
-            zm[s] = (pos[s] == c) ? zc : zm[s];
-            zl = (pos[s] == c) ? zc : zl;
+            for (int q = 0; q < KP; ++q) ur[s][q] = sU[ub[s] + 2 * q];
         }
-        const double z = seg_all_or_d<SEG>(zl, lane);  // exactly one slot holds position c
-#pragma unroll
-        for (int s = 0; s < SL; ++s) yv[s] = (pos[s] < c) ? fma(-a[s][c], z, yv[s]) : yv[s];
     }
+    const uint32_t luflag = seg_all<SEG, OpMax>(lukey, lane) & 3u;
+    bc_step<KP, SEG, SL, KP - 1, PRE>(sU, ub, ur[0], yb, mb, zm, l0, upper8);
 
     // ---- status and outputs -----------------------------------------------
 #pragma unroll
     for (int s = 0; s < SL; ++s)
-        if (pos[s] < K && !isfinite(zm[s])) flags |= F_ZBAD;
+        if (l0 + SEG * s < K && !isfinite(zm[s])) flags |= F_ZBAD;
     flags = seg_all<SEG, OpOr>(flags, lane);
     int st = RBFFD_OK;
     if (flags & F_BADIDX) st = RBFFD_BAD_INDEX;
@@ -398,11 +504,13 @@ __device__ __forceinline__ void weights_ms_body(
     const double s2 = sc * sc;
     const bool good = st == RBFFD_OK;
 #pragma unroll
-    for (int s = 0; s < SL; ++s)
-        if (pos[s] < n) wi[pos[s]] = good ? zm[s] / s2 : __builtin_nan("");
+    for (int s = 0; s < SL; ++s) {
+        const int r = l0 + SEG * s;
+        if (r < n) wi[r] = good ? zm[s] / s2 : __builtin_nan("");
+    }
     for (int q = n + l0; q < k_stride; q += SEG) wi[q] = 0.0;
     if (l0 == 0 && status) status[i] = good ? ok_code : st;
-    if (sv_lu) {
+    if constexpr (SAVE) {
         const int64_t kk = (int64_t)sv_kmax * sv_kmax;
 #pragma unroll
         for (int s = 0; s < SL; ++s) {
@@ -411,17 +519,19 @@ __device__ __forceinline__ void weights_ms_body(
 #pragma unroll
                 for (int q = 0; q < KP; ++q)
                     if (q < K) dst[q] = a[s][q];
-                sv_z[i * (int64_t)sv_kmax + pos[s]] = zm[s];
                 sv_perm[i * (int64_t)sv_kmax + pos[s]] = (uint8_t)(l0 + SEG * s);
-                if (pos[s] == 0) sv_s[i] = sc;
             }
+            const int r = l0 + SEG * s;
+            if (r < K) sv_z[i * (int64_t)sv_kmax + r] = zm[s];
         }
+        if (l0 == 0) sv_s[i] = sc;
     }
 }
 
-template <int KP, int SEG, int SL, int NFIX, int MFIX, int OCC>
+template <int KP, int SEG, int SL, int NFIX, int MFIX, int OCC, bool SAVE>
 __global__ __launch_bounds__(kWave)
-__attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1))) void weights_ms_kernel(
+__attribute__((amdgpu_waves_per_eu(OCC <= 0 ? 1 : (SAVE && OCC > 2 ? 2 : OCC)))) void
+weights_ms_kernel(
     const double *__restrict__ x, const double *__restrict__ y, int64_t n_nodes,
     const int32_t *__restrict__ nbr, int32_t k_stride, const int32_t *__restrict__ rows,
     const int32_t *__restrict__ n_rows_dev, int64_t n_rows, int32_t n_arg, int32_t m_arg,
@@ -429,9 +539,10 @@ __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1))) void weights_ms_kernel(
     double *__restrict__ sv_z, double *__restrict__ sv_s, uint8_t *__restrict__ sv_perm,
     int32_t sv_kmax, int32_t ok_code) {
     if (n_rows_dev) n_rows = *n_rows_dev;
-    weights_ms_body<KP, SEG, SL, NFIX, MFIX, 1>(x, y, n_nodes, nbr, k_stride, rows, n_rows, n_arg,
-                                                m_arg, w, status, sv_lu, sv_z, sv_s, sv_perm,
-                                                sv_kmax, ok_code, (int64_t)blockIdx.x, 0);
+    weights_ms_body<KP, SEG, SL, NFIX, MFIX, 1, SAVE>(x, y, n_nodes, nbr, k_stride, rows, n_rows,
+                                                      n_arg, m_arg, w, status, sv_lu, sv_z, sv_s,
+                                                      sv_perm, sv_kmax, ok_code,
+                                                      (int64_t)blockIdx.x, 0);
 }
 
 template <int KP, int SEG, int SL, int NFIX, int MFIX, int OCC = 0>
@@ -443,9 +554,16 @@ inline int launch_ms(const double *x, const double *y, int64_t n_nodes, const in
     if (n_rows <= 0) return RBFFD_SUCCESS;
     const int64_t blocks = ceil_div(n_rows, GPB);
     if (blocks > 0x7fffffff) return RBFFD_ERR_UNSUPPORTED;
-    hipLaunchKernelGGL((weights_ms_kernel<KP, SEG, SL, NFIX, MFIX, OCC>), dim3((unsigned)blocks),
-                       dim3(kWave), 0, stream, x, y, n_nodes, nbr, k_stride, rows, n_rows_dev,
-                       n_rows, n, m, w, status, sv.lu, sv.z, sv.s, sv.perm, sv.kmax, ok_code);
+    if (sv.lu)
+        hipLaunchKernelGGL((weights_ms_kernel<KP, SEG, SL, NFIX, MFIX, OCC, true>),
+                           dim3((unsigned)blocks), dim3(kWave), 0, stream, x, y, n_nodes, nbr,
+                           k_stride, rows, n_rows_dev, n_rows, n, m, w, status, sv.lu, sv.z, sv.s,
+                           sv.perm, sv.kmax, ok_code);
+    else
+        hipLaunchKernelGGL((weights_ms_kernel<KP, SEG, SL, NFIX, MFIX, OCC, false>),
+                           dim3((unsigned)blocks), dim3(kWave), 0, stream, x, y, n_nodes, nbr,
+                           k_stride, rows, n_rows_dev, n_rows, n, m, w, status, nullptr, nullptr,
+                           nullptr, nullptr, 0, ok_code);
     return last_launch_rc();
 }
 
