@@ -54,8 +54,12 @@ def source_digest(paths) -> str:
     return h.hexdigest()[:16]
 
 
-WEIGHTS_SOURCES = ["paper_2107_03632_amd/csrc/weights_kernel.h",
+# sources of the dominant kernel (K = 45 instance of the multi-slot kernel)
+WEIGHTS_SOURCES = ["paper_2107_03632_amd/csrc/common.h",
+                   "paper_2107_03632_amd/csrc/weights_kernel.h",
+                   "paper_2107_03632_amd/csrc/weights_ms.h",
                    "paper_2107_03632_amd/csrc/weights_k45.hip"]
+WEIGHTS_KERNEL = "weights_ms_kernel<45, 64, 1, 30, 4, 4, false>"
 
 
 def read_traffic(kernel_tag: str):
@@ -197,7 +201,7 @@ def main():
         "config": {"workload": "unit disk, 100k jittered lattice nodes + 1000 boundary, "
                                "m=4, n=30, FP64: kNN -> weights -> CSR -> W u - f",
                    "n_nodes": N, "m": m, "n": n, "global_batch": N, "parallelism": "none"},
-        "roofline": {"bound": "alu", "kernel": "weights_fp64_kernel<45,64,30,4>",
+        "roofline": {"bound": "alu", "kernel": WEIGHTS_KERNEL,
                      "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
                      "flops_per_stencil": weights_flops(m, n), "launch_ms": w_ms_avg},
@@ -265,15 +269,58 @@ def extras_per_order(torch, rb, nodes, dev, stream):
         }
     O = torch.as_tensor(ns.order, device=dev)
     ms = timed(torch, stream, lambda: rb.rbffd_weights(X, Y, nbr, order=O))
+    ms_graph = graph_timed(torch, lambda: rb.rbffd_weights(X, Y, nbr, order=O))
     ms_mx = timed(torch, stream, lambda: rb.rbffd_weights(X, Y, nbr, order=O, precision=rb.MIXED))
     counts = {mm: int((ns.order == mm).sum()) for mm in (2, 4, 6)}
     fl = sum(counts[mm] * weights_flops(mm, nn) for mm, nn in ((2, 12), (4, 30), (6, 56)))
     res["mixed_order"] = {"fp64": {"stencils_per_s": N / (ms * 1e-3), "ms": ms,
-                                   "frac_fp64_peak": fl / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS},
+                                   "frac_fp64_peak": fl / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+                                   "graph_replay_ms": ms_graph,
+                                   "graph_stencils_per_s": N / (ms_graph * 1e-3)},
                           "mixed": {"stencils_per_s": N / (ms_mx * 1e-3), "ms": ms_mx,
                                     "speedup_vs_fp64": ms / ms_mx}}
     res["knn_k56_ms"] = timed(torch, stream, lambda: rb.rbffd_knn(X, Y, 56))
+    # m = 6 at h = 1e-2 (10k nodes): both precisions on the same input
+    ns10 = nodes.workload("square_10k_m6")
+    X10 = torch.as_tensor(ns10.x, device=dev)
+    Y10 = torch.as_tensor(ns10.y, device=dev)
+    nb10 = rb.rbffd_knn(X10, Y10, 56)
+    ms64 = timed(torch, stream, lambda: rb.rbffd_weights(X10, Y10, nb10, m=6, n=56))
+    msmx = timed(torch, stream, lambda: rb.rbffd_weights(X10, Y10, nb10, m=6, n=56,
+                                                         precision=rb.MIXED))
+    w64, _, _ = rb.rbffd_weights(X10, Y10, nb10, m=6, n=56)
+    wmx, stmx, _ = rb.rbffd_weights(X10, Y10, nb10, m=6, n=56, precision=rb.MIXED)
+    err = ((wmx - w64).abs().amax(1) / w64.abs().amax(1)).max().item()
+    res["square_10k_m6"] = {"n_nodes": ns10.n_nodes, "fp64_ms": ms64, "mixed_ms": msmx,
+                            "fell_back": int((stmx == rb.FELL_BACK_FP64).sum().item()),
+                            "max_rel_err_mixed_vs_fp64": err}
     return res
+
+
+def graph_timed(torch, fn, reps=3):
+    """Median time of one replay of fn captured in a graph (fn allocates its
+    outputs and workspace from the graph's private pool)."""
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fn()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    g.replay()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.replay()
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts))
 
 
 if __name__ == "__main__":

@@ -8,7 +8,7 @@
 #define RBFFD_SL_K45 1
 #endif
 #ifndef RBFFD_OCC_K45
-#define RBFFD_OCC_K45 3
+#define RBFFD_OCC_K45 4
 #endif
 
 namespace rbffd {

@@ -32,6 +32,14 @@ namespace wk {
 
 using lds_f64 = __attribute__((address_space(3))) double;
 
+#ifndef RBFFD_ROWS_BY_READLANE
+#define RBFFD_ROWS_BY_READLANE 1
+#endif
+// One stencil per wavefront: broadcast the pivot row with readlane (VALU,
+// scalar operands) instead of LDS reads by every lane.
+constexpr bool kRowsByReadlane = RBFFD_ROWS_BY_READLANE != 0;
+
+
 template <int CTRL>
 __device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, false);
@@ -299,6 +307,9 @@ __device__ __forceinline__ void weights_ms_body(
                     const double ey = uy[s] - s_uy[l];
                     const double rr = ex * ex + ey * ey;
                     if (prow && l != r && rr == 0.0) flags |= F_DUP;
+                    // settle the check now: sunk past the loop it would keep
+                    // every squared distance alive (no instruction emitted)
+                    asm volatile("" : "+v"(flags));
                     phs = rr * sqrt(rr);
                 }
                 const double pt = s_P[l][jr];
@@ -411,7 +422,17 @@ __device__ __forceinline__ void weights_ms_body(
         // further ahead, which bounds the registers they occupy while still
         // overlapping them with two chunks of updates (no instruction is
         // emitted for the tie).
-        {
+        if constexpr (GPB == 1 && SL == 1 && kRowsByReadlane) {
+            // one stencil per wavefront: the pivot row comes straight from
+            // the winning lane's registers into scalar registers
+            const int wl = __builtin_amdgcn_readfirstlane(win);
+#pragma unroll
+            for (int q = c + 1; q <= KP; ++q) {
+                const double uqv = readlane_d(q < KP ? a[0][q] : yv[0], wl);
+                if (q < KP) a[0][q] = fma(-lm[0], uqv, a[0][q]);
+                else yv[0] = fma(-lm[0], uqv, yv[0]);
+            }
+        } else {
             constexpr int CH = 4;
             lds_f64 *up = (lds_f64 *)u;
             double dep0 = 0.0, dep1 = 0.0;
