@@ -17,7 +17,7 @@
 
 #include <atomic>
 
-#include "weights_ms.h"
+#include "weights_cs.h"
 
 namespace rbffd {
 namespace {
@@ -53,7 +53,7 @@ __global__ __launch_bounds__(kPB) void weights_batch_kernel(
         if (tile >= total) break;
         if (tile < T6) {
             for (int q = 0; q < gpt6; ++q)
-                wk::weights_fp64_body<84, 128, 56, 6>(
+                wk::weights_cs_body<84, 56, 6, SAVE>(
                     x, y, n_nodes, nbr, k_stride, lists + 2 * n_nodes, c6, 56, 6, w, status, sv_lu,
                     sv_z, sv_s, sv_perm, sv_kmax, RBFFD_OK, tile * gpt6 + q);
         } else if (tile < T6 + T4) {
