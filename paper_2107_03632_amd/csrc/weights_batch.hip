@@ -22,6 +22,10 @@
 namespace rbffd {
 namespace {
 
+#ifndef RBFFD_BATCH_OCC
+#define RBFFD_BATCH_OCC 2
+#endif
+
 constexpr int kPB = 128;
 // per-wavefront layouts of the K = 18 and K = 45 bodies (segment width, rows
 // per lane): the same as the single-order kernels
@@ -31,7 +35,7 @@ constexpr int kG18 = kWave / kSeg18;  // stencils per wavefront group, K = 18
 constexpr int kG45 = kWave / kSeg45;  // K = 45
 
 template <bool SAVE>
-__global__ __launch_bounds__(kPB) void weights_batch_kernel(
+__global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(RBFFD_BATCH_OCC))) void weights_batch_kernel(
     const double *__restrict__ x, const double *__restrict__ y, int64_t n_nodes,
     const int32_t *__restrict__ nbr, int32_t k_stride, const int32_t *__restrict__ lists,
     const int32_t *__restrict__ counts, int32_t *__restrict__ queue, int32_t gpt2, int32_t gpt4,
@@ -39,6 +43,12 @@ __global__ __launch_bounds__(kPB) void weights_batch_kernel(
     double *__restrict__ sv_lu, double *__restrict__ sv_z, double *__restrict__ sv_s,
     uint8_t *__restrict__ sv_perm, int32_t sv_kmax) {
     __shared__ int32_t s_tile;
+    // one LDS buffer serves whichever body the current tile runs
+    constexpr int kLds0 = wk::cs_lds_bytes<84, 6>();
+    constexpr int kLds1 = wk::ms_lds_bytes<45, kSeg45, 4, 2>();
+    constexpr int kLds2 = wk::ms_lds_bytes<18, kSeg18, 2, 2>();
+    constexpr int kLds = kLds0 > kLds1 ? (kLds0 > kLds2 ? kLds0 : kLds2) : (kLds1 > kLds2 ? kLds1 : kLds2);
+    __shared__ __align__(16) char lds[kLds];
     const int64_t c2 = counts[0], c4 = counts[1], c6 = counts[2];
     const int64_t T6 = ceil_div(c6, gpt6);
     const int64_t T4 = ceil_div(c4, 2 * (int64_t)gpt4 * kG45);
@@ -55,19 +65,19 @@ __global__ __launch_bounds__(kPB) void weights_batch_kernel(
             for (int q = 0; q < gpt6; ++q)
                 wk::weights_cs_body<84, 56, 6, SAVE>(
                     x, y, n_nodes, nbr, k_stride, lists + 2 * n_nodes, c6, 56, 6, w, status, sv_lu,
-                    sv_z, sv_s, sv_perm, sv_kmax, RBFFD_OK, tile * gpt6 + q);
+                    sv_z, sv_s, sv_perm, sv_kmax, RBFFD_OK, tile * gpt6 + q, lds);
         } else if (tile < T6 + T4) {
             const int64_t base = (tile - T6) * 2 * gpt4;
             for (int q = 0; q < gpt4; ++q)
                 wk::weights_ms_body<45, kSeg45, kSl45, 30, 4, 2, SAVE>(
                     x, y, n_nodes, nbr, k_stride, lists + n_nodes, c4, 30, 4, w, status, sv_lu,
-                    sv_z, sv_s, sv_perm, sv_kmax, RBFFD_OK, base + 2 * q + wave, wave);
+                    sv_z, sv_s, sv_perm, sv_kmax, RBFFD_OK, base + 2 * q + wave, wave, lds);
         } else {
             const int64_t base = (tile - T6 - T4) * 2 * gpt2;
             for (int q = 0; q < gpt2; ++q)
                 wk::weights_ms_body<18, kSeg18, kSl18, 12, 2, 2, SAVE>(
                     x, y, n_nodes, nbr, k_stride, lists, c2, 12, 2, w, status, sv_lu, sv_z, sv_s,
-                    sv_perm, sv_kmax, RBFFD_OK, base + 2 * q + wave, wave);
+                    sv_perm, sv_kmax, RBFFD_OK, base + 2 * q + wave, wave, lds);
         }
     }
 }

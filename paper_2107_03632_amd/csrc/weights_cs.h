@@ -342,6 +342,14 @@ __device__ __forceinline__ void weights_cs_wave(
     }
 }
 
+// LDS bytes of weights_cs_body: the U triangle / assembly tables, the
+// multipliers [2][2][64], the pivot record [2][4] and one flag word.
+template <int KP, int MFIX>
+__host__ __device__ constexpr int cs_lds_bytes() {
+    constexpr int MM = MFIX ? (MFIX + 1) * (MFIX + 2) / 2 : 28;
+    return (int)sizeof(double) * (MsLds<KP, MM>::SZ + 2 * 2 * kWave) + 4 * 8 + 16;
+}
+
 // One block (two wavefronts) computes stencil `t` of the row list.
 template <int KP, int NFIX, int MFIX, bool SAVE>
 __device__ __forceinline__ void weights_cs_body(
@@ -350,22 +358,23 @@ __device__ __forceinline__ void weights_cs_body(
     int64_t n_rows, int32_t n_arg, int32_t m_arg, double *__restrict__ w,
     int32_t *__restrict__ status, double *__restrict__ sv_lu, double *__restrict__ sv_z,
     double *__restrict__ sv_s, uint8_t *__restrict__ sv_perm, int32_t sv_kmax, int32_t ok_code,
-    int64_t t) {
+    int64_t t, char *lds) {
     constexpr int MM = MFIX ? (MFIX + 1) * (MFIX + 2) / 2 : 28;
-    __shared__ double sU[MsLds<KP, MM>::SZ];
-    __shared__ double s_lm[2][2][kWave];
-    __shared__ int32_t s_pv[2][4];
-    __shared__ uint32_t s_fl;
+    constexpr int SZ = MsLds<KP, MM>::SZ;
+    double *sU = reinterpret_cast<double *>(lds);
+    auto s_lm = reinterpret_cast<double(*)[2][kWave]>(lds + sizeof(double) * SZ);
+    auto s_pv = reinterpret_cast<int32_t(*)[4]>(lds + sizeof(double) * (SZ + 2 * 2 * kWave));
+    uint32_t *s_fl_p = reinterpret_cast<uint32_t *>(lds + sizeof(double) * (SZ + 2 * 2 * kWave) + 32);
     if (t >= n_rows) return;  // whole block idle
     const int64_t i = rows ? (int64_t)rows[t] : t;
     if ((threadIdx.x >> 6) & 1)
         weights_cs_wave<KP, NFIX, MFIX, SAVE, 1>(x, y, n_nodes, nbr, k_stride, i, n_arg, m_arg, w,
                                                  status, sv_lu, sv_z, sv_s, sv_perm, sv_kmax,
-                                                 ok_code, sU, s_lm, s_pv, &s_fl);
+                                                 ok_code, sU, s_lm, s_pv, s_fl_p);
     else
         weights_cs_wave<KP, NFIX, MFIX, SAVE, 0>(x, y, n_nodes, nbr, k_stride, i, n_arg, m_arg, w,
                                                  status, sv_lu, sv_z, sv_s, sv_perm, sv_kmax,
-                                                 ok_code, sU, s_lm, s_pv, &s_fl);
+                                                 ok_code, sU, s_lm, s_pv, s_fl_p);
 }
 
 template <int KP, int NFIX, int MFIX, bool SAVE>
@@ -377,10 +386,11 @@ __attribute__((amdgpu_waves_per_eu(2))) void weights_cs_kernel(
     double *__restrict__ w, int32_t *__restrict__ status, double *__restrict__ sv_lu,
     double *__restrict__ sv_z, double *__restrict__ sv_s, uint8_t *__restrict__ sv_perm,
     int32_t sv_kmax, int32_t ok_code) {
+    __shared__ __align__(16) char lds[cs_lds_bytes<KP, MFIX>()];
     if (n_rows_dev) n_rows = *n_rows_dev;
     weights_cs_body<KP, NFIX, MFIX, SAVE>(x, y, n_nodes, nbr, k_stride, rows, n_rows, n_arg,
                                           m_arg, w, status, sv_lu, sv_z, sv_s, sv_perm,
-                                          sv_kmax, ok_code, (int64_t)blockIdx.x);
+                                          sv_kmax, ok_code, (int64_t)blockIdx.x, lds);
 }
 
 template <int KP, int NFIX, int MFIX>

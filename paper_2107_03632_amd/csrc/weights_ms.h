@@ -181,6 +181,14 @@ struct MsLds {
     static constexpr int SZ = ((USZ > ASZ ? USZ : ASZ) + 1) & ~1;
 };
 
+// LDS bytes of weights_ms_body for WPB wavefronts per block.
+template <int KP, int SEG, int MFIX, int WPB>
+__host__ __device__ constexpr int ms_lds_bytes() {
+    constexpr int MM = MFIX ? (MFIX + 1) * (MFIX + 2) / 2 : 28;
+    constexpr int GPB = kWave / SEG;
+    return (int)sizeof(double) * WPB * GPB * MsLds<KP, MM>::SZ + 4 * WPB * 2 * GPB;
+}
+
 // LDS ordering inside one wavefront: this wave's earlier LDS writes are
 // complete and visible to its later reads (no barrier with other waves).
 __device__ __forceinline__ void wave_sync() {
@@ -223,7 +231,7 @@ __device__ __forceinline__ void weights_ms_body(
     int64_t n_rows, int32_t n_arg, int32_t m_arg, double *__restrict__ w,
     int32_t *__restrict__ status, double *__restrict__ sv_lu, double *__restrict__ sv_z,
     double *__restrict__ sv_s, uint8_t *__restrict__ sv_perm, int32_t sv_kmax, int32_t ok_code,
-    int64_t grp, int wave) {
+    int64_t grp, int wave, char *lds) {
     static_assert(SEG * SL >= KP, "slots must cover the system");
     constexpr int GPB = kWave / SEG;
     constexpr int MM = MFIX ? (MFIX + 1) * (MFIX + 2) / 2 : 28;
@@ -233,8 +241,10 @@ __device__ __forceinline__ void weights_ms_body(
     const int NM = (m + 1) * (m + 2) / 2;
     const int K = n + NM;
 
-    __shared__ double s_lds[WPB][GPB][L::SZ];
-    __shared__ int32_t s_pos_b[WPB][2][GPB];  // position of the pivot row
+    // block LDS (ms_lds_bytes): [WPB][GPB][SZ] doubles, then the pivot
+    // positions [WPB][2][GPB]
+    auto s_lds = reinterpret_cast<double(*)[GPB][L::SZ]>(lds);
+    auto s_pos_b = reinterpret_cast<int32_t(*)[2][GPB]>(lds + sizeof(double) * WPB * GPB * L::SZ);
 
     const int lane = threadIdx.x & (kWave - 1);
     const int g = lane / SEG;
@@ -608,11 +618,12 @@ weights_ms_kernel(
     double *__restrict__ w, int32_t *__restrict__ status, double *__restrict__ sv_lu,
     double *__restrict__ sv_z, double *__restrict__ sv_s, uint8_t *__restrict__ sv_perm,
     int32_t sv_kmax, int32_t ok_code) {
+    __shared__ __align__(16) char lds[ms_lds_bytes<KP, SEG, MFIX, 1>()];
     if (n_rows_dev) n_rows = *n_rows_dev;
     weights_ms_body<KP, SEG, SL, NFIX, MFIX, 1, SAVE>(x, y, n_nodes, nbr, k_stride, rows, n_rows,
                                                       n_arg, m_arg, w, status, sv_lu, sv_z, sv_s,
                                                       sv_perm, sv_kmax, ok_code,
-                                                      (int64_t)blockIdx.x, 0);
+                                                      (int64_t)blockIdx.x, 0, lds);
 }
 
 template <int KP, int SEG, int SL, int NFIX, int MFIX, int OCC = 0>
