@@ -2,7 +2,7 @@
 // cell grid.
 //
 //   1. bounding box of the finite coordinates (two-pass reduction);
-//   2. square cells sized for ~k/2 nodes each, the cell count bounded by a
+//   2. square cells sized for ~k/3 nodes each, the cell count bounded by a
 //      host-known maximum so no host round trip is needed;
 //   3. counting sort of the nodes by cell (histogram, scan, scatter); the
 //      sorted copy of (x, y, id) is what the queries stream through;
@@ -32,8 +32,23 @@ struct GridParams {
     int32_t pad[2];
 };
 
+#ifndef RBFFD_KNN_CELL_NUM
+#define RBFFD_KNN_CELL_NUM 1
+#endif
+#ifndef RBFFD_KNN_CELL_DEN
+#define RBFFD_KNN_CELL_DEN 3
+#endif
+
+// Target nodes per cell: RBFFD_KNN_CELL_NUM / RBFFD_KNN_CELL_DEN of k.
+double per_cell(int32_t k) {
+    const double p = (double)k * RBFFD_KNN_CELL_NUM / RBFFD_KNN_CELL_DEN;
+    return p > 1.0 ? p : 1.0;
+}
+
+// Upper bound on the cell count: three times the target (room for a
+// bounding box larger than the node cloud; past it the cells grow)
 int64_t max_cells(int64_t n_nodes, int32_t k) {
-    const int64_t per = k / 2 > 1 ? k / 2 : 1;
+    const int64_t per = (int64_t)per_cell(k) > 1 ? (int64_t)per_cell(k) : 1;
     return 3 * ceil_div(n_nodes, per) + 2;
 }
 
@@ -67,17 +82,33 @@ __global__ __launch_bounds__(kThreads) void bbox_partial(const double *__restric
     if (threadIdx.x < 4) part[blockIdx.x * 4 + threadIdx.x] = sh[threadIdx.x][0];
 }
 
-__global__ __launch_bounds__(64) void grid_setup(const double *__restrict__ part, int n_parts,
-                                                 int64_t n, double per_cell, int64_t cell_cap,
-                                                 GridParams *__restrict__ gp) {
-    if (threadIdx.x != 0) return;
-    double xmn = DBL_MAX, xmx = -DBL_MAX, ymn = DBL_MAX, ymx = -DBL_MAX;
-    for (int b = 0; b < n_parts; ++b) {
-        xmn = fmin(xmn, part[4 * b + 0]);
-        xmx = fmax(xmx, part[4 * b + 1]);
-        ymn = fmin(ymn, part[4 * b + 2]);
-        ymx = fmax(ymx, part[4 * b + 3]);
+__global__ __launch_bounds__(kThreads) void grid_setup(const double *__restrict__ part,
+                                                       int n_parts, int64_t n, double per_cell,
+                                                       int64_t cell_cap,
+                                                       GridParams *__restrict__ gp) {
+    // min/max of the per-block boxes (exact, so the order does not matter)
+    double v[4] = {DBL_MAX, -DBL_MAX, DBL_MAX, -DBL_MAX};
+    for (int b = threadIdx.x; b < n_parts; b += kThreads) {
+        v[0] = fmin(v[0], part[4 * b + 0]);
+        v[1] = fmax(v[1], part[4 * b + 1]);
+        v[2] = fmin(v[2], part[4 * b + 2]);
+        v[3] = fmax(v[3], part[4 * b + 3]);
     }
+    __shared__ double sh[4][kThreads];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) sh[c][threadIdx.x] = v[c];
+    __syncthreads();
+    for (int o = kThreads / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            sh[0][threadIdx.x] = fmin(sh[0][threadIdx.x], sh[0][threadIdx.x + o]);
+            sh[1][threadIdx.x] = fmax(sh[1][threadIdx.x], sh[1][threadIdx.x + o]);
+            sh[2][threadIdx.x] = fmin(sh[2][threadIdx.x], sh[2][threadIdx.x + o]);
+            sh[3][threadIdx.x] = fmax(sh[3][threadIdx.x], sh[3][threadIdx.x + o]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    double xmn = sh[0][0], xmx = sh[1][0], ymn = sh[2][0], ymx = sh[3][0];
     if (!(xmn <= xmx)) xmn = xmx = 0.0;  // no finite node
     if (!(ymn <= ymx)) ymn = ymx = 0.0;
     const double wx = xmx - xmn, wy = ymx - ymn;
@@ -305,8 +336,8 @@ extern "C" int rbffd_knn(const double *x, const double *y, int64_t n_nodes, int3
                                                                        : kBBoxBlocks);
     int rc;
     hipLaunchKernelGGL(bbox_partial, dim3(parts), dim3(kThreads), 0, s, x, y, n_nodes, w.part);
-    hipLaunchKernelGGL(grid_setup, dim3(1), dim3(64), 0, s, (const double *)w.part, parts,
-                       n_nodes, (double)(k / 2 > 1 ? k / 2 : 1), cells, w.gp);
+    hipLaunchKernelGGL(grid_setup, dim3(1), dim3(kThreads), 0, s, (const double *)w.part, parts,
+                       n_nodes, per_cell(k), cells, w.gp);
     if ((rc = fill_i32(w.counts, 0, cells + 1, s)) != 0) return rc;
     if ((rc = fill_i32(w.fill, 0, cells + 1, s)) != 0) return rc;
     hipLaunchKernelGGL(cell_count, dim3(nb), dim3(kThreads), 0, s, x, y, n_nodes,
