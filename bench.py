@@ -81,6 +81,26 @@ def read_traffic(kernel_tag: str):
         return None
 
 
+def measured_fma_peak(torch, dev, dtype: int, blocks: int = 8192, iters: int = 4096):
+    """TFLOP/s of a plain vector FMA loop on this device (dtype 0 FP64, 1 FP32),
+    from the calibration library built beside librbffd."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2107_03632_amd", "libcalib.so"))
+    lib.calib_fma_loop.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p,
+                                   ctypes.c_int32, ctypes.c_void_p]
+    sink = torch.empty(blocks * 256, dtype=torch.float64 if dtype == 0 else torch.float32,
+                       device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def run():
+        rc = lib.calib_fma_loop(dtype, iters, ctypes.c_void_p(sink.data_ptr()), blocks,
+                                ctypes.c_void_p(stream.cuda_stream))
+        if rc != 0:
+            raise RuntimeError(f"calib_fma_loop failed: {rc}")
+    ms = timed(torch, stream, run, reps=3)
+    return blocks * 256 * iters * 8 * 2 / (ms * 1e-3) / 1e12
+
+
 def cpu_baseline(ns, m, n, stride):
     """The oracle, single-threaded, on every stride-th node: brute-force kNN,
     weights, CSR rows and SpMV rows for those stencils."""
@@ -184,6 +204,8 @@ def main():
     flops_launch = weights_flops(m, n) * N
     achieved = flops_launch / (w_ms_avg * 1e-3) / 1e12
     traffic = read_traffic("weights_k45_disk100k")
+    fma64 = measured_fma_peak(torch, dev, 0)
+    fma32 = measured_fma_peak(torch, dev, 1)
     out = {
         "metric": "RBF-FD Laplacian stencils/s (kNN + FP64 weights + CSR + residual), "
                   "unit disk ~100k nodes, m=4, n=30",
@@ -204,7 +226,9 @@ def main():
         "roofline": {"bound": "alu", "kernel": WEIGHTS_KERNEL,
                      "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
-                     "flops_per_stencil": weights_flops(m, n), "launch_ms": w_ms_avg},
+                     "flops_per_stencil": weights_flops(m, n), "launch_ms": w_ms_avg,
+                     "measured_fp64_fma_tflops": fma64, "frac_of_measured": achieved / fma64,
+                     "measured_fp32_fma_tflops": fma32},
         "weights_stencils_per_s": N / (w_ms_avg * 1e-3),
         "failed_stencils": bad,
         "residual_max_interior": resid,
@@ -212,6 +236,7 @@ def main():
 
     if not args.no_extras:
         out["per_order_1M_square"] = extras_per_order(torch, rb, nodes, dev, stream)
+        out["adjoint_annulus_200k_m4"] = extras_adjoint(torch, rb, nodes, dev, stream)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(ns, m, n, args.cpu_stride)
@@ -273,7 +298,15 @@ def extras_per_order(torch, rb, nodes, dev, stream):
     ms_mx = timed(torch, stream, lambda: rb.rbffd_weights(X, Y, nbr, order=O, precision=rb.MIXED))
     counts = {mm: int((ns.order == mm).sum()) for mm in (2, 4, 6)}
     fl = sum(counts[mm] * weights_flops(mm, nn) for mm, nn in ((2, 12), (4, 30), (6, 56)))
+    # baselines for the one-launch batch: the same stencils as three
+    # single-order launches (from the uniform 1M runs above), and every
+    # stencil padded to the order-6 system (the uniform m = 6 run)
+    per_order = sum(counts[mm] / N * res[f"m{mm}_n{nn}"]["fp64"]["ms"]
+                    for mm, nn in ((2, 12), (4, 30), (6, 56)))
+    padded = res["m6_n56"]["fp64"]["ms"]
     res["mixed_order"] = {"fp64": {"stencils_per_s": N / (ms * 1e-3), "ms": ms,
+                                   "speedup_vs_padded_k84": padded / ms,
+                                   "speedup_vs_single_order_launches": per_order / ms,
                                    "frac_fp64_peak": fl / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
                                    "graph_replay_ms": ms_graph,
                                    "graph_stencils_per_s": N / (ms_graph * 1e-3)},
@@ -295,6 +328,25 @@ def extras_per_order(torch, rb, nodes, dev, stream):
                             "fell_back": int((stmx == rb.FELL_BACK_FP64).sum().item()),
                             "max_rel_err_mixed_vs_fp64": err}
     return res
+
+
+def extras_adjoint(torch, rb, nodes, dev, stream):
+    """Forward with saved factors, and the adjoint, on the 200k-node annulus
+    (m = 4, n = 30), cotangent G ~ N(0, 1)."""
+    ns = nodes.workload("annulus_200k_m4")
+    X = torch.as_tensor(ns.x, device=dev)
+    Y = torch.as_tensor(ns.y, device=dev)
+    nbr = rb.rbffd_knn(X, Y, 30)
+    G = torch.as_tensor(nodes.gaussian_cotangent(ns.n_nodes, 30, seed=55), device=dev)
+    N = ns.n_nodes
+    plain = timed(torch, stream, lambda: rb.rbffd_weights(X, Y, nbr, m=4, n=30))
+    fwd = timed(torch, stream, lambda: rb.rbffd_weights(X, Y, nbr, m=4, n=30, save=True))
+    _, st, sv = rb.rbffd_weights(X, Y, nbr, m=4, n=30, save=True)
+    bwd = timed(torch, stream,
+                lambda: rb.rbffd_weights_backward(X, Y, nbr, G, sv, status=st, m=4, n=30))
+    return {"n_nodes": N, "forward_ms": plain, "forward_saving_factors_ms": fwd,
+            "backward_ms": bwd, "backward_stencils_per_s": N / (bwd * 1e-3),
+            "save_bytes": int(sv.numel())}
 
 
 def graph_timed(torch, fn, reps=3):

@@ -48,6 +48,18 @@ def _compile(src: str, force: bool) -> str:
     return obj
 
 
+CALIB_SRC = os.path.join(HERE, "calib", "fma_peak.hip")
+CALIB_LIB = os.path.join(HERE, "libcalib.so")
+
+
+def build_calib() -> str:
+    """The benchmark's FMA-rate calibration kernels (not part of librbffd)."""
+    tmp = CALIB_LIB + ".tmp%d" % os.getpid()
+    subprocess.run([HIPCC, *FLAGS, "-shared", CALIB_SRC, "-o", tmp], check=True)
+    os.replace(tmp, CALIB_LIB)
+    return CALIB_LIB
+
+
 def build(jobs: int = 16, force: bool = True) -> str:
     """Compile every source (force) or only the out-of-date ones, then link."""
     os.makedirs(BUILD, exist_ok=True)
@@ -59,6 +71,9 @@ def build(jobs: int = 16, force: bool = True) -> str:
     tmp = LIB + ".tmp%d" % os.getpid()
     subprocess.run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs], check=True)
     os.replace(tmp, LIB)
+    if force or not os.path.exists(CALIB_LIB) or \
+            os.path.getmtime(CALIB_LIB) < os.path.getmtime(CALIB_SRC):
+        build_calib()
     return LIB
 
 
