@@ -72,6 +72,8 @@ def _load():
                                            P, P, P]
             lib.oracle_csr.argtypes = [I64, P, I32, P, I32, P, P, P, P, P, P]
             lib.oracle_spmv.argtypes = [I64, P, P, P, P, P, P]
+            lib.oracle_time_steps.argtypes = [I64, P, I32, I32, P, P, P, ctypes.c_double,
+                                              I64, P]
             _lib = lib
     return _lib
 
@@ -229,3 +231,17 @@ def spmv(row_ptr, col, val, u, f=None):
     y = np.empty(n)
     lib.oracle_spmv(n, _p(row_ptr), _p(col), _p(val), _p(u), _p(fz), _p(y))
     return y
+
+
+def time_steps(nbr, w, n: int, f, u0, dt: float, n_steps: int, is_boundary=None):
+    """n_steps of the explicit loop of eq. (3); returns the final u (copy)."""
+    lib = _load()
+    nbr, w, f = _i32(nbr), _f64(w), _f64(f)
+    N, ks = nbr.shape
+    u = _f64(u0).copy()
+    b = None if is_boundary is None else np.ascontiguousarray(is_boundary, dtype=np.uint8)
+    rc = lib.oracle_time_steps(N, _p(nbr), ks, int(n), _p(w), _p(b), _p(f), float(dt),
+                               int(n_steps), _p(u))
+    if rc != 0:
+        raise ValueError(f"oracle_time_steps: error {rc}")
+    return u

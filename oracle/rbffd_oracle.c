@@ -40,6 +40,7 @@
  *   oracle_csr        the discrete operator of eq. (1) as a CSR matrix, with the
  *                     Dirichlet rows of section IV replaced by identity rows.
  *   oracle_spmv       y = W u - f, a sequential row sum in CSR order.
+ *   oracle_time_steps the explicit pseudo-time loop of section IV, eq. (3).
  */
 
 #include <math.h>
@@ -789,5 +790,49 @@ int oracle_spmv(int64_t n_rows, const int64_t *row_ptr, const int32_t *col,
             acc = fma(val[e], u[col[e]], acc);
         y[i] = f ? acc - f[i] : acc;
     }
+    return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Explicit pseudo-time loop (section IV, eq. (3))                         */
+/* ---------------------------------------------------------------------- */
+
+/* n_steps steps of u_2 = u_1 + dt (f + lap u_1) at the interior nodes, the
+ * Laplacian being the stencil sum over the first n supports of each row
+ * (fma over k ascending from 0); t = f + sum, then u_1 + dt * t.  Boundary
+ * nodes (is_boundary[i] != 0, or none when NULL) keep their values.  A
+ * support index outside [0, n_nodes) makes the node's value NaN.  u holds
+ * the initial values and receives the final ones. */
+int oracle_time_steps(int64_t n_nodes, const int32_t *nbr, int32_t k_stride, int32_t n,
+                      const double *w, const uint8_t *is_boundary, const double *f, double dt,
+                      int64_t n_steps, double *u)
+{
+    if (n_nodes < 1 || n < 1 || k_stride < n || n_steps < 0)
+        return OR_EARG;
+    double *next = (double *)malloc(sizeof(double) * (size_t)n_nodes);
+    if (!next)
+        return OR_ENOMEM;
+    for (int64_t t = 0; t < n_steps; ++t) {
+        for (int64_t i = 0; i < n_nodes; ++i) {
+            if (is_boundary && is_boundary[i]) {
+                next[i] = u[i];
+                continue;
+            }
+            double lap = 0.0;
+            int bad = 0;
+            for (int k = 0; k < n; ++k) {
+                int32_t j = nbr[i * k_stride + k];
+                if (j < 0 || j >= n_nodes) {
+                    bad = 1;
+                    continue;
+                }
+                lap = fma(w[i * k_stride + k], u[j], lap);
+            }
+            double tt = f[i] + lap;
+            next[i] = bad ? NAN : u[i] + dt * tt;
+        }
+        memcpy(u, next, sizeof(double) * (size_t)n_nodes);
+    }
+    free(next);
     return 0;
 }
