@@ -190,6 +190,25 @@ int rbffd_assemble_csr(int64_t n_nodes, const int32_t *nbr, int32_t k_stride,
                        void *workspace, size_t workspace_bytes, void *stream);
 
 /* ==========================================================================
+ * The explicit pseudo-time loop of section IV, eq. (3), n_steps times:
+ *   u(x_i) <- u(x_i) + dt (f(x_i) + sum_{k < n} w[i][k] u(x_nbr[i][k]))
+ * for interior nodes (is_boundary[i] == 0); Dirichlet nodes
+ * (is_boundary[i] != 0) keep their values.  is_boundary may be NULL (no
+ * boundary).  The sum runs with fma over k ascending from 0, then
+ * t = f + sum and u + dt * t (two roundings).  Supports and weights are the
+ * ELL rows of rbffd_knn / rbffd_weights: nbr, w [n_nodes][k_stride], the
+ * first n entries of each row used.  u [n_nodes] holds the initial values
+ * (boundary values included) and receives the values after the last step;
+ * u_work [n_nodes] is caller-owned scratch (must differ from u).  A support
+ * index outside [0, n_nodes) turns the node's value into NaN.
+ * Errors: RBFFD_ERR_ARG for null pointers, n < 1, k_stride < n,
+ * n_steps < 0 or dt NaN.  n_steps = 0 leaves u unchanged.
+ * ======================================================================== */
+int rbffd_time_steps(int64_t n_nodes, const int32_t *nbr, int32_t k_stride, int32_t n,
+                     const double *w, const uint8_t *is_boundary, const double *f, double dt,
+                     int64_t n_steps, double *u, double *u_work, void *stream);
+
+/* ==========================================================================
  * y = W u - f for a CSR matrix (the operator product of eq. (3)); f may be
  * NULL (then y = W u).  Each row is summed in CSR order with fma, starting
  * from 0.  The operator is square: row_ptr [n_rows+1] int64, col int32,

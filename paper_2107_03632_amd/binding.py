@@ -55,6 +55,8 @@ def _load():
             "rbffd_assemble_csr": ([I64, P, I32, P, I32, P, P, P, P, P, P, I64, P, SZ, P],
                                    ctypes.c_int),
             "rbffd_spmv": ([I64, P, P, P, P, P, P, P], ctypes.c_int),
+            "rbffd_time_steps": ([I64, P, I32, I32, P, P, P, ctypes.c_double, I64, P, P, P],
+                                 ctypes.c_int),
             "rbffd_batch_tuning_set": ([P], ctypes.c_int),
             "rbffd_batch_tuning_get": ([P], ctypes.c_int),
         }
@@ -261,6 +263,26 @@ def rbffd_spmv(row_ptr, col, val, u, f=None, out=None):
     _check(lib.rbffd_spmv(n, _p(row_ptr), _p(col), _p(val), _p(u), _p(fz), _p(y),
                           _stream(u.device)), "rbffd_spmv")
     return y
+
+
+def rbffd_time_steps(nbr, w, n: int, f, u, dt: float, n_steps: int, is_boundary=None,
+                     u_work=None):
+    """n_steps of the explicit pseudo-time loop of eq. (3), in place on u:
+    u <- u + dt (f + sum_k w u[nbr]) at interior nodes.  Returns u."""
+    lib = _load()
+    nbr = _dev(nbr, torch.int32, "nbr")
+    w = _dev(w, torch.float64, "w")
+    f = _dev(f, torch.float64, "f")
+    if not isinstance(u, torch.Tensor) or not u.is_cuda or u.dtype != torch.float64 \
+            or not u.is_contiguous():
+        raise TypeError("u must be a contiguous FP64 GPU tensor (updated in place)")
+    N, ks = nbr.shape
+    b = None if is_boundary is None else _dev(is_boundary, torch.uint8, "is_boundary")
+    work = u_work if u_work is not None else torch.empty_like(u)
+    _check(lib.rbffd_time_steps(N, _p(nbr), ks, int(n), _p(w), _p(b), _p(f), float(dt),
+                                int(n_steps), _p(u), _p(work), _stream(u.device)),
+           "rbffd_time_steps")
+    return u
 
 
 class _WeightsFn(torch.autograd.Function):
