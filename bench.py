@@ -237,6 +237,7 @@ def main():
     if not args.no_extras:
         out["per_order_1M_square"] = extras_per_order(torch, rb, nodes, dev, stream)
         out["adjoint_annulus_200k_m4"] = extras_adjoint(torch, rb, nodes, dev, stream)
+        out["time_loop_unit_disk"] = extras_time_loop(torch, rb, nodes, dev, stream)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(ns, m, n, args.cpu_stride)
@@ -347,6 +348,43 @@ def extras_adjoint(torch, rb, nodes, dev, stream):
     return {"n_nodes": N, "forward_ms": plain, "forward_saving_factors_ms": fwd,
             "backward_ms": bwd, "backward_stencils_per_s": N / (bwd * 1e-3),
             "save_bytes": int(sv.numel())}
+
+
+def extras_time_loop(torch, rb, nodes, dev, stream, steps=200, dt=1e-6):
+    """The paper's explicit loop (eq. (3)) on unit disks: ms per step and the
+    bandwidth of the paper's per-node data model, 8 (4 + n) + 4 (1 + n) bytes
+    (weights, values, f and indices), at several N (cache regimes of the
+    MI355X: 4 MB L2 per XCD, 256 MB Infinity Cache, 8 TB/s HBM)."""
+    res = []
+    for n_target, n_bnd, m, n in ((10_000, 300, 2, 12), (100_000, 1000, 2, 12),
+                                  (100_000, 1000, 4, 30), (1_000_000, 3000, 2, 12)):
+        ns = nodes.unit_disk(n_target, n_bnd, seed=2)
+        X = torch.as_tensor(ns.x, device=dev)
+        Y = torch.as_tensor(ns.y, device=dev)
+        nbr = rb.rbffd_knn(X, Y, n)
+        w, st, _ = rb.rbffd_weights(X, Y, nbr, m=m, n=n)
+        u_exact, F = nodes.manufactured(ns.x, ns.y)
+        f = torch.as_tensor(-F, device=dev)
+        B = torch.as_tensor(ns.is_boundary, device=dev)
+        u = torch.as_tensor(np.where(ns.is_boundary != 0, u_exact, 0.0), device=dev)
+        work = torch.empty_like(u)
+        ws = torch.empty(ns.n_nodes * n * 12 + 1024, dtype=torch.uint8, device=dev)
+        ms = timed(torch, stream, lambda: rb.rbffd_time_steps(nbr, w, n, f, u, dt, steps,
+                                                              is_boundary=B, u_work=work,
+                                                              workspace=ws))
+        per = ms / steps
+        nbytes = ns.n_nodes * (8 * (4 + n) + 4 * (1 + n))
+        row = {"n_nodes": ns.n_nodes, "m": m, "n": n, "steps": steps,
+               "ms_per_step": per, "node_updates_per_s": ns.n_nodes / (per * 1e-3),
+               "model_bytes_per_step": nbytes, "gb_per_s": nbytes / (per * 1e-3) / 1e9,
+               "frac_hbm_8tbs": nbytes / (per * 1e-3) / 8e12}
+        if n_target == 10_000:
+            gms = graph_timed(torch, lambda: rb.rbffd_time_steps(nbr, w, n, f, u, dt, 100,
+                                                                 is_boundary=B, u_work=work,
+                                                                 workspace=ws))
+            row["graph_100_steps_ms_per_step"] = gms / 100
+        res.append(row)
+    return res
 
 
 def graph_timed(torch, fn, reps=3):

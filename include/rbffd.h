@@ -199,14 +199,18 @@ int rbffd_assemble_csr(int64_t n_nodes, const int32_t *nbr, int32_t k_stride,
  * ELL rows of rbffd_knn / rbffd_weights: nbr, w [n_nodes][k_stride], the
  * first n entries of each row used.  u [n_nodes] holds the initial values
  * (boundary values included) and receives the values after the last step;
- * u_work [n_nodes] is caller-owned scratch (must differ from u).  A support
+ * u_work [n_nodes] is caller-owned scratch (must differ from u).  The
+ * workspace (size from rbffd_time_steps_workspace_size) receives a k-major
+ * copy of the first n columns of nbr and w, made once per call.  A support
  * index outside [0, n_nodes) turns the node's value into NaN.
  * Errors: RBFFD_ERR_ARG for null pointers, n < 1, k_stride < n,
- * n_steps < 0 or dt NaN.  n_steps = 0 leaves u unchanged.
+ * n_steps < 0, dt NaN or a short workspace.  n_steps = 0 leaves u unchanged.
  * ======================================================================== */
+int rbffd_time_steps_workspace_size(int64_t n_nodes, int32_t n, size_t *bytes /* host */);
 int rbffd_time_steps(int64_t n_nodes, const int32_t *nbr, int32_t k_stride, int32_t n,
                      const double *w, const uint8_t *is_boundary, const double *f, double dt,
-                     int64_t n_steps, double *u, double *u_work, void *stream);
+                     int64_t n_steps, double *u, double *u_work, void *workspace,
+                     size_t workspace_bytes, void *stream);
 
 /* ==========================================================================
  * y = W u - f for a CSR matrix (the operator product of eq. (3)); f may be

@@ -55,8 +55,9 @@ def _load():
             "rbffd_assemble_csr": ([I64, P, I32, P, I32, P, P, P, P, P, P, I64, P, SZ, P],
                                    ctypes.c_int),
             "rbffd_spmv": ([I64, P, P, P, P, P, P, P], ctypes.c_int),
-            "rbffd_time_steps": ([I64, P, I32, I32, P, P, P, ctypes.c_double, I64, P, P, P],
-                                 ctypes.c_int),
+            "rbffd_time_steps_workspace_size": ([I64, I32, PSZ], ctypes.c_int),
+            "rbffd_time_steps": ([I64, P, I32, I32, P, P, P, ctypes.c_double, I64, P, P, P, SZ,
+                                  P], ctypes.c_int),
             "rbffd_batch_tuning_set": ([P], ctypes.c_int),
             "rbffd_batch_tuning_get": ([P], ctypes.c_int),
         }
@@ -266,7 +267,7 @@ def rbffd_spmv(row_ptr, col, val, u, f=None, out=None):
 
 
 def rbffd_time_steps(nbr, w, n: int, f, u, dt: float, n_steps: int, is_boundary=None,
-                     u_work=None):
+                     u_work=None, workspace=None):
     """n_steps of the explicit pseudo-time loop of eq. (3), in place on u:
     u <- u + dt (f + sum_k w u[nbr]) at interior nodes.  Returns u."""
     lib = _load()
@@ -279,9 +280,11 @@ def rbffd_time_steps(nbr, w, n: int, f, u, dt: float, n_steps: int, is_boundary=
     N, ks = nbr.shape
     b = None if is_boundary is None else _dev(is_boundary, torch.uint8, "is_boundary")
     work = u_work if u_work is not None else torch.empty_like(u)
+    ws = workspace if workspace is not None else \
+        _workspace(_size(lib.rbffd_time_steps_workspace_size, N, max(int(n), 1)), u.device)
     _check(lib.rbffd_time_steps(N, _p(nbr), ks, int(n), _p(w), _p(b), _p(f), float(dt),
-                                int(n_steps), _p(u), _p(work), _stream(u.device)),
-           "rbffd_time_steps")
+                                int(n_steps), _p(u), _p(work), _p(ws), ws.numel(),
+                                _stream(u.device)), "rbffd_time_steps")
     return u
 
 

@@ -1,10 +1,12 @@
 // The explicit pseudo-time loop of section IV, eq. (3):
 //   u_2(x_i) = u_1(x_i) + dt (f(x_i) + lap u_1(x_i)),  lap u_1(x_i) = sum_k w_ik u_1(x_nbr_ik),
-// for interior nodes; Dirichlet nodes keep their values.  One launch per
-// step, one thread per node: each thread streams its row of supports and
-// weights (rows are contiguous, so a wavefront's 64 rows form one
-// contiguous span) and gathers the neighbours' values, which the spatial
-// order of the nodes keeps in cache.  The two buffers swap roles each step.
+// for interior nodes; Dirichlet nodes keep their values.
+// Once per call the first n columns of the supports and weights are copied
+// to k-major order (workspace), so that every step's loads are coalesced:
+// thread i reads entry k of row i at k * N + i.  One launch per step, one
+// thread per node summing its row with fma in k order; the neighbours'
+// values are gathered (the spatial order of the nodes keeps them in cache).
+// The two value buffers swap roles each step.
 
 #include "common.h"
 
@@ -13,9 +15,21 @@ namespace {
 
 constexpr int kTL = 256;
 
-__global__ __launch_bounds__(kTL) void explicit_step(int64_t n, const int32_t *__restrict__ nbr,
+// k-major copies: nbrT[k * n + i] = nbr[i][k], wT likewise, k < nk
+__global__ __launch_bounds__(kTL) void ell_to_kmajor(int64_t n, const int32_t *__restrict__ nbr,
                                                       int32_t k_stride, int32_t nk,
                                                       const double *__restrict__ w,
+                                                      int32_t *__restrict__ nbrT,
+                                                      double *__restrict__ wT) {
+    const int64_t e = (int64_t)blockIdx.x * kTL + threadIdx.x;  // destination index
+    if (e >= n * nk) return;
+    const int64_t k = e / n, i = e - k * n;
+    nbrT[e] = nbr[i * (int64_t)k_stride + k];
+    wT[e] = w[i * (int64_t)k_stride + k];
+}
+
+__global__ __launch_bounds__(kTL) void explicit_step(int64_t n, const int32_t *__restrict__ nbrT,
+                                                      int32_t nk, const double *__restrict__ wT,
                                                       const uint8_t *__restrict__ is_boundary,
                                                       const double *__restrict__ f, double dt,
                                                       const double *__restrict__ src,
@@ -27,15 +41,13 @@ __global__ __launch_bounds__(kTL) void explicit_step(int64_t n, const int32_t *_
         dst[i] = ui;
         return;
     }
-    const int32_t *ni = nbr + i * (int64_t)k_stride;
-    const double *wi = w + i * (int64_t)k_stride;
     double lap = 0.0;
     bool bad = false;
     for (int k = 0; k < nk; ++k) {
-        const int32_t j = ni[k];
+        const int32_t j = nbrT[k * n + i];
         const bool ok = j >= 0 && (int64_t)j < n;
         bad = bad || !ok;
-        lap = fma(wi[k], src[ok ? j : 0], lap);
+        lap = fma(wT[k * n + i], src[ok ? j : 0], lap);
     }
     const double t = f[i] + lap;
     dst[i] = bad ? __builtin_nan("") : ui + dt * t;
@@ -52,21 +64,49 @@ __global__ __launch_bounds__(kTL) void copy_f64(int64_t n, const double *__restr
 
 using namespace rbffd;
 
+namespace {
+struct TlWs {
+    int32_t *nbrT;
+    double *wT;
+    size_t bytes;
+};
+TlWs carve_tl(void *base, int64_t n_nodes, int32_t n) {
+    Carver c(base);
+    TlWs ws;
+    ws.nbrT = c.take<int32_t>((size_t)n_nodes * n);
+    ws.wT = c.take<double>((size_t)n_nodes * n);
+    ws.bytes = c.bytes();
+    return ws;
+}
+}  // namespace
+
+extern "C" int rbffd_time_steps_workspace_size(int64_t n_nodes, int32_t n, size_t *bytes) {
+    if (!bytes || n_nodes < 1 || n < 1) return RBFFD_ERR_ARG;
+    *bytes = carve_tl(nullptr, n_nodes, n).bytes;
+    return RBFFD_SUCCESS;
+}
+
 extern "C" int rbffd_time_steps(int64_t n_nodes, const int32_t *nbr, int32_t k_stride, int32_t n,
                                 const double *w, const uint8_t *is_boundary, const double *f,
                                 double dt, int64_t n_steps, double *u, double *u_work,
-                                void *stream) {
+                                void *workspace, size_t workspace_bytes, void *stream) {
     if (n_nodes < 1 || !nbr || !w || !f || !u || !u_work || n < 1 || k_stride < n ||
-        n_steps < 0 || !(dt == dt) || u == u_work)
+        n_steps < 0 || !(dt == dt) || u == u_work || !workspace)
         return RBFFD_ERR_ARG;
+    const TlWs ws = carve_tl(workspace, n_nodes, n);
+    if (workspace_bytes < ws.bytes) return RBFFD_ERR_ARG;
     if (n_steps == 0) return RBFFD_SUCCESS;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const int64_t blocks = ceil_div(n_nodes, kTL);
-    if (blocks > 0x7fffffff) return RBFFD_ERR_UNSUPPORTED;
+    const int64_t tblocks = ceil_div(n_nodes * n, kTL);
+    if (tblocks > 0x7fffffff) return RBFFD_ERR_UNSUPPORTED;
+    hipLaunchKernelGGL(ell_to_kmajor, dim3((unsigned)tblocks), dim3(kTL), 0, s, n_nodes, nbr,
+                       k_stride, n, w, ws.nbrT, ws.wT);
     double *a = u, *b = u_work;
     for (int64_t t = 0; t < n_steps; ++t) {
-        hipLaunchKernelGGL(explicit_step, dim3((unsigned)blocks), dim3(kTL), 0, s, n_nodes, nbr,
-                           k_stride, n, w, is_boundary, f, dt, (const double *)a, b);
+        hipLaunchKernelGGL(explicit_step, dim3((unsigned)blocks), dim3(kTL), 0, s, n_nodes,
+                           (const int32_t *)ws.nbrT, n, (const double *)ws.wT, is_boundary, f,
+                           dt, (const double *)a, b);
         double *c = a;
         a = b;
         b = c;

@@ -67,9 +67,9 @@ def test_argument_errors_before_any_launch(lib):
     lib.rbffd_knn.argtypes = [P, P, ctypes.c_int64, ctypes.c_int32, P, P, ctypes.c_size_t, P]
     assert lib.rbffd_knn(None, None, 10, 3, None, None, 0, None) == -1
     lib.rbffd_time_steps.argtypes = [ctypes.c_int64, P, ctypes.c_int32, ctypes.c_int32, P, P, P,
-                                     ctypes.c_double, ctypes.c_int64, P, P, P]
+                                     ctypes.c_double, ctypes.c_int64, P, P, P, ctypes.c_size_t, P]
     assert lib.rbffd_time_steps(10, None, 12, 12, None, None, None, 1e-3, 1, None, None,
-                                None) == -1
+                                None, 0, None) == -1
 
 
 def test_product_path_never_imports_the_oracle():
