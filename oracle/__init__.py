@@ -90,6 +90,14 @@ def _i32(a):
     return np.ascontiguousarray(a, dtype=np.int32)
 
 
+def _check_supports(x, y, nbr, k_stride=None):
+    """The C routines index nbr as [len(x)][k_stride]: refuse other shapes."""
+    if y.shape != x.shape or nbr.ndim != 2 or nbr.shape[0] != x.shape[0]:
+        raise ValueError(f"need x, y [N] and nbr [N, k]; got {x.shape}, {y.shape}, {nbr.shape}")
+    if k_stride is not None and k_stride != nbr.shape[1]:
+        raise ValueError(f"k_stride {k_stride} != nbr.shape[1] {nbr.shape[1]}")
+
+
 def n_monomials(m: int) -> int:
     return (m + 1) * (m + 2) // 2
 
@@ -148,6 +156,7 @@ def weights(x, y, nbr, m: int | None = None, n: int | None = None, order=None,
     Returns (w [rows, k_stride], status [rows])."""
     lib = _load()
     x, y, nbr = _f64(x), _f64(y), _i32(nbr)
+    _check_supports(x, y, nbr, k_stride)
     N = x.shape[0]
     ks = nbr.shape[1] if k_stride is None else k_stride
     nfm = _i32(n_for_m)
@@ -170,6 +179,7 @@ def weights_mixed(x, y, nbr, m: int | None = None, n: int | None = None, order=N
     refinement, FP64 fallback.  Returns (w, status, corrections)."""
     lib = _load()
     x, y, nbr = _f64(x), _f64(y), _i32(nbr)
+    _check_supports(x, y, nbr, k_stride)
     N = x.shape[0]
     ks = nbr.shape[1] if k_stride is None else k_stride
     o = None if order is None else np.ascontiguousarray(order, dtype=np.int8)
@@ -191,6 +201,9 @@ def adjoint(x, y, nbr, G, m: int | None = None, n: int | None = None, order=None
     """dL/dx, dL/dy of all nodes given G = dL/dw (reverse mode of weights)."""
     lib = _load()
     x, y, nbr, G = _f64(x), _f64(y), _i32(nbr), _f64(G)
+    _check_supports(x, y, nbr)
+    if G.shape != nbr.shape:
+        raise ValueError(f"G {G.shape} must have the shape of nbr {nbr.shape}")
     N = x.shape[0]
     gx = np.empty(N)
     gy = np.empty(N)

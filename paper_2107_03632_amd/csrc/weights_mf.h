@@ -1,0 +1,446 @@
+#pragma once
+// RBF-FD Laplacian stencil weights, FP64, K = 84 (m = 6, n = 56): LU blocked
+// by panels of four columns with the trailing updates on the matrix cores.
+//
+// v_mfma_f64_16x16x4f64 forms each output as four fused multiply-adds taken
+// in k order, fma(a3, b3, fma(a2, b2, fma(a1, b1, fma(a0, b0, c)))).  A
+// right-looking LU whose trailing update is L21 x (-U12) on those units
+// therefore applies to every element the fused updates of the unblocked
+// elimination, in the same order, and the weights are the same bits as
+// those of the other kernels (same shift, scale, assembly, pivot rule and
+// back substitution).
+//
+// Layout: the system padded to 96 x 96 (right-hand side in column 84; rows
+// and columns 85..95 zero; rows 84..95 never pivot), in 16 x 16 tiles held
+// transposed as MFMA accumulators: in tile (I, J), lane l = 16 g + j,
+// register r holds row 16 I + j, column 16 J + g + 4 r.  Wavefront w of the
+// block owns the tile columns J = w, w + 2, w + 4 (all six tile rows).
+//
+// The four columns of a panel [c0, c0 + 4) are then register (c0 % 16) / 4
+// of the tiles of column c0 / 16, column c0 + g in lane group g, so the
+// owner runs the panel's column steps on fixed registers:
+//   * pivot search over the 96 rows of group k (six rows per lane, then a
+//     16-lane reduction; the exact (|a|, position) key when the high words
+//     tie, positions kept in LDS);
+//   * the pivot row's four panel entries through LDS; the multipliers of
+//     group k through LDS to the other groups, which update their column;
+//   * each panel's multipliers end up in LDS in the B-operand layout.
+// At the panel's end (one block barrier) each wavefront forms, for its
+// trailing tile columns, the pivot rows' entries with the panel's own
+// corrections applied in order (U12, the A operand) and updates every tile
+// with one MFMA.  Rows of U go to the packed LDS triangle as they are
+// completed; wavefront 0 runs the back substitution from there.
+
+#include "weights_ms.h"
+
+namespace rbffd {
+namespace wk {
+
+typedef double mf_v4d __attribute__((ext_vector_type(4)));
+
+// LDS of one block: doubles first, then int32.
+struct MfLds {
+    static constexpr int KP = 84, MM = 28, NT = 6;
+    static constexpr int SZ = MsLds<KP, MM>::SZ;    // U triangle / assembly tables
+    static constexpr int B = SZ;                    // [2][NT][64] panel multipliers
+    static constexpr int PROW = B + 2 * NT * kWave;  // [4] pivot row, panel columns
+    static constexpr int UB = PROW + 4;             // [2 waves][4][16] pivot rows, one tile column
+    static constexpr int DBL = UB + 2 * 4 * 16;
+    static constexpr int REC = 0;                   // [2][4] pivot rows of a panel
+    static constexpr int POS = 8;                   // [96] position of each row
+    static constexpr int AT = POS + 96;             // [96] row at each position
+    static constexpr int FL = AT + 96;              // flags of wavefront 1
+    static constexpr int INTS = FL + 2;
+    static constexpr int BYTES = 8 * DBL + 4 * INTS;
+};
+
+template <int WV>
+__device__ __forceinline__ void weights_mf_wave(
+    const double *__restrict__ x, const double *__restrict__ y, int64_t n_nodes,
+    const int32_t *__restrict__ nbr, int32_t k_stride, int64_t i, double *__restrict__ w,
+    int32_t *__restrict__ status, int32_t ok_code, char *lds) {
+    constexpr int KP = 84, n = 56, K = 84, MM = 28, NT = 6, SL = 2;
+    using L = MsLds<KP, MM>;
+    using B = MfLds;
+    double *sU = reinterpret_cast<double *>(lds);
+    double *s_ux = sU;
+    double *s_uy = sU + KP;
+    double(*s_P)[MM] = reinterpret_cast<double(*)[MM]>(sU + 2 * KP);
+    double(*s_B)[NT][kWave] = reinterpret_cast<double(*)[NT][kWave]>(sU + B::B);
+    double *s_prow = sU + B::PROW;
+    double(*s_ub)[16] = reinterpret_cast<double(*)[16]>(sU + B::UB + WV * 64);
+    int32_t *si = reinterpret_cast<int32_t *>(lds + 8 * B::DBL);
+    int32_t(*s_rec)[4] = reinterpret_cast<int32_t(*)[4]>(si + B::REC);
+    int32_t *s_pos = si + B::POS;
+    int32_t *s_at = si + B::AT;
+    uint32_t *s_fl = reinterpret_cast<uint32_t *>(si + B::FL);
+
+    const int lane = threadIdx.x & (kWave - 1);
+    const int g = lane >> 4, jl = lane & 15;
+
+    // ---- shift and scale (row order: rows lane, lane + 64) -----------------
+    uint32_t flags = 0;
+    double dx[SL], dy[SL];
+    double d2m = 0.0;
+    const double xi = x[i], yi = y[i];
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+        const int r = lane + kWave * s;
+        dx[s] = 0.0;
+        dy[s] = 0.0;
+        if (r < n) {
+            const int32_t j = nbr[i * (int64_t)k_stride + r];
+            if (j < 0 || (int64_t)j >= n_nodes) {
+                flags |= F_BADIDX;
+            } else {
+                const double ddx = x[j] - xi, ddy = y[j] - yi;
+                if (!isfinite(ddx) || !isfinite(ddy)) {
+                    flags |= F_NONFIN;
+                } else {
+                    dx[s] = ddx;
+                    dy[s] = ddy;
+                    const double d2 = ddx * ddx + ddy * ddy;
+                    d2m = fmax(d2m, d2);
+                }
+            }
+        }
+    }
+    const double sc = sqrt(seg_all_max_d<kWave>(d2m, lane));
+    if (sc == 0.0) flags |= F_DUP;
+    if (WV == 0) {
+#pragma unroll
+        for (int s = 0; s < SL; ++s) {
+            const int r = lane + kWave * s;
+            if (r < n) {
+                const double ux = dx[s] / sc, uy = dy[s] / sc;
+                s_ux[r] = ux;
+                s_uy[r] = uy;
+                double px[7], py[7];
+                px[0] = 1.0;
+                py[0] = 1.0;
+#pragma unroll
+                for (int e = 1; e < 7; ++e) {
+                    px[e] = px[e - 1] * ux;
+                    py[e] = py[e - 1] * uy;
+                }
+#pragma unroll
+                for (int j = 0; j < MM; ++j) s_P[r][j] = px[mono_a(j)] * py[mono_b(j)];
+            }
+        }
+    } else {
+        for (int r = lane; r < 96; r += kWave) {
+            s_pos[r] = r;
+            s_at[r] = r;
+        }
+    }
+    __syncthreads();
+
+    // ---- assembly of this wavefront's tile columns (transposed tiles) ------
+    mf_v4d T[NT][3];
+#pragma unroll
+    for (int I = 0; I < NT; ++I) {
+        const int R = 16 * I + jl;
+        const bool prow = R < n;
+        const bool qrow = R >= n && R < K;
+        const int jr = qrow ? R - n : 0;
+        const double uxr = (16 * I < n && prow) ? s_ux[R] : 0.0;
+        const double uyr = (16 * I < n && prow) ? s_uy[R] : 0.0;
+#pragma unroll
+        for (int jt = 0; jt < 3; ++jt) {
+            const int J = 2 * jt + WV;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int C = 16 * J + g + 4 * r;
+                double v = 0.0;
+                if (16 * J < n && C < n) {
+                    double phs = 0.0;
+                    if (16 * I < n) {
+                        const double ex = uxr - s_ux[C];
+                        const double ey = uyr - s_uy[C];
+                        const double rr = ex * ex + ey * ey;
+                        if (prow && C != R && rr == 0.0) flags |= F_DUP;
+                        asm volatile("" : "+v"(flags));
+                        phs = rr * sqrt(rr);
+                    }
+                    const double pt = s_P[C][jr];
+                    v = prow ? phs : (qrow ? pt : 0.0);
+                } else if (16 * J + 15 >= n && 16 * J < K && C >= n && C < K) {
+                    v = prow ? s_P[prow ? R : 0][C - n] : 0.0;
+                } else if (16 * J + 15 >= KP && 16 * J <= KP && C == KP) {
+                    const double r0 = uxr * uxr + uyr * uyr;
+                    const double rb = 9.0 * sqrt(r0);
+                    v = prow ? rb : ((qrow && (jr == 3 || jr == 5)) ? 2.0 : 0.0);
+                }
+                T[I][jt][r] = v;
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    asm volatile("" : "+v"(flags));
+    __syncthreads();  // the assembly tables' space becomes the rows of U
+
+    // ---- LU, panels of four columns ----------------------------------------
+    uint32_t dmask = 0;  // bit I: row 16 I + jl pivoted already (or padding)
+#pragma unroll
+    for (int I = 0; I < NT; ++I)
+        if (16 * I + jl >= KP) dmask |= 1u << I;
+
+#pragma unroll
+    for (int c0 = 0; c0 < KP; c0 += 4) {
+        const int pb = (c0 >> 2) & 1;
+        const int J0 = c0 >> 4;         // tile column of the panel
+        const int rc = (c0 & 15) >> 2;  // its register
+        if ((J0 & 1) == WV) {
+            const int jt0 = J0 >> 1;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int c = c0 + k;
+                // pivot search over the rows of group k: high words first
+                uint32_t bh = 0;
+                int bI = 0;
+                bool dup = false;
+#pragma unroll
+                for (int I = 0; I < NT; ++I) {
+                    const uint64_t bits =
+                        (uint64_t)__double_as_longlong(T[I][jt0][rc]) & 0x7fffffffffffffffull;
+                    const uint32_t hi = (uint32_t)(bits >> 32) + 1u;
+                    const bool act = ((dmask >> I) & 1u) == 0u;
+                    const bool gt = act && hi > bh;
+                    const bool eq = act && hi == bh;
+                    dup = gt ? false : (dup || eq);
+                    bI = gt ? I : bI;
+                    bh = gt ? hi : bh;
+                }
+                const uint32_t mh = seg_all<16, OpMax>(bh, lane);
+                const uint64_t gmask = 0xffffull << (16 * k);
+                const uint64_t chunk = __ballot(bh == mh) & gmask;
+                const int wl0 = __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)chunk) - 1);
+                const bool dupw = __builtin_amdgcn_readlane(dup ? 1 : 0, wl0) != 0;
+                int win, wI;
+                if (__builtin_expect((chunk & (chunk - 1ull)) != 0ull || dupw, 0)) {
+                    // full key (|a| bits, position)
+                    uint32_t kh = 0, kl = 0;
+                    int kpp = 0x7fffffff, kI = 0;
+#pragma unroll
+                    for (int I = 0; I < NT; ++I) {
+                        const uint64_t bits =
+                            (uint64_t)__double_as_longlong(T[I][jt0][rc]) & 0x7fffffffffffffffull;
+                        const bool act = ((dmask >> I) & 1u) == 0u;
+                        const uint32_t h = act ? (uint32_t)(bits >> 32) + 1u : 0u;
+                        const uint32_t l = act ? (uint32_t)bits : 0u;
+                        const int p = act ? s_pos[16 * I + jl] : 0x7fffffff;
+                        if (key_better(h, l, p, kh, kl, kpp)) {
+                            kh = h;
+                            kl = l;
+                            kpp = p;
+                            kI = I;
+                        }
+                    }
+                    uint32_t gh = kh, gl = kl;
+                    int gp = kpp;
+                    seg_argmax_full<16>(gh, gl, gp);
+                    const uint64_t ch2 = __ballot(kpp == gp && kh != 0u) & gmask;
+                    win = __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)ch2) - 1);
+                    wI = __builtin_amdgcn_readlane(kI, win);
+                } else {
+                    win = wl0;
+                    wI = __builtin_amdgcn_readlane(bI, win);
+                }
+                const int ip = win & 15;
+                const int Ip = wI;
+                const int prow_id = 16 * Ip + ip;
+                // the pivot row's entries in the panel columns; row c of U
+                if (jl == ip) {
+                    double pv = 0.0;
+#pragma unroll
+                    for (int I = 0; I < NT; ++I)
+                        if (I == Ip) pv = T[I][jt0][rc];
+                    s_prow[g] = pv;
+                    if (g >= k) sU[L::ubase(c) + 2 * (c0 + g)] = pv;
+                }
+                if (jl == ip) dmask |= 1u << Ip;
+                wave_sync();
+                const double u = s_prow[g];  // in group k: the pivot
+                const double inv = 1.0 / u;
+                if (g == k) {
+#pragma unroll
+                    for (int I = 0; I < NT; ++I) {
+                        const bool act = ((dmask >> I) & 1u) == 0u;
+                        s_B[pb][I][lane] = act ? T[I][jt0][rc] * inv : 0.0;
+                    }
+                }
+                if (lane == 0) {
+                    const int kp = s_pos[prow_id];
+                    const int q = s_at[c];
+                    s_pos[q] = kp;
+                    s_at[kp] = q;
+                    s_pos[prow_id] = c;
+                    s_at[c] = prow_id;
+                    s_rec[pb][k] = prow_id;
+                }
+                wave_sync();
+                if (k < 3) {
+                    double lb[NT];
+#pragma unroll
+                    for (int I = 0; I < NT; ++I) lb[I] = s_B[pb][I][16 * k + jl];
+                    if (g > k) {
+#pragma unroll
+                        for (int I = 0; I < NT; ++I)
+                            T[I][jt0][rc] = fma(-lb[I], u, T[I][jt0][rc]);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+
+        // ---- panel end: trailing tile columns of this wavefront ------------
+        int pr[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) pr[k] = __builtin_amdgcn_readfirstlane(s_rec[pb][k]);
+        if ((J0 & 1) != WV) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (jl == (pr[k] & 15)) dmask |= 1u << (pr[k] >> 4);
+        }
+        // first tile column of this wavefront that still has trailing columns
+        const int first_jt = ((J0 & 1) == WV) ? ((rc < 3) ? (J0 >> 1) : (J0 >> 1) + 1)
+                                              : ((J0 + 1) >> 1);
+        if (first_jt < 3) {
+            // multipliers of the panel's pivot rows in its earlier columns
+            double l11[4][3];
+#pragma unroll
+            for (int m2 = 1; m2 < 4; ++m2)
+#pragma unroll
+                for (int k2 = 0; k2 < m2; ++k2)
+                    l11[m2][k2] = s_B[pb][pr[m2] >> 4][16 * k2 + (pr[m2] & 15)];
+            double Bop[NT];
+#pragma unroll
+            for (int I = 0; I < NT; ++I) Bop[I] = s_B[pb][I][lane];
+#pragma unroll
+            for (int jt = 0; jt < 3; ++jt) {
+                if (jt < first_jt) continue;
+                const int J = 2 * jt + WV;
+                const int i0 = (J == J0) ? 4 * rc + 4 : 0;  // first trailing column in the tile
+                // the pivot rows' entries in tile column J
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int Ipk = pr[k] >> 4, ipk = pr[k] & 15;
+                    if (jl == ipk) {
+#pragma unroll
+                        for (int I = 0; I < NT; ++I) {
+                            if (I == Ipk) {
+#pragma unroll
+                                for (int r = 0; r < 4; ++r) s_ub[k][g + 4 * r] = T[I][jt][r];
+                            }
+                        }
+                    }
+                }
+                wave_sync();
+                const double r0 = s_ub[0][jl], r1 = s_ub[1][jl];
+                const double r2 = s_ub[2][jl], r3 = s_ub[3][jl];
+                const double u0 = r0;
+                const double u1 = fma(-l11[1][0], u0, r1);
+                const double u2 = fma(-l11[2][1], u1, fma(-l11[2][0], u0, r2));
+                const double u3 =
+                    fma(-l11[3][2], u2, fma(-l11[3][1], u1, fma(-l11[3][0], u0, r3)));
+                const double ug = g == 0 ? u0 : (g == 1 ? u1 : (g == 2 ? u2 : u3));
+                const int q = 16 * J + jl;
+                if (jl >= i0 && q <= KP) sU[L::ubase(c0 + g) + 2 * q] = ug;
+                const double Aop = jl >= i0 ? -ug : 0.0;
+#pragma unroll
+                for (int I = 0; I < NT; ++I)
+                    T[I][jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(Aop, Bop[I], T[I][jt], 0, 0, 0);
+                wave_sync();  // s_ub is rewritten for the next tile column
+            }
+        }
+    }
+    // wavefront 1's flags to wavefront 0
+    uint32_t fl = seg_all<kWave, OpOr>(flags, lane);
+    if (WV == 1 && lane == 0) *s_fl = fl;
+    __syncthreads();  // the rows of U and the flags are visible
+    if (WV != 0) return;
+    fl |= *s_fl;
+
+    // ---- back substitution over the rows of U in LDS (wavefront 0) ---------
+    int ub[SL];
+    double yb[SL], mb[SL], zm[SL];
+    double ur[1][1];
+    uint32_t lukey = 0;
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+        const int r0 = lane + kWave * s;
+        const int r = r0 < KP ? r0 : KP - 1;
+        ub[s] = L::ubase(r);
+        yb[s] = sU[ub[s] + 2 * KP];
+        const double d = sU[ub[s] + 2 * r];
+        mb[s] = 1.0 / d;
+        zm[s] = 0.0;
+        const uint32_t f = !isfinite(d) ? L_NONFIN : (d == 0.0 ? L_SING : 0u);
+        const uint32_t key = ((uint32_t)(KP - r0) << 2) | f;
+        if (r0 < KP && f && key > lukey) lukey = key;
+    }
+    const uint32_t luflag = seg_all<kWave, OpMax>(lukey, lane) & 3u;
+    bc_step<KP, kWave, SL, KP - 1, false>(sU, ub, ur[0], yb, mb, zm, lane, false);
+
+#pragma unroll
+    for (int s = 0; s < SL; ++s)
+        if (lane + kWave * s < K && !isfinite(zm[s])) fl |= F_ZBAD;
+    fl = seg_all<kWave, OpOr>(fl, lane);
+    int st = RBFFD_OK;
+    if (fl & F_BADIDX) st = RBFFD_BAD_INDEX;
+    else if (fl & F_NONFIN) st = RBFFD_NONFINITE;
+    else if (fl & F_DUP) st = RBFFD_DUPLICATE;
+    else if (luflag == L_NONFIN) st = RBFFD_NONFINITE;
+    else if (luflag == L_SING) st = RBFFD_SINGULAR;
+    else if (fl & F_ZBAD) st = RBFFD_NONFINITE;
+    double *wi = w + i * (int64_t)k_stride;
+    const double s2 = sc * sc;
+    const bool good = st == RBFFD_OK;
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+        const int r = lane + kWave * s;
+        if (r < n) wi[r] = good ? zm[s] / s2 : __builtin_nan("");
+    }
+    for (int q = n + lane; q < k_stride; q += kWave) wi[q] = 0.0;
+    if (lane == 0 && status) status[i] = good ? ok_code : st;
+}
+
+// One block (two wavefronts) computes stencil `t` of the row list.
+__device__ __forceinline__ void weights_mf_body(
+    const double *__restrict__ x, const double *__restrict__ y, int64_t n_nodes,
+    const int32_t *__restrict__ nbr, int32_t k_stride, const int32_t *__restrict__ rows,
+    int64_t n_rows, double *__restrict__ w, int32_t *__restrict__ status, int32_t ok_code,
+    int64_t t, char *lds) {
+    if (t >= n_rows) return;  // whole block idle
+    const int64_t i = rows ? (int64_t)rows[t] : t;
+    if ((threadIdx.x >> 6) & 1)
+        weights_mf_wave<1>(x, y, n_nodes, nbr, k_stride, i, w, status, ok_code, lds);
+    else
+        weights_mf_wave<0>(x, y, n_nodes, nbr, k_stride, i, w, status, ok_code, lds);
+}
+
+__global__ __launch_bounds__(2 * kWave)
+__attribute__((amdgpu_waves_per_eu(2))) void weights_mf_kernel(
+    const double *__restrict__ x, const double *__restrict__ y, int64_t n_nodes,
+    const int32_t *__restrict__ nbr, int32_t k_stride, const int32_t *__restrict__ rows,
+    const int32_t *__restrict__ n_rows_dev, int64_t n_rows, double *__restrict__ w,
+    int32_t *__restrict__ status, int32_t ok_code) {
+    __shared__ __align__(16) char lds[MfLds::BYTES];
+    if (n_rows_dev) n_rows = *n_rows_dev;
+    weights_mf_body(x, y, n_nodes, nbr, k_stride, rows, n_rows, w, status, ok_code,
+                    (int64_t)blockIdx.x, lds);
+}
+
+inline int launch_mf(const double *x, const double *y, int64_t n_nodes, const int32_t *nbr,
+                     int32_t k_stride, const int32_t *rows, const int32_t *n_rows_dev,
+                     int64_t n_rows, double *w, int32_t *status, int32_t ok_code,
+                     hipStream_t stream) {
+    if (n_rows <= 0) return RBFFD_SUCCESS;
+    if (n_rows > 0x7fffffff) return RBFFD_ERR_UNSUPPORTED;
+    hipLaunchKernelGGL(weights_mf_kernel, dim3((unsigned)n_rows), dim3(2 * kWave), 0, stream, x, y,
+                       n_nodes, nbr, k_stride, rows, n_rows_dev, n_rows, w, status, ok_code);
+    return last_launch_rc();
+}
+
+}  // namespace wk
+}  // namespace rbffd
