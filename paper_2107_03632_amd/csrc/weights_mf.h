@@ -16,15 +16,14 @@
 // register r holds row 16 I + j, column 16 J + g + 4 r.  Wavefront w of the
 // block owns the tile columns J = w, w + 2, w + 4 (all six tile rows).
 //
-// The four columns of a panel [c0, c0 + 4) are then register (c0 % 16) / 4
-// of the tiles of column c0 / 16, column c0 + g in lane group g, so the
-// owner runs the panel's column steps on fixed registers:
-//   * pivot search over the 96 rows of group k (six rows per lane, then a
-//     16-lane reduction; the exact (|a|, position) key when the high words
-//     tie, positions kept in LDS);
-//   * the pivot row's four panel entries through LDS; the multipliers of
-//     group k through LDS to the other groups, which update their column;
-//   * each panel's multipliers end up in LDS in the B-operand layout.
+// The four columns of a panel [c0, c0 + 4) are register (c0 % 16) / 4 of
+// the tiles of column c0 / 16 (column c0 + g in lane group g).  Their owner
+// moves them through LDS to row layout (lane l: rows l and l + 64, four
+// columns each) and runs the panel's column steps there as the unblocked
+// kernels do: pivot search by the exact (|a|, position) key, the pivot
+// row's entries by readlane, the multipliers in place of the column, the
+// later panel columns updated with fused multiply-adds.  The multipliers go
+// back to LDS, where both wavefronts read them in the B-operand layout.
 // At the panel's end (one block barrier) each wavefront forms, for its
 // trailing tile columns, the pivot rows' entries with the panel's own
 // corrections applied in order (U12, the A operand) and updates every tile
@@ -38,18 +37,25 @@ namespace wk {
 
 typedef double mf_v4d __attribute__((ext_vector_type(4)));
 
+// LDS traffic of one wavefront is processed in issue order, so a write by
+// one lane is seen by a later read of another lane of the same wavefront
+// without waiting for the write to complete; this only keeps the compiler
+// from reordering the accesses.
+__device__ __forceinline__ void lds_order() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_wave_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 // LDS of one block: doubles first, then int32.
 struct MfLds {
     static constexpr int KP = 84, MM = 28, NT = 6;
     static constexpr int SZ = MsLds<KP, MM>::SZ;    // U triangle / assembly tables
-    static constexpr int B = SZ;                    // [2][NT][64] panel multipliers
-    static constexpr int PROW = B + 2 * NT * kWave;  // [4] pivot row, panel columns
-    static constexpr int UB = PROW + 4;             // [2 waves][4][16] pivot rows, one tile column
-    static constexpr int DBL = UB + 2 * 4 * 16;
-    static constexpr int REC = 0;                   // [2][4] pivot rows of a panel
-    static constexpr int POS = 8;                   // [96] position of each row
-    static constexpr int AT = POS + 96;             // [96] row at each position
-    static constexpr int FL = AT + 96;              // flags of wavefront 1
+    static constexpr int PAN = SZ;                  // [2][96][4] panel, row layout
+    static constexpr int UB = PAN + 2 * 96 * 4;     // [2 waves][3][4][16] pivot rows of a panel
+    static constexpr int DBL = UB + 2 * 3 * 4 * 16;
+    static constexpr int REC = 0;                   // [2][4][2] pivot row, its position
+    static constexpr int FL = 16;                   // flags of wavefront 1
     static constexpr int INTS = FL + 2;
     static constexpr int BYTES = 8 * DBL + 4 * INTS;
 };
@@ -66,13 +72,10 @@ __device__ __forceinline__ void weights_mf_wave(
     double *s_ux = sU;
     double *s_uy = sU + KP;
     double(*s_P)[MM] = reinterpret_cast<double(*)[MM]>(sU + 2 * KP);
-    double(*s_B)[NT][kWave] = reinterpret_cast<double(*)[NT][kWave]>(sU + B::B);
-    double *s_prow = sU + B::PROW;
-    double(*s_ub)[16] = reinterpret_cast<double(*)[16]>(sU + B::UB + WV * 64);
+    double(*s_pan)[96][4] = reinterpret_cast<double(*)[96][4]>(sU + B::PAN);
+    double(*s_ub)[4][16] = reinterpret_cast<double(*)[4][16]>(sU + B::UB + WV * 3 * 64);
     int32_t *si = reinterpret_cast<int32_t *>(lds + 8 * B::DBL);
-    int32_t(*s_rec)[4] = reinterpret_cast<int32_t(*)[4]>(si + B::REC);
-    int32_t *s_pos = si + B::POS;
-    int32_t *s_at = si + B::AT;
+    int32_t(*s_rec)[4][2] = reinterpret_cast<int32_t(*)[4][2]>(si + B::REC);
     uint32_t *s_fl = reinterpret_cast<uint32_t *>(si + B::FL);
 
     const int lane = threadIdx.x & (kWave - 1);
@@ -127,11 +130,6 @@ __device__ __forceinline__ void weights_mf_wave(
                 for (int j = 0; j < MM; ++j) s_P[r][j] = px[mono_a(j)] * py[mono_b(j)];
             }
         }
-    } else {
-        for (int r = lane; r < 96; r += kWave) {
-            s_pos[r] = r;
-            s_at[r] = r;
-        }
     }
     __syncthreads();
 
@@ -180,10 +178,15 @@ __device__ __forceinline__ void weights_mf_wave(
     __syncthreads();  // the assembly tables' space becomes the rows of U
 
     // ---- LU, panels of four columns ----------------------------------------
-    uint32_t dmask = 0;  // bit I: row 16 I + jl pivoted already (or padding)
+    // Row-layout state (rows lane, lane + 64): done = pivoted already (or
+    // padding), pos = current position of the row.
+    int pos[SL];
+    bool done[SL];
 #pragma unroll
-    for (int I = 0; I < NT; ++I)
-        if (16 * I + jl >= KP) dmask |= 1u << I;
+    for (int s = 0; s < SL; ++s) {
+        pos[s] = lane + kWave * s;
+        done[s] = pos[s] >= KP;
+    }
 
 #pragma unroll
     for (int c0 = 0; c0 < KP; c0 += 4) {
@@ -192,102 +195,91 @@ __device__ __forceinline__ void weights_mf_wave(
         const int rc = (c0 & 15) >> 2;  // its register
         if ((J0 & 1) == WV) {
             const int jt0 = J0 >> 1;
+            // the panel to row layout through LDS: pc[s][j] = row lane + 64 s,
+            // column c0 + j
+#pragma unroll
+            for (int I = 0; I < NT; ++I) s_pan[pb][16 * I + jl][g] = T[I][jt0][rc];
+            lds_order();
+            double pc[SL][4];
+#pragma unroll
+            for (int s = 0; s < SL; ++s) {
+                const int r = lane + kWave * s;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) pc[s][j] = r < 96 ? s_pan[pb][r < 96 ? r : 0][j] : 0.0;
+            }
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const int c = c0 + k;
-                // pivot search over the rows of group k: high words first
-                uint32_t bh = 0;
-                int bI = 0;
-                bool dup = false;
+                // pivot search over both slots: exact key (|a| bits, position)
+                uint64_t bb = 0;
+                int bp = 0x7fffffff, bsl = 0;
+                double bv = 0.0;
+                bool ba = false;
 #pragma unroll
-                for (int I = 0; I < NT; ++I) {
+                for (int s = 0; s < SL; ++s) {
                     const uint64_t bits =
-                        (uint64_t)__double_as_longlong(T[I][jt0][rc]) & 0x7fffffffffffffffull;
-                    const uint32_t hi = (uint32_t)(bits >> 32) + 1u;
-                    const bool act = ((dmask >> I) & 1u) == 0u;
-                    const bool gt = act && hi > bh;
-                    const bool eq = act && hi == bh;
-                    dup = gt ? false : (dup || eq);
-                    bI = gt ? I : bI;
-                    bh = gt ? hi : bh;
+                        (uint64_t)__double_as_longlong(pc[s][k]) & 0x7fffffffffffffffull;
+                    const bool take = !done[s] && (!ba || bits > bb || (bits == bb && pos[s] < bp));
+                    bb = take ? bits : bb;
+                    bp = take ? pos[s] : bp;
+                    bsl = take ? s : bsl;
+                    bv = take ? pc[s][k] : bv;
+                    ba = ba || !done[s];
                 }
-                const uint32_t mh = seg_all<16, OpMax>(bh, lane);
-                const uint64_t gmask = 0xffffull << (16 * k);
-                const uint64_t chunk = __ballot(bh == mh) & gmask;
-                const int wl0 = __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)chunk) - 1);
-                const bool dupw = __builtin_amdgcn_readlane(dup ? 1 : 0, wl0) != 0;
-                int win, wI;
-                if (__builtin_expect((chunk & (chunk - 1ull)) != 0ull || dupw, 0)) {
-                    // full key (|a| bits, position)
-                    uint32_t kh = 0, kl = 0;
-                    int kpp = 0x7fffffff, kI = 0;
-#pragma unroll
-                    for (int I = 0; I < NT; ++I) {
-                        const uint64_t bits =
-                            (uint64_t)__double_as_longlong(T[I][jt0][rc]) & 0x7fffffffffffffffull;
-                        const bool act = ((dmask >> I) & 1u) == 0u;
-                        const uint32_t h = act ? (uint32_t)(bits >> 32) + 1u : 0u;
-                        const uint32_t l = act ? (uint32_t)bits : 0u;
-                        const int p = act ? s_pos[16 * I + jl] : 0x7fffffff;
-                        if (key_better(h, l, p, kh, kl, kpp)) {
-                            kh = h;
-                            kl = l;
-                            kpp = p;
-                            kI = I;
-                        }
-                    }
-                    uint32_t gh = kh, gl = kl;
-                    int gp = kpp;
-                    seg_argmax_full<16>(gh, gl, gp);
-                    const uint64_t ch2 = __ballot(kpp == gp && kh != 0u) & gmask;
-                    win = __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)ch2) - 1);
-                    wI = __builtin_amdgcn_readlane(kI, win);
-                } else {
-                    win = wl0;
-                    wI = __builtin_amdgcn_readlane(bI, win);
+                const uint32_t kh = ba ? (uint32_t)(bb >> 32) + 1u : 0u;
+                const uint32_t mh = seg_all<kWave, OpMax>(kh, lane);
+                uint64_t chunk = __ballot(ba && kh == mh);
+                if (__builtin_expect((chunk & (chunk - 1ull)) != 0ull, 0)) {
+                    uint32_t h2 = kh, l2 = ba ? (uint32_t)bb : 0u;
+                    int p2 = ba ? bp : 0x7fffffff;
+                    seg_argmax_full<kWave>(h2, l2, p2);
+                    chunk = __ballot(ba && bp == p2);
                 }
-                const int ip = win & 15;
-                const int Ip = wI;
-                const int prow_id = 16 * Ip + ip;
-                // the pivot row's entries in the panel columns; row c of U
-                if (jl == ip) {
-                    double pv = 0.0;
+                const int win = __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)chunk) - 1);
+                const int bs = __builtin_amdgcn_readlane(bsl, win);
+                const int kp = __builtin_amdgcn_readlane(bp, win);
+                const double piv = readlane_d(bv, win);
+                const double inv = 1.0 / piv;
+                const bool b1 = bs != 0;
+                // row c of U, panel columns c .. c0 + 3
+                if (lane == win) {
 #pragma unroll
-                    for (int I = 0; I < NT; ++I)
-                        if (I == Ip) pv = T[I][jt0][rc];
-                    s_prow[g] = pv;
-                    if (g >= k) sU[L::ubase(c) + 2 * (c0 + g)] = pv;
+                    for (int j = k; j < 4; ++j)
+                        sU[L::ubase(c) + 2 * (c0 + j)] = b1 ? pc[1][j] : pc[0][j];
                 }
-                if (jl == ip) dmask |= 1u << Ip;
-                wave_sync();
-                const double u = s_prow[g];  // in group k: the pivot
-                const double inv = 1.0 / u;
-                if (g == k) {
+                double uq[4];
 #pragma unroll
-                    for (int I = 0; I < NT; ++I) {
-                        const bool act = ((dmask >> I) & 1u) == 0u;
-                        s_B[pb][I][lane] = act ? T[I][jt0][rc] * inv : 0.0;
-                    }
+                for (int j = k + 1; j < 4; ++j) uq[j] = readlane_d(b1 ? pc[1][j] : pc[0][j], win);
+                // multipliers, in place (zero for pivoted rows and the pivot)
+#pragma unroll
+                for (int s = 0; s < SL; ++s) {
+                    const bool upd = !done[s] && !(lane == win && bs == s);
+                    const double lmv = upd ? pc[s][k] * inv : 0.0;
+                    pc[s][k] = lmv;
+#pragma unroll
+                    for (int j = k + 1; j < 4; ++j) pc[s][j] = fma(-lmv, uq[j], pc[s][j]);
+                }
+#pragma unroll
+                for (int s = 0; s < SL; ++s) {
+                    const bool isp = lane == win && bs == s;
+                    pos[s] = isp ? c : ((!done[s] && pos[s] == c) ? kp : pos[s]);
+                    done[s] = done[s] || isp;
+                    int dn = done[s] ? 1 : 0;
+                    asm volatile("" : "+v"(pos[s]), "+v"(dn));
+                    done[s] = dn != 0;
                 }
                 if (lane == 0) {
-                    const int kp = s_pos[prow_id];
-                    const int q = s_at[c];
-                    s_pos[q] = kp;
-                    s_at[kp] = q;
-                    s_pos[prow_id] = c;
-                    s_at[c] = prow_id;
-                    s_rec[pb][k] = prow_id;
+                    s_rec[pb][k][0] = win + kWave * bs;
+                    s_rec[pb][k][1] = kp;
                 }
-                wave_sync();
-                if (k < 3) {
-                    double lb[NT];
+            }
+            // the panel's multipliers, row layout, for both wavefronts
 #pragma unroll
-                    for (int I = 0; I < NT; ++I) lb[I] = s_B[pb][I][16 * k + jl];
-                    if (g > k) {
+            for (int s = 0; s < SL; ++s) {
+                const int r = lane + kWave * s;
+                if (r < 96) {
 #pragma unroll
-                        for (int I = 0; I < NT; ++I)
-                            T[I][jt0][rc] = fma(-lb[I], u, T[I][jt0][rc]);
-                    }
+                    for (int j = 0; j < 4; ++j) s_pan[pb][r][j] = pc[s][j];
                 }
             }
         }
@@ -296,62 +288,90 @@ __device__ __forceinline__ void weights_mf_wave(
         // ---- panel end: trailing tile columns of this wavefront ------------
         int pr[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) pr[k] = __builtin_amdgcn_readfirstlane(s_rec[pb][k]);
+        for (int k = 0; k < 4; ++k) pr[k] = __builtin_amdgcn_readfirstlane(s_rec[pb][k][0]);
         if ((J0 & 1) != WV) {
+            // the owner's row bookkeeping, replayed
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (jl == (pr[k] & 15)) dmask |= 1u << (pr[k] >> 4);
+            for (int k = 0; k < 4; ++k) {
+                const int c = c0 + k;
+                const int kp = __builtin_amdgcn_readfirstlane(s_rec[pb][k][1]);
+#pragma unroll
+                for (int s = 0; s < SL; ++s) {
+                    const bool isp = lane + kWave * s == pr[k];
+                    pos[s] = isp ? c : ((!done[s] && pos[s] == c) ? kp : pos[s]);
+                    done[s] = done[s] || isp;
+                    int dn = done[s] ? 1 : 0;
+                    asm volatile("" : "+v"(pos[s]), "+v"(dn));
+                    done[s] = dn != 0;
+                }
+            }
         }
         // first tile column of this wavefront that still has trailing columns
         const int first_jt = ((J0 & 1) == WV) ? ((rc < 3) ? (J0 >> 1) : (J0 >> 1) + 1)
                                               : ((J0 + 1) >> 1);
         if (first_jt < 3) {
+            // the panel's pivot rows, in every trailing tile column of this
+            // wavefront, to LDS (one uniform branch per row)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int Ipk = pr[k] >> 4, ipk = pr[k] & 15;
+                if (jl == ipk) {
+#pragma unroll
+                    for (int I = 0; I < NT; ++I) {
+                        if (I == Ipk) {
+#pragma unroll
+                            for (int jt = 0; jt < 3; ++jt)
+                                if (jt >= first_jt) {
+#pragma unroll
+                                    for (int r = 0; r < 4; ++r)
+                                        s_ub[jt][k][g + 4 * r] = T[I][jt][r];
+                                }
+                        }
+                    }
+                }
+            }
+            lds_order();
             // multipliers of the panel's pivot rows in its earlier columns
             double l11[4][3];
 #pragma unroll
             for (int m2 = 1; m2 < 4; ++m2)
 #pragma unroll
-                for (int k2 = 0; k2 < m2; ++k2)
-                    l11[m2][k2] = s_B[pb][pr[m2] >> 4][16 * k2 + (pr[m2] & 15)];
+                for (int k2 = 0; k2 < m2; ++k2) l11[m2][k2] = s_pan[pb][pr[m2]][k2];
+            // B operands: lane (g, j) holds the multiplier of row 16 I + j in
+            // panel column c0 + g
             double Bop[NT];
 #pragma unroll
-            for (int I = 0; I < NT; ++I) Bop[I] = s_B[pb][I][lane];
+            for (int I = 0; I < NT; ++I) Bop[I] = s_pan[pb][16 * I + jl][g];
+            // the tile column of the next panel first: its updates are the
+            // ones the next column steps wait for
+            const int J0n = (c0 + 4) >> 4;
+            const int jtn = ((J0n & 1) == WV && c0 + 4 < KP) ? (J0n >> 1) : -1;
 #pragma unroll
-            for (int jt = 0; jt < 3; ++jt) {
-                if (jt < first_jt) continue;
-                const int J = 2 * jt + WV;
-                const int i0 = (J == J0) ? 4 * rc + 4 : 0;  // first trailing column in the tile
-                // the pivot rows' entries in tile column J
+            for (int pass = 0; pass < 2; ++pass) {
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int Ipk = pr[k] >> 4, ipk = pr[k] & 15;
-                    if (jl == ipk) {
+                for (int jt = 0; jt < 3; ++jt) {
+                    if (jt < first_jt) continue;
+                    if ((pass == 0) != (jt == jtn)) continue;
+                    const int J = 2 * jt + WV;
+                    const int i0 = (J == J0) ? 4 * rc + 4 : 0;  // first trailing column in the tile
+                    const double r0 = s_ub[jt][0][jl], r1 = s_ub[jt][1][jl];
+                    const double r2 = s_ub[jt][2][jl], r3 = s_ub[jt][3][jl];
+                    const double u0 = r0;
+                    const double u1 = fma(-l11[1][0], u0, r1);
+                    const double u2 = fma(-l11[2][1], u1, fma(-l11[2][0], u0, r2));
+                    const double u3 =
+                        fma(-l11[3][2], u2, fma(-l11[3][1], u1, fma(-l11[3][0], u0, r3)));
+                    const double ug = g == 0 ? u0 : (g == 1 ? u1 : (g == 2 ? u2 : u3));
+                    const int q = 16 * J + jl;
+                    if (jl >= i0 && q <= KP) sU[L::ubase(c0 + g) + 2 * q] = ug;
+                    const double Aop = jl >= i0 ? -ug : 0.0;
 #pragma unroll
-                        for (int I = 0; I < NT; ++I) {
-                            if (I == Ipk) {
-#pragma unroll
-                                for (int r = 0; r < 4; ++r) s_ub[k][g + 4 * r] = T[I][jt][r];
-                            }
-                        }
-                    }
+                    for (int I = 0; I < NT; ++I)
+                        T[I][jt] =
+                            __builtin_amdgcn_mfma_f64_16x16x4f64(Aop, Bop[I], T[I][jt], 0, 0, 0);
                 }
-                wave_sync();
-                const double r0 = s_ub[0][jl], r1 = s_ub[1][jl];
-                const double r2 = s_ub[2][jl], r3 = s_ub[3][jl];
-                const double u0 = r0;
-                const double u1 = fma(-l11[1][0], u0, r1);
-                const double u2 = fma(-l11[2][1], u1, fma(-l11[2][0], u0, r2));
-                const double u3 =
-                    fma(-l11[3][2], u2, fma(-l11[3][1], u1, fma(-l11[3][0], u0, r3)));
-                const double ug = g == 0 ? u0 : (g == 1 ? u1 : (g == 2 ? u2 : u3));
-                const int q = 16 * J + jl;
-                if (jl >= i0 && q <= KP) sU[L::ubase(c0 + g) + 2 * q] = ug;
-                const double Aop = jl >= i0 ? -ug : 0.0;
-#pragma unroll
-                for (int I = 0; I < NT; ++I)
-                    T[I][jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(Aop, Bop[I], T[I][jt], 0, 0, 0);
-                wave_sync();  // s_ub is rewritten for the next tile column
             }
+            lds_order();  // s_ub is rewritten at the next panel
         }
     }
     // wavefront 1's flags to wavefront 0
