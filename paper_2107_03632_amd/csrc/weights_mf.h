@@ -51,8 +51,8 @@ __device__ __forceinline__ void lds_order() {
 struct MfLds {
     static constexpr int KP = 84, MM = 28, NT = 6;
     static constexpr int SZ = MsLds<KP, MM>::SZ;    // U triangle / assembly tables
-    static constexpr int PAN = SZ;                  // [2][96][4] panel, row layout
-    static constexpr int UB = PAN + 2 * 96 * 4;     // [2 waves][3][4][16] pivot rows of a panel
+    static constexpr int PAN = SZ;                  // [2][96][5] panel, row layout (padded)
+    static constexpr int UB = PAN + 2 * 96 * 5;     // [2 waves][3][4][16] pivot rows of a panel
     static constexpr int DBL = UB + 2 * 3 * 4 * 16;
     static constexpr int REC = 0;                   // [2][4][2] pivot row, its position
     static constexpr int FL = 16;                   // flags of wavefront 1
@@ -72,7 +72,7 @@ __device__ __forceinline__ void weights_mf_wave(
     double *s_ux = sU;
     double *s_uy = sU + KP;
     double(*s_P)[MM] = reinterpret_cast<double(*)[MM]>(sU + 2 * KP);
-    double(*s_pan)[96][4] = reinterpret_cast<double(*)[96][4]>(sU + B::PAN);
+    double(*s_pan)[96][5] = reinterpret_cast<double(*)[96][5]>(sU + B::PAN);
     double(*s_ub)[4][16] = reinterpret_cast<double(*)[4][16]>(sU + B::UB + WV * 3 * 64);
     int32_t *si = reinterpret_cast<int32_t *>(lds + 8 * B::DBL);
     int32_t(*s_rec)[4][2] = reinterpret_cast<int32_t(*)[4][2]>(si + B::REC);
@@ -326,6 +326,10 @@ __device__ __forceinline__ void weights_mf_wave(
                                     for (int r = 0; r < 4; ++r)
                                         s_ub[jt][k][g + 4 * r] = T[I][jt][r];
                                 }
+                            // keeps each case's stores in its own branch
+                            // (merged, they would first copy the row
+                            // into common registers)
+                            asm volatile(";tile row %0" ::"i"(I) : "memory");
                         }
                     }
                 }
