@@ -5,7 +5,9 @@
 // queue, largest systems first so the long tiles start early and the short
 // ones fill the tail:
 //   * an order-6 tile is gpt[2] stencils, each spread over both wavefronts
-//     of the block (one matrix row per lane, 84 rows);
+//     of the block: the blocked LU with the trailing updates on the matrix
+//     cores (weights_mf.h), or, when the factors are saved for the adjoint,
+//     the column-split kernel (weights_cs.h);
 //   * an order-4 tile gives each wavefront gpt[1] stencils (one row per
 //     lane);
 //   * an order-2 tile gives each wavefront gpt[0] groups of 8 stencils
@@ -18,6 +20,7 @@
 #include <atomic>
 
 #include "weights_cs.h"
+#include "weights_mf.h"
 
 namespace rbffd {
 namespace {
@@ -44,7 +47,9 @@ __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(RBFFD_BATCH
     uint8_t *__restrict__ sv_perm, int32_t sv_kmax) {
     __shared__ int32_t s_tile;
     // one LDS buffer serves whichever body the current tile runs
-    constexpr int kLds0 = wk::cs_lds_bytes<84, 6>();
+    constexpr int kLds0 = SAVE || wk::cs_lds_bytes<84, 6>() > wk::MfLds::BYTES
+                              ? wk::cs_lds_bytes<84, 6>()
+                              : wk::MfLds::BYTES;
     constexpr int kLds1 = wk::ms_lds_bytes<45, kSeg45, 4, 2>();
     constexpr int kLds2 = wk::ms_lds_bytes<18, kSeg18, 2, 2>();
     constexpr int kLds = kLds0 > kLds1 ? (kLds0 > kLds2 ? kLds0 : kLds2) : (kLds1 > kLds2 ? kLds1 : kLds2);
@@ -62,10 +67,15 @@ __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(RBFFD_BATCH
         __syncthreads();
         if (tile >= total) break;
         if (tile < T6) {
-            for (int q = 0; q < gpt6; ++q)
-                wk::weights_cs_body<84, 56, 6, SAVE>(
-                    x, y, n_nodes, nbr, k_stride, lists + 2 * n_nodes, c6, 56, 6, w, status, sv_lu,
-                    sv_z, sv_s, sv_perm, sv_kmax, RBFFD_OK, tile * gpt6 + q, lds);
+            for (int q = 0; q < gpt6; ++q) {
+                if constexpr (SAVE)
+                    wk::weights_cs_body<84, 56, 6, SAVE>(
+                        x, y, n_nodes, nbr, k_stride, lists + 2 * n_nodes, c6, 56, 6, w, status,
+                        sv_lu, sv_z, sv_s, sv_perm, sv_kmax, RBFFD_OK, tile * gpt6 + q, lds);
+                else
+                    wk::weights_mf_body(x, y, n_nodes, nbr, k_stride, lists + 2 * n_nodes, c6, w,
+                                        status, RBFFD_OK, tile * gpt6 + q, lds);
+            }
         } else if (tile < T6 + T4) {
             const int64_t base = (tile - T6) * 2 * gpt4;
             for (int q = 0; q < gpt4; ++q)

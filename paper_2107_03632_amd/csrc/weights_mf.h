@@ -443,12 +443,14 @@ __device__ __forceinline__ void weights_mf_body(
         weights_mf_wave<0>(x, y, n_nodes, nbr, k_stride, i, w, status, ok_code, lds);
 }
 
+template <int KP>
 __global__ __launch_bounds__(2 * kWave)
 __attribute__((amdgpu_waves_per_eu(2))) void weights_mf_kernel(
     const double *__restrict__ x, const double *__restrict__ y, int64_t n_nodes,
     const int32_t *__restrict__ nbr, int32_t k_stride, const int32_t *__restrict__ rows,
     const int32_t *__restrict__ n_rows_dev, int64_t n_rows, double *__restrict__ w,
     int32_t *__restrict__ status, int32_t ok_code) {
+    static_assert(KP == MfLds::KP, "the blocked kernel is written for K = 84");
     __shared__ __align__(16) char lds[MfLds::BYTES];
     if (n_rows_dev) n_rows = *n_rows_dev;
     weights_mf_body(x, y, n_nodes, nbr, k_stride, rows, n_rows, w, status, ok_code,
@@ -461,7 +463,7 @@ inline int launch_mf(const double *x, const double *y, int64_t n_nodes, const in
                      hipStream_t stream) {
     if (n_rows <= 0) return RBFFD_SUCCESS;
     if (n_rows > 0x7fffffff) return RBFFD_ERR_UNSUPPORTED;
-    hipLaunchKernelGGL(weights_mf_kernel, dim3((unsigned)n_rows), dim3(2 * kWave), 0, stream, x, y,
+    hipLaunchKernelGGL(weights_mf_kernel<84>, dim3((unsigned)n_rows), dim3(2 * kWave), 0, stream, x, y,
                        n_nodes, nbr, k_stride, rows, n_rows_dev, n_rows, w, status, ok_code);
     return last_launch_rc();
 }
