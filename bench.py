@@ -54,12 +54,13 @@ def source_digest(paths) -> str:
     return h.hexdigest()[:16]
 
 
-# sources of the dominant kernel (K = 45 instance of the multi-slot kernel)
+# sources of the dominant kernel (K = 45 instance of the blocked MFMA kernel)
 WEIGHTS_SOURCES = ["paper_2107_03632_amd/csrc/common.h",
                    "paper_2107_03632_amd/csrc/weights_kernel.h",
                    "paper_2107_03632_amd/csrc/weights_ms.h",
+                   "paper_2107_03632_amd/csrc/weights_mf.h",
                    "paper_2107_03632_amd/csrc/weights_k45.hip"]
-WEIGHTS_KERNEL = "weights_ms_kernel<45, 64, 1, 30, 4, 4, false>"
+WEIGHTS_KERNEL = "weights_mf_kernel<45, 30, 4, 1, 4>"
 
 
 def read_traffic(kernel_tag: str):
@@ -223,6 +224,8 @@ def main():
         "config": {"workload": "unit disk, 100k jittered lattice nodes + 1000 boundary, "
                                "m=4, n=30, FP64: kNN -> weights -> CSR -> W u - f",
                    "n_nodes": N, "m": m, "n": n, "global_batch": N, "parallelism": "none"},
+        # the FP64 MFMA peak of this chip equals its FP64 vector peak; the
+        # kernel is bound by its vector instruction stream (column steps)
         "roofline": {"bound": "alu", "kernel": WEIGHTS_KERNEL,
                      "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,

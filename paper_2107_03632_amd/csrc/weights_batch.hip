@@ -8,8 +8,9 @@
 //     of the block: the blocked LU with the trailing updates on the matrix
 //     cores (weights_mf.h), or, when the factors are saved for the adjoint,
 //     the column-split kernel (weights_cs.h);
-//   * an order-4 tile gives each wavefront gpt[1] stencils (one row per
-//     lane);
+//   * an order-4 tile gives each wavefront gpt[1] stencils (the blocked
+//     LU of weights_mf.h, one stencil per wavefront; one row per lane in the
+//     launch that saves factors);
 //   * an order-2 tile gives each wavefront gpt[0] groups of 8 stencils
 //     (8 lanes x 3 rows per stencil).
 // Tile sizes and the grid size (blocks per compute unit) are runtime
@@ -36,6 +37,8 @@ constexpr int kSeg18 = 8, kSl18 = 3;
 constexpr int kSeg45 = 64, kSl45 = 1;
 constexpr int kG18 = kWave / kSeg18;  // stencils per wavefront group, K = 18
 constexpr int kG45 = kWave / kSeg45;  // K = 45
+// LDS of one K = 45 blocked-LU stencil (one per wavefront), 16-byte aligned
+constexpr int kMf45 = (wk::mf_lds_bytes<45, 30, 4>(1) + 15) & ~15;
 
 template <bool SAVE>
 __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(RBFFD_BATCH_OCC))) void weights_batch_kernel(
@@ -47,10 +50,12 @@ __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(RBFFD_BATCH
     uint8_t *__restrict__ sv_perm, int32_t sv_kmax) {
     __shared__ int32_t s_tile;
     // one LDS buffer serves whichever body the current tile runs
-    constexpr int kLds0 = SAVE || wk::cs_lds_bytes<84, 6>() > wk::MfLds::BYTES
+    constexpr int kLds0 = SAVE || wk::cs_lds_bytes<84, 6>() > wk::mf_lds_bytes<84, 56, 6>(2)
                               ? wk::cs_lds_bytes<84, 6>()
-                              : wk::MfLds::BYTES;
-    constexpr int kLds1 = wk::ms_lds_bytes<45, kSeg45, 4, 2>();
+                              : wk::mf_lds_bytes<84, 56, 6>(2);
+    constexpr int kLds1 = SAVE || wk::ms_lds_bytes<45, kSeg45, 4, 2>() > 2 * kMf45
+                              ? wk::ms_lds_bytes<45, kSeg45, 4, 2>()
+                              : 2 * kMf45;
     constexpr int kLds2 = wk::ms_lds_bytes<18, kSeg18, 2, 2>();
     constexpr int kLds = kLds0 > kLds1 ? (kLds0 > kLds2 ? kLds0 : kLds2) : (kLds1 > kLds2 ? kLds1 : kLds2);
     __shared__ __align__(16) char lds[kLds];
@@ -73,15 +78,22 @@ __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(RBFFD_BATCH
                         x, y, n_nodes, nbr, k_stride, lists + 2 * n_nodes, c6, 56, 6, w, status,
                         sv_lu, sv_z, sv_s, sv_perm, sv_kmax, RBFFD_OK, tile * gpt6 + q, lds);
                 else
-                    wk::weights_mf_body(x, y, n_nodes, nbr, k_stride, lists + 2 * n_nodes, c6, w,
+                    wk::weights_mf_body<84, 56, 6, 2>(x, y, n_nodes, nbr, k_stride, lists + 2 * n_nodes, c6, w,
                                         status, RBFFD_OK, tile * gpt6 + q, lds);
             }
         } else if (tile < T6 + T4) {
             const int64_t base = (tile - T6) * 2 * gpt4;
-            for (int q = 0; q < gpt4; ++q)
-                wk::weights_ms_body<45, kSeg45, kSl45, 30, 4, 2, SAVE>(
-                    x, y, n_nodes, nbr, k_stride, lists + n_nodes, c4, 30, 4, w, status, sv_lu,
-                    sv_z, sv_s, sv_perm, sv_kmax, RBFFD_OK, base + 2 * q + wave, wave, lds);
+            for (int q = 0; q < gpt4; ++q) {
+                if constexpr (SAVE)
+                    wk::weights_ms_body<45, kSeg45, kSl45, 30, 4, 2, SAVE>(
+                        x, y, n_nodes, nbr, k_stride, lists + n_nodes, c4, 30, 4, w, status,
+                        sv_lu, sv_z, sv_s, sv_perm, sv_kmax, RBFFD_OK, base + 2 * q + wave, wave,
+                        lds);
+                else
+                    wk::weights_mf_body<45, 30, 4, 1>(x, y, n_nodes, nbr, k_stride,
+                                                      lists + n_nodes, c4, w, status, RBFFD_OK,
+                                                      base + 2 * q + wave, lds + wave * kMf45);
+            }
         } else {
             const int64_t base = (tile - T6 - T4) * 2 * gpt2;
             for (int q = 0; q < gpt2; ++q)

@@ -1,6 +1,8 @@
 #pragma once
-// RBF-FD Laplacian stencil weights, FP64, K = 84 (m = 6, n = 56): LU blocked
-// by panels of four columns with the trailing updates on the matrix cores.
+// RBF-FD Laplacian stencil weights, FP64: LU blocked by panels of four
+// columns with the trailing updates on the matrix cores.  Instances: K = 84
+// (m = 6, n = 56; two wavefronts per stencil) and K = 45 (m = 4, n = 30; one
+// wavefront per stencil).
 //
 // v_mfma_f64_16x16x4f64 forms each output as four fused multiply-adds taken
 // in k order, fma(a3, b3, fma(a2, b2, fma(a1, b1, fma(a0, b0, c)))).  A
@@ -10,25 +12,29 @@
 // those of the other kernels (same shift, scale, assembly, pivot rule and
 // back substitution).
 //
-// Layout: the system padded to 96 x 96 (right-hand side in column 84; rows
-// and columns 85..95 zero; rows 84..95 never pivot), in 16 x 16 tiles held
-// transposed as MFMA accumulators: in tile (I, J), lane l = 16 g + j,
-// register r holds row 16 I + j, column 16 J + g + 4 r.  Wavefront w of the
-// block owns the tile columns J = w, w + 2, w + 4 (all six tile rows).
+// Layout: the system padded to NP x NP, NP = 16 NT (96 for K = 84, 48 for
+// K = 45; right-hand side in column KP, the other padding rows and columns
+// zero, padding rows never pivot), in 16 x 16 tiles held transposed as MFMA
+// accumulators: in tile (I, J), lane l = 16 g + j, register r holds row
+// 16 I + j, column 16 J + g + 4 r.  With NW wavefronts per stencil,
+// wavefront w owns the tile columns J = w, w + NW, ... (all tile rows).
 //
 // The four columns of a panel [c0, c0 + 4) are register (c0 % 16) / 4 of
 // the tiles of column c0 / 16 (column c0 + g in lane group g).  Their owner
-// moves them through LDS to row layout (lane l: rows l and l + 64, four
+// moves them through LDS to row layout (lane l: rows l, l + 64, ...; four
 // columns each) and runs the panel's column steps there as the unblocked
 // kernels do: pivot search by the exact (|a|, position) key, the pivot
 // row's entries by readlane, the multipliers in place of the column, the
 // later panel columns updated with fused multiply-adds.  The multipliers go
 // back to LDS, where both wavefronts read them in the B-operand layout.
-// At the panel's end (one block barrier) each wavefront forms, for its
+// When KP is not a multiple of 4 the last panel has fewer column steps and
+// the right-hand side is one of its columns.
+// At the panel's end (a block barrier with two wavefronts) each wavefront
+// forms, for its
 // trailing tile columns, the pivot rows' entries with the panel's own
 // corrections applied in order (U12, the A operand) and updates every tile
-// with one MFMA.  Rows of U go to the packed LDS triangle as they are
-// completed; wavefront 0 runs the back substitution from there.
+// with one MFMA per tile.  Rows of U go to the packed LDS triangle as they
+// are completed; wavefront 0 runs the back substitution from there.
 
 #include "weights_ms.h"
 
@@ -47,33 +53,43 @@ __device__ __forceinline__ void lds_order() {
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-// LDS of one block: doubles first, then int32.
+// LDS of one block: doubles first, then int32.  Panel buffers alternate
+// between consecutive panels when two wavefronts share them.
+template <int KP, int MM, int NT, int NW>
 struct MfLds {
-    static constexpr int KP = 84, MM = 28, NT = 6;
+    static constexpr int NP = 16 * NT;
+    static constexpr int NPB = NW > 1 ? 2 : 1;       // panel buffers
+    static constexpr int NJT = NT / NW;             // tile columns per wavefront
     static constexpr int SZ = MsLds<KP, MM>::SZ;    // U triangle / assembly tables
-    static constexpr int PAN = SZ;                  // [2][96][5] panel, row layout (padded)
-    static constexpr int UB = PAN + 2 * 96 * 5;     // [2 waves][3][4][16] pivot rows of a panel
-    static constexpr int DBL = UB + 2 * 3 * 4 * 16;
-    static constexpr int REC = 0;                   // [2][4][2] pivot row, its position
-    static constexpr int FL = 16;                   // flags of wavefront 1
+    static constexpr int PAN = SZ;                  // [NPB][NP][5] panel, row layout (padded)
+    static constexpr int UB = PAN + NPB * NP * 5;   // [NW][NJT][4][16] pivot rows of a panel
+    static constexpr int DBL = UB + NW * NJT * 64;
+    static constexpr int REC = 0;                   // [NPB][4][2] pivot row, its position
+    static constexpr int FL = 8 * NPB;              // flags of wavefront 1
     static constexpr int INTS = FL + 2;
     static constexpr int BYTES = 8 * DBL + 4 * INTS;
 };
 
-template <int WV>
+template <int KP, int NFIX, int MFIX, int NW, int WV>
 __device__ __forceinline__ void weights_mf_wave(
     const double *__restrict__ x, const double *__restrict__ y, int64_t n_nodes,
     const int32_t *__restrict__ nbr, int32_t k_stride, int64_t i, double *__restrict__ w,
     int32_t *__restrict__ status, int32_t ok_code, char *lds) {
-    constexpr int KP = 84, n = 56, K = 84, MM = 28, NT = 6, SL = 2;
+    constexpr int MM = (MFIX + 1) * (MFIX + 2) / 2, n = NFIX, K = NFIX + MM;
+    static_assert(K == KP, "no identity padding in the blocked kernel");
+    constexpr int NT = (KP + 1 + 15) / 16;  // tiles per dimension (rhs included)
+    constexpr int NP = 16 * NT;
+    constexpr int SL = (NP + kWave - 1) / kWave;  // rows per lane in row layout
+    static_assert(NT % NW == 0, "tile columns split evenly");
+    constexpr int NJT = NT / NW;
     using L = MsLds<KP, MM>;
-    using B = MfLds;
+    using B = MfLds<KP, MM, NT, NW>;
     double *sU = reinterpret_cast<double *>(lds);
     double *s_ux = sU;
     double *s_uy = sU + KP;
     double(*s_P)[MM] = reinterpret_cast<double(*)[MM]>(sU + 2 * KP);
-    double(*s_pan)[96][5] = reinterpret_cast<double(*)[96][5]>(sU + B::PAN);
-    double(*s_ub)[4][16] = reinterpret_cast<double(*)[4][16]>(sU + B::UB + WV * 3 * 64);
+    double(*s_pan)[NP][5] = reinterpret_cast<double(*)[NP][5]>(sU + B::PAN);
+    double(*s_ub)[4][16] = reinterpret_cast<double(*)[4][16]>(sU + B::UB + WV * NJT * 64);
     int32_t *si = reinterpret_cast<int32_t *>(lds + 8 * B::DBL);
     int32_t(*s_rec)[4][2] = reinterpret_cast<int32_t(*)[4][2]>(si + B::REC);
     uint32_t *s_fl = reinterpret_cast<uint32_t *>(si + B::FL);
@@ -131,10 +147,15 @@ __device__ __forceinline__ void weights_mf_wave(
             }
         }
     }
-    __syncthreads();
+    // one wavefront: its own LDS traffic is ordered, and it may share its
+    // block with a wavefront running another stencil, so no block barrier
+    if constexpr (NW > 1)
+        __syncthreads();
+    else
+        lds_order();
 
     // ---- assembly of this wavefront's tile columns (transposed tiles) ------
-    mf_v4d T[NT][3];
+    mf_v4d T[NT][NJT];
 #pragma unroll
     for (int I = 0; I < NT; ++I) {
         const int R = 16 * I + jl;
@@ -144,8 +165,8 @@ __device__ __forceinline__ void weights_mf_wave(
         const double uxr = (16 * I < n && prow) ? s_ux[R] : 0.0;
         const double uyr = (16 * I < n && prow) ? s_uy[R] : 0.0;
 #pragma unroll
-        for (int jt = 0; jt < 3; ++jt) {
-            const int J = 2 * jt + WV;
+        for (int jt = 0; jt < NJT; ++jt) {
+            const int J = NW * jt + WV;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int C = 16 * J + g + 4 * r;
@@ -175,7 +196,11 @@ __device__ __forceinline__ void weights_mf_wave(
         }
     }
     asm volatile("" : "+v"(flags));
-    __syncthreads();  // the assembly tables' space becomes the rows of U
+    // the assembly tables' space becomes the rows of U
+    if constexpr (NW > 1)
+        __syncthreads();
+    else
+        lds_order();
 
     // ---- LU, panels of four columns ----------------------------------------
     // Row-layout state (rows lane, lane + 64): done = pivoted already (or
@@ -190,11 +215,12 @@ __device__ __forceinline__ void weights_mf_wave(
 
 #pragma unroll
     for (int c0 = 0; c0 < KP; c0 += 4) {
-        const int pb = (c0 >> 2) & 1;
-        const int J0 = c0 >> 4;         // tile column of the panel
-        const int rc = (c0 & 15) >> 2;  // its register
-        if ((J0 & 1) == WV) {
-            const int jt0 = J0 >> 1;
+        const int pb = B::NPB > 1 ? (c0 >> 2) & 1 : 0;
+        const int J0 = c0 >> 4;                  // tile column of the panel
+        const int rc = (c0 & 15) >> 2;           // its register
+        const int nk = KP - c0 < 4 ? KP - c0 : 4;  // column steps in the panel
+        if (J0 % NW == WV) {
+            const int jt0 = J0 / NW;
             // the panel to row layout through LDS: pc[s][j] = row lane + 64 s,
             // column c0 + j
 #pragma unroll
@@ -205,12 +231,13 @@ __device__ __forceinline__ void weights_mf_wave(
             for (int s = 0; s < SL; ++s) {
                 const int r = lane + kWave * s;
 #pragma unroll
-                for (int j = 0; j < 4; ++j) pc[s][j] = r < 96 ? s_pan[pb][r < 96 ? r : 0][j] : 0.0;
+                for (int j = 0; j < 4; ++j) pc[s][j] = r < NP ? s_pan[pb][r < NP ? r : 0][j] : 0.0;
             }
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
+                if (k >= nk) break;
                 const int c = c0 + k;
-                // pivot search over both slots: exact key (|a| bits, position)
+                // pivot search over the slots: exact key (|a| bits, position)
                 uint64_t bb = 0;
                 int bp = 0x7fffffff, bsl = 0;
                 double bv = 0.0;
@@ -241,15 +268,17 @@ __device__ __forceinline__ void weights_mf_wave(
                 const double piv = readlane_d(bv, win);
                 const double inv = 1.0 / piv;
                 const bool b1 = bs != 0;
-                // row c of U, panel columns c .. c0 + 3
+                // row c of U, panel columns c .. c0 + 3 (up to the rhs)
                 if (lane == win) {
 #pragma unroll
                     for (int j = k; j < 4; ++j)
-                        sU[L::ubase(c) + 2 * (c0 + j)] = b1 ? pc[1][j] : pc[0][j];
+                        if (c0 + j <= KP)
+                            sU[L::ubase(c) + 2 * (c0 + j)] = b1 ? pc[SL - 1][j] : pc[0][j];
                 }
                 double uq[4];
 #pragma unroll
-                for (int j = k + 1; j < 4; ++j) uq[j] = readlane_d(b1 ? pc[1][j] : pc[0][j], win);
+                for (int j = k + 1; j < 4; ++j)
+                    uq[j] = c0 + j <= KP ? readlane_d(b1 ? pc[SL - 1][j] : pc[0][j], win) : 0.0;
                 // multipliers, in place (zero for pivoted rows and the pivot)
 #pragma unroll
                 for (int s = 0; s < SL; ++s) {
@@ -257,7 +286,8 @@ __device__ __forceinline__ void weights_mf_wave(
                     const double lmv = upd ? pc[s][k] * inv : 0.0;
                     pc[s][k] = lmv;
 #pragma unroll
-                    for (int j = k + 1; j < 4; ++j) pc[s][j] = fma(-lmv, uq[j], pc[s][j]);
+                    for (int j = k + 1; j < 4; ++j)
+                        if (c0 + j <= KP) pc[s][j] = fma(-lmv, uq[j], pc[s][j]);
                 }
 #pragma unroll
                 for (int s = 0; s < SL; ++s) {
@@ -277,22 +307,27 @@ __device__ __forceinline__ void weights_mf_wave(
 #pragma unroll
             for (int s = 0; s < SL; ++s) {
                 const int r = lane + kWave * s;
-                if (r < 96) {
+                if (r < NP) {
 #pragma unroll
                     for (int j = 0; j < 4; ++j) s_pan[pb][r][j] = pc[s][j];
                 }
             }
         }
-        __syncthreads();
+        if constexpr (NW > 1)
+            __syncthreads();
+        else
+            lds_order();
 
         // ---- panel end: trailing tile columns of this wavefront ------------
-        int pr[4];
+        int pr[4] = {0, 0, 0, 0};
 #pragma unroll
-        for (int k = 0; k < 4; ++k) pr[k] = __builtin_amdgcn_readfirstlane(s_rec[pb][k][0]);
-        if ((J0 & 1) != WV) {
+        for (int k = 0; k < 4; ++k)
+            if (k < nk) pr[k] = __builtin_amdgcn_readfirstlane(s_rec[pb][k][0]);
+        if (J0 % NW != WV) {
             // the owner's row bookkeeping, replayed
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
+                if (k >= nk) break;
                 const int c = c0 + k;
                 const int kp = __builtin_amdgcn_readfirstlane(s_rec[pb][k][1]);
 #pragma unroll
@@ -307,9 +342,9 @@ __device__ __forceinline__ void weights_mf_wave(
             }
         }
         // first tile column of this wavefront that still has trailing columns
-        const int first_jt = ((J0 & 1) == WV) ? ((rc < 3) ? (J0 >> 1) : (J0 >> 1) + 1)
-                                              : ((J0 + 1) >> 1);
-        if (first_jt < 3) {
+        const int first_jt = (J0 % NW == WV) ? ((rc < 3) ? J0 / NW : J0 / NW + 1)
+                                             : (J0 + 1) / NW;
+        if (first_jt < NJT) {  // (a partial panel is the last: nothing trails it)
             // the panel's pivot rows, in every trailing tile column of this
             // wavefront, to LDS (one uniform branch per row)
 #pragma unroll
@@ -320,7 +355,7 @@ __device__ __forceinline__ void weights_mf_wave(
                     for (int I = 0; I < NT; ++I) {
                         if (I == Ipk) {
 #pragma unroll
-                            for (int jt = 0; jt < 3; ++jt)
+                            for (int jt = 0; jt < NJT; ++jt)
                                 if (jt >= first_jt) {
 #pragma unroll
                                     for (int r = 0; r < 4; ++r)
@@ -349,14 +384,14 @@ __device__ __forceinline__ void weights_mf_wave(
             // the tile column of the next panel first: its updates are the
             // ones the next column steps wait for
             const int J0n = (c0 + 4) >> 4;
-            const int jtn = ((J0n & 1) == WV && c0 + 4 < KP) ? (J0n >> 1) : -1;
+            const int jtn = (J0n % NW == WV && c0 + 4 < KP) ? J0n / NW : -1;
 #pragma unroll
             for (int pass = 0; pass < 2; ++pass) {
 #pragma unroll
-                for (int jt = 0; jt < 3; ++jt) {
+                for (int jt = 0; jt < NJT; ++jt) {
                     if (jt < first_jt) continue;
                     if ((pass == 0) != (jt == jtn)) continue;
-                    const int J = 2 * jt + WV;
+                    const int J = NW * jt + WV;
                     const int i0 = (J == J0) ? 4 * rc + 4 : 0;  // first trailing column in the tile
                     const double r0 = s_ub[jt][0][jl], r1 = s_ub[jt][1][jl];
                     const double r2 = s_ub[jt][2][jl], r3 = s_ub[jt][3][jl];
@@ -378,12 +413,16 @@ __device__ __forceinline__ void weights_mf_wave(
             lds_order();  // s_ub is rewritten at the next panel
         }
     }
-    // wavefront 1's flags to wavefront 0
     uint32_t fl = seg_all<kWave, OpOr>(flags, lane);
-    if (WV == 1 && lane == 0) *s_fl = fl;
-    __syncthreads();  // the rows of U and the flags are visible
-    if (WV != 0) return;
-    fl |= *s_fl;
+    if constexpr (NW > 1) {
+        // wavefront 1's flags to wavefront 0
+        if (WV == 1 && lane == 0) *s_fl = fl;
+        __syncthreads();  // the rows of U and the flags are visible
+        if (WV != 0) return;
+        fl |= *s_fl;
+    } else {
+        lds_order();
+    }
 
     // ---- back substitution over the rows of U in LDS (wavefront 0) ---------
     int ub[SL];
@@ -429,7 +468,8 @@ __device__ __forceinline__ void weights_mf_wave(
     if (lane == 0 && status) status[i] = good ? ok_code : st;
 }
 
-// One block (two wavefronts) computes stencil `t` of the row list.
+// One block (NW wavefronts) computes stencil `t` of the row list.
+template <int KP, int NFIX, int MFIX, int NW>
 __device__ __forceinline__ void weights_mf_body(
     const double *__restrict__ x, const double *__restrict__ y, int64_t n_nodes,
     const int32_t *__restrict__ nbr, int32_t k_stride, const int32_t *__restrict__ rows,
@@ -437,34 +477,44 @@ __device__ __forceinline__ void weights_mf_body(
     int64_t t, char *lds) {
     if (t >= n_rows) return;  // whole block idle
     const int64_t i = rows ? (int64_t)rows[t] : t;
-    if ((threadIdx.x >> 6) & 1)
-        weights_mf_wave<1>(x, y, n_nodes, nbr, k_stride, i, w, status, ok_code, lds);
+    if (NW > 1 && ((threadIdx.x >> 6) & 1))
+        weights_mf_wave<KP, NFIX, MFIX, NW, NW - 1>(x, y, n_nodes, nbr, k_stride, i, w, status,
+                                                   ok_code, lds);
     else
-        weights_mf_wave<0>(x, y, n_nodes, nbr, k_stride, i, w, status, ok_code, lds);
+        weights_mf_wave<KP, NFIX, MFIX, NW, 0>(x, y, n_nodes, nbr, k_stride, i, w, status,
+                                               ok_code, lds);
 }
 
-template <int KP>
-__global__ __launch_bounds__(2 * kWave)
-__attribute__((amdgpu_waves_per_eu(2))) void weights_mf_kernel(
+template <int KP, int NFIX, int MFIX>
+__host__ __device__ constexpr int mf_lds_bytes(int nw) {
+    constexpr int MM = (MFIX + 1) * (MFIX + 2) / 2;
+    constexpr int NT = (KP + 1 + 15) / 16;
+    return nw > 1 ? MfLds<KP, MM, NT, 2>::BYTES : MfLds<KP, MM, NT, 1>::BYTES;
+}
+
+template <int KP, int NFIX, int MFIX, int NW, int OCC>
+__global__ __launch_bounds__(NW * kWave)
+__attribute__((amdgpu_waves_per_eu(OCC))) void weights_mf_kernel(
     const double *__restrict__ x, const double *__restrict__ y, int64_t n_nodes,
     const int32_t *__restrict__ nbr, int32_t k_stride, const int32_t *__restrict__ rows,
     const int32_t *__restrict__ n_rows_dev, int64_t n_rows, double *__restrict__ w,
     int32_t *__restrict__ status, int32_t ok_code) {
-    static_assert(KP == MfLds::KP, "the blocked kernel is written for K = 84");
-    __shared__ __align__(16) char lds[MfLds::BYTES];
+    __shared__ __align__(16) char lds[mf_lds_bytes<KP, NFIX, MFIX>(NW)];
     if (n_rows_dev) n_rows = *n_rows_dev;
-    weights_mf_body(x, y, n_nodes, nbr, k_stride, rows, n_rows, w, status, ok_code,
-                    (int64_t)blockIdx.x, lds);
+    weights_mf_body<KP, NFIX, MFIX, NW>(x, y, n_nodes, nbr, k_stride, rows, n_rows, w, status,
+                                        ok_code, (int64_t)blockIdx.x, lds);
 }
 
+template <int KP, int NFIX, int MFIX, int NW, int OCC>
 inline int launch_mf(const double *x, const double *y, int64_t n_nodes, const int32_t *nbr,
                      int32_t k_stride, const int32_t *rows, const int32_t *n_rows_dev,
                      int64_t n_rows, double *w, int32_t *status, int32_t ok_code,
                      hipStream_t stream) {
     if (n_rows <= 0) return RBFFD_SUCCESS;
     if (n_rows > 0x7fffffff) return RBFFD_ERR_UNSUPPORTED;
-    hipLaunchKernelGGL(weights_mf_kernel<84>, dim3((unsigned)n_rows), dim3(2 * kWave), 0, stream, x, y,
-                       n_nodes, nbr, k_stride, rows, n_rows_dev, n_rows, w, status, ok_code);
+    hipLaunchKernelGGL((weights_mf_kernel<KP, NFIX, MFIX, NW, OCC>), dim3((unsigned)n_rows),
+                       dim3(NW * kWave), 0, stream, x, y, n_nodes, nbr, k_stride, rows,
+                       n_rows_dev, n_rows, w, status, ok_code);
     return last_launch_rc();
 }
 
