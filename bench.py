@@ -238,6 +238,8 @@ def main():
     }
 
     if not args.no_extras:
+        out["implicit_solve_unit_disk"] = extras_solve(torch, rb, nodes, dev, X, Y, B, U, F,
+                                                       ns, m, n)
         out["per_order_1M_square"] = extras_per_order(torch, rb, nodes, dev, stream)
         out["adjoint_annulus_200k_m4"] = extras_adjoint(torch, rb, nodes, dev, stream)
         out["time_loop_unit_disk"] = extras_time_loop(torch, rb, nodes, dev, stream)
@@ -332,6 +334,31 @@ def extras_per_order(torch, rb, nodes, dev, stream):
                             "fell_back": int((stmx == rb.FELL_BACK_FP64).sum().item()),
                             "max_rel_err_mixed_vs_fp64": err}
     return res
+
+
+def extras_solve(torch, rb, nodes, dev, X, Y, B, U, F, ns, m, n, rtol=1e-10):
+    """Implicit solve of the assembled Dirichlet Poisson system on the bench
+    disk (BiCGSTAB, rbffd_solve): wall time of the call (it synchronizes),
+    iterations, the true relative residual and the error against the
+    manufactured solution.  Bytes per iteration on the model of two SpMVs
+    (12 B per nonzero + 8 B gathered per nonzero + 16 B per row) and the
+    vector updates (14 vectors of 8 B per row)."""
+    nbr = rb.rbffd_knn(X, Y, n)
+    w, st, _ = rb.rbffd_weights(X, Y, nbr, m=m, n=n)
+    rp, col, val = rb.rbffd_assemble_csr(nbr, w, n=n, is_boundary=B)
+    b = torch.where(B == 1, U, F)
+    rb.rbffd_solve(rp, col, val, b, rtol=rtol)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, it, rr, info = rb.rbffd_solve(rp, col, val, b, rtol=rtol)
+    ms = 1e3 * (time.perf_counter() - t0)
+    N, nnz = ns.n_nodes, int(col.numel())
+    per_it = 2 * (20 * nnz + 16 * N) + 14 * 8 * N
+    return {"method": "BiCGSTAB, no preconditioner", "rtol": rtol, "iterations": it,
+            "info": info, "relres_true": rr, "ms": ms, "ms_per_iteration": ms / max(it, 1),
+            "model_bytes_per_iteration": per_it,
+            "model_gb_per_s": per_it * it / (ms * 1e-3) / 1e9,
+            "max_err_vs_exact": (x - U).abs().max().item(), "nnz": nnz}
 
 
 def extras_adjoint(torch, rb, nodes, dev, stream):

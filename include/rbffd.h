@@ -52,6 +52,12 @@ extern "C" {
 #define RBFFD_BAD_ORDER 6       /* per-node order not in {2,4,6} */
 
 /* ---- precision ---------------------------------------------------------- */
+/* outcome of rbffd_solve (its `info` output) */
+#define RBFFD_SOLVE_CONVERGED 0  /* ||b - W x|| <= rtol ||b|| by the recurrence */
+#define RBFFD_SOLVE_MAX_ITER 1   /* max_iter iterations without converging */
+#define RBFFD_SOLVE_BREAKDOWN 2  /* (r0, v) = 0, (r0, r) = 0 or omega = 0 */
+#define RBFFD_SOLVE_NONFINITE 3  /* a non-finite scalar (NaN or Inf in W, b, x) */
+
 #define RBFFD_FP64 0   /* FP64 assembly, factorisation and solves */
 #define RBFFD_MIXED 1  /* FP32 factorisation + FP64 iterative refinement */
 
@@ -222,6 +228,33 @@ int rbffd_time_steps(int64_t n_nodes, const int32_t *nbr, int32_t k_stride, int3
 int rbffd_spmv(int64_t n_rows, const int64_t *row_ptr, const int32_t *col,
                const double *val, const double *u, const double *f, double *y,
                void *stream);
+
+/* ==========================================================================
+ * Implicit solve of the assembled operator, W x = b: the steady Dirichlet
+ * Poisson problem of eq. (2) with the boundary rows of section IV (an
+ * extension the conclusions name).  W is a square CSR matrix as built by
+ * rbffd_assemble_csr (row_ptr [n_rows+1] int64, col int32, val FP64); b and
+ * x are [n_rows] FP64 device vectors; x holds the initial guess on entry and
+ * the solution on return.  Method: BiCGSTAB (van der Vorst 1992) without a
+ * preconditioner, stopped when the recurrence residual satisfies
+ * ||r|| <= rtol ||b|| or after max_iter iterations.  Dot products are
+ * reduced in a fixed order, so a call is reproducible bit for bit.
+ * Host outputs: iters (iterations run), relres = ||b - W x|| / ||b|| of the
+ * returned x (recomputed, not the recurrence value; ||b - W x|| when b = 0),
+ * info = RBFFD_SOLVE_*.  Unlike the other calls this one synchronizes the
+ * stream (it reads the convergence flag every 8 iterations), so it cannot
+ * be captured into a graph.  workspace: rbffd_solve_workspace_size bytes
+ * (six vectors and the reduction partials).
+ * Errors: RBFFD_ERR_ARG for null pointers, n_rows < 1, rtol < 0 or NaN,
+ * max_iter < 0; RBFFD_ERR_WORKSPACE for a short workspace.  A column
+ * outside [0, n_rows) makes its row NaN and the solve ends with
+ * RBFFD_SOLVE_NONFINITE.
+ * ======================================================================== */
+int rbffd_solve_workspace_size(int64_t n_rows, size_t *bytes /* host */);
+int rbffd_solve(int64_t n_rows, const int64_t *row_ptr, const int32_t *col, const double *val,
+                const double *b, double *x, double rtol, int32_t max_iter,
+                int32_t *iters /* host */, double *relres /* host */, int32_t *info /* host */,
+                void *workspace, size_t workspace_bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -14,7 +14,8 @@ itself: brute-force and k-d tree kNN, polynomial reproduction, the classical
 five-point Laplacian, scale/rigid-motion invariance, lattice symmetry,
 LAPACK and exact rational solves, the convergence order of the Poisson
 solution, central finite differences of the adjoint, and SciPy's CSR
-product.
+product.  ``solve`` (the assembled system's solution) is SciPy's direct
+solver itself, pinned by its residual and by the convergence order.
 """
 
 from __future__ import annotations
@@ -244,6 +245,19 @@ def spmv(row_ptr, col, val, u, f=None):
     y = np.empty(n)
     lib.oracle_spmv(n, _p(row_ptr), _p(col), _p(val), _p(u), _p(fz), _p(y))
     return y
+
+
+def solve(row_ptr, col, val, b):
+    """The solution of the assembled system W x = b (the steady Dirichlet
+    problem of eq. (2) with the boundary rows of section IV), by its plain
+    definition: a direct sparse LU solve (SciPy's SuperLU).  Any iterative
+    method the GPU runs approximates this vector."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spl
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    n = row_ptr.shape[0] - 1
+    A = sp.csc_matrix(sp.csr_matrix((_f64(val), _i32(col), row_ptr), shape=(n, n)))
+    return spl.spsolve(A, _f64(b))
 
 
 def time_steps(nbr, w, n: int, f, u0, dt: float, n_steps: int, is_boundary=None):

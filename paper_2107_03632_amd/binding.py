@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "librbffd.so")
 
 FP64, MIXED = 0, 1
 OK, SINGULAR, FELL_BACK_FP64, NONFINITE, BAD_INDEX, DUPLICATE, BAD_ORDER = range(7)
+SOLVE_CONVERGED, SOLVE_MAX_ITER, SOLVE_BREAKDOWN, SOLVE_NONFINITE = range(4)
 DEFAULT_N_FOR_ORDER = (12, 30, 56)
 
 _lock = threading.Lock()
@@ -58,6 +59,10 @@ def _load():
             "rbffd_time_steps_workspace_size": ([I64, I32, PSZ], ctypes.c_int),
             "rbffd_time_steps": ([I64, P, I32, I32, P, P, P, ctypes.c_double, I64, P, P, P, SZ,
                                   P], ctypes.c_int),
+            "rbffd_solve_workspace_size": ([I64, PSZ], ctypes.c_int),
+            "rbffd_solve": ([I64, P, P, P, P, P, ctypes.c_double, I32,
+                             ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
+                             ctypes.POINTER(ctypes.c_int32), P, SZ, P], ctypes.c_int),
             "rbffd_batch_tuning_set": ([P], ctypes.c_int),
             "rbffd_batch_tuning_get": ([P], ctypes.c_int),
         }
@@ -264,6 +269,27 @@ def rbffd_spmv(row_ptr, col, val, u, f=None, out=None):
     _check(lib.rbffd_spmv(n, _p(row_ptr), _p(col), _p(val), _p(u), _p(fz), _p(y),
                           _stream(u.device)), "rbffd_spmv")
     return y
+
+
+def rbffd_solve(row_ptr, col, val, b, x0=None, rtol: float = 1e-10, max_iter: int = 20000):
+    """Solve W x = b (CSR W, BiCGSTAB on the GPU).  Returns (x, iterations,
+    relative true residual ||b - W x|| / ||b||, info = SOLVE_*).  Synchronizes
+    the stream."""
+    lib = _load()
+    row_ptr = _dev(row_ptr, torch.int64, "row_ptr")
+    col = _dev(col, torch.int32, "col")
+    val = _dev(val, torch.float64, "val")
+    b = _dev(b, torch.float64, "b")
+    n = row_ptr.numel() - 1
+    if b.numel() != n:
+        raise ValueError(f"b has {b.numel()} entries for {n} rows")
+    x = torch.zeros_like(b) if x0 is None else _dev(x0, torch.float64, "x0").clone()
+    ws = _workspace(_size(lib.rbffd_solve_workspace_size, n), b.device)
+    it, rr, info = ctypes.c_int32(0), ctypes.c_double(0.0), ctypes.c_int32(0)
+    _check(lib.rbffd_solve(n, _p(row_ptr), _p(col), _p(val), _p(b), _p(x), float(rtol),
+                           int(max_iter), ctypes.byref(it), ctypes.byref(rr), ctypes.byref(info),
+                           _p(ws), ws.numel(), _stream(b.device)), "rbffd_solve")
+    return x, it.value, rr.value, info.value
 
 
 def rbffd_time_steps(nbr, w, n: int, f, u, dt: float, n_steps: int, is_boundary=None,

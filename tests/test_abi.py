@@ -29,7 +29,7 @@ def lib():
 def test_header_declares_the_boundary():
     names = declared()
     for fn in ["rbffd_knn", "rbffd_weights", "rbffd_weights_backward", "rbffd_assemble_csr",
-               "rbffd_spmv", "rbffd_time_steps"]:
+               "rbffd_spmv", "rbffd_time_steps", "rbffd_solve"]:
         assert fn in names
 
 
@@ -70,6 +70,17 @@ def test_argument_errors_before_any_launch(lib):
                                      ctypes.c_double, ctypes.c_int64, P, P, P, ctypes.c_size_t, P]
     assert lib.rbffd_time_steps(10, None, 12, 12, None, None, None, 1e-3, 1, None, None,
                                 None, 0, None) == -1
+    I32P, DP = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)
+    lib.rbffd_solve.argtypes = [ctypes.c_int64, P, P, P, P, P, ctypes.c_double, ctypes.c_int32,
+                                I32P, DP, I32P, P, ctypes.c_size_t, P]
+    it, rr, info = ctypes.c_int32(), ctypes.c_double(), ctypes.c_int32()
+    assert lib.rbffd_solve(10, None, None, None, None, None, 1e-10, 100, ctypes.byref(it),
+                           ctypes.byref(rr), ctypes.byref(info), None, 0, None) == -1
+    sz = ctypes.c_size_t(0)
+    lib.rbffd_solve_workspace_size.argtypes = [ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]
+    assert lib.rbffd_solve_workspace_size(1000, ctypes.byref(sz)) == 0
+    assert sz.value >= 6 * 1000 * 8
+    assert lib.rbffd_solve_workspace_size(0, ctypes.byref(sz)) == -1
 
 
 def test_product_path_never_imports_the_oracle():
