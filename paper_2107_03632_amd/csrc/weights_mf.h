@@ -54,7 +54,10 @@ __device__ __forceinline__ void lds_order() {
 }
 
 // LDS of one block: doubles first, then int32.  Panel buffers alternate
-// between consecutive panels when two wavefronts share them.
+// between consecutive panels when two wavefronts share them.  With one
+// wavefront the pivot rows of a panel's end overlay its panel buffer (read
+// out before the rows are written), which keeps K = 45 at 15 wavefronts
+// per CU.
 template <int KP, int MM, int NT, int NW>
 struct MfLds {
     static constexpr int NP = 16 * NT;
@@ -62,8 +65,9 @@ struct MfLds {
     static constexpr int NJT = NT / NW;             // tile columns per wavefront
     static constexpr int SZ = MsLds<KP, MM>::SZ;    // U triangle / assembly tables
     static constexpr int PAN = SZ;                  // [NPB][NP][5] panel, row layout (padded)
-    static constexpr int UB = PAN + NPB * NP * 5;   // [NW][NJT][4][16] pivot rows of a panel
-    static constexpr int DBL = UB + NW * NJT * 64;
+    static constexpr int UB = NW > 1 ? PAN + NPB * NP * 5 : PAN;  // [NW][NJT][4][16] pivot rows
+    static constexpr int DBL =
+        NW > 1 ? UB + NW * NJT * 64 : PAN + (NP * 5 > NJT * 64 ? NP * 5 : NJT * 64);
     static constexpr int REC = 0;                   // [NPB][4][2] pivot row, its position
     static constexpr int FL = 8 * NPB;              // flags of wavefront 1
     static constexpr int INTS = FL + 2;
@@ -345,6 +349,18 @@ __device__ __forceinline__ void weights_mf_wave(
         const int first_jt = (J0 % NW == WV) ? ((rc < 3) ? J0 / NW : J0 / NW + 1)
                                              : (J0 + 1) / NW;
         if (first_jt < NJT) {  // (a partial panel is the last: nothing trails it)
+            // multipliers of the panel's pivot rows in its earlier columns
+            double l11[4][3];
+#pragma unroll
+            for (int m2 = 1; m2 < 4; ++m2)
+#pragma unroll
+                for (int k2 = 0; k2 < m2; ++k2) l11[m2][k2] = s_pan[pb][pr[m2]][k2];
+            // B operands: lane (g, j) holds the multiplier of row 16 I + j in
+            // panel column c0 + g
+            double Bop[NT];
+#pragma unroll
+            for (int I = 0; I < NT; ++I) Bop[I] = s_pan[pb][16 * I + jl][g];
+            lds_order();  // (with one wavefront the rows below overlay the panel)
             // the panel's pivot rows, in every trailing tile column of this
             // wavefront, to LDS (one uniform branch per row)
 #pragma unroll
@@ -370,17 +386,6 @@ __device__ __forceinline__ void weights_mf_wave(
                 }
             }
             lds_order();
-            // multipliers of the panel's pivot rows in its earlier columns
-            double l11[4][3];
-#pragma unroll
-            for (int m2 = 1; m2 < 4; ++m2)
-#pragma unroll
-                for (int k2 = 0; k2 < m2; ++k2) l11[m2][k2] = s_pan[pb][pr[m2]][k2];
-            // B operands: lane (g, j) holds the multiplier of row 16 I + j in
-            // panel column c0 + g
-            double Bop[NT];
-#pragma unroll
-            for (int I = 0; I < NT; ++I) Bop[I] = s_pan[pb][16 * I + jl][g];
             // the tile column of the next panel first: its updates are the
             // ones the next column steps wait for
             const int J0n = (c0 + 4) >> 4;
