@@ -32,34 +32,6 @@ namespace wk {
 
 using lds_f64 = __attribute__((address_space(3))) double;
 
-#ifndef RBFFD_ROWS_BY_READLANE
-#define RBFFD_ROWS_BY_READLANE 1
-#endif
-// One stencil per wavefront: broadcast the pivot row with readlane (VALU,
-// scalar operands) instead of LDS reads by every lane.
-constexpr bool kRowsByReadlane = RBFFD_ROWS_BY_READLANE != 0;
-#ifndef RBFFD_LDS_EVERY
-#define RBFFD_LDS_EVERY 0
-#endif
-constexpr int kLdsEvery = RBFFD_LDS_EVERY;
-#ifndef RBFFD_ROWS_BY_DPP
-#define RBFFD_ROWS_BY_DPP 0
-#endif
-// One stencil per wavefront: four lanes read the pivot row from LDS and a
-// 64-bit DPP row_newbcast feeds the update (two VALU per entry, not three).
-constexpr bool kRowsByDpp = RBFFD_ROWS_BY_DPP != 0;
-
-// acc + nl * u, with u taken from the first lane of this lane's 16-lane row
-// (one v_fmac_f64 with a DPP row_newbcast operand).  The s_nop covers the
-// two wait states a DPP read needs after a VALU write of its source.
-__device__ __forceinline__ double fma_row_head(double nl, double u, double acc) {
-    asm("s_nop 1\n\tv_fmac_f64_dpp %0, %1, %2 row_newbcast:0 row_mask:0xf bank_mask:0xf"
-        : "+v"(acc)
-        : "v"(u), "v"(nl));
-    return acc;
-}
-
-
 template <int CTRL>
 __device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, false);
@@ -452,42 +424,14 @@ __device__ __forceinline__ void weights_ms_body(
         // further ahead, which bounds the registers they occupy while still
         // overlapping them with two chunks of updates (no instruction is
         // emitted for the tie).
-        if constexpr (GPB == 1 && SL == 1 && kRowsByDpp) {
-            // one stencil per wavefront: the first lane of each 16-lane row
-            // reads the pivot row from LDS; the update takes it from there
-            // with a 64-bit DPP row broadcast
-            const lds_f64 *up = (const lds_f64 *)u;
-            const bool head = (lane & 15) == 0;
-            const double nl = -lm[0];
-            constexpr int CH = 8;
-#pragma unroll
-            for (int q0 = c + 1; q0 <= KP; q0 += CH) {
-                double uq[CH];  // defined in the row heads only
-                if (head) {
-#pragma unroll
-                    for (int j = 0; j < CH; ++j)
-                        if (q0 + j <= KP) uq[j] = up[2 * (q0 + j)];
-                }
-#pragma unroll
-                for (int j = 0; j < CH; ++j) {
-                    const int q = q0 + j;
-                    if (q > KP) continue;
-                    if (q < KP) a[0][q] = fma_row_head(nl, uq[j], a[0][q]);
-                    else yv[0] = fma_row_head(nl, uq[j], yv[0]);
-                }
-            }
-        } else if constexpr (GPB == 1 && SL == 1 && kRowsByReadlane) {
+        if constexpr (GPB == 1 && SL == 1) {
             // one stencil per wavefront: the pivot row comes straight from
-            // the winning lane's registers into scalar registers
+            // the winning lane's registers into scalar registers (VALU
+            // readlane, scalar fma operands), not from LDS reads by every lane
             const int wl = __builtin_amdgcn_readfirstlane(win);
-            const lds_f64 *up = (const lds_f64 *)u;
 #pragma unroll
             for (int q = c + 1; q <= KP; ++q) {
-                // every kLdsEvery-th entry is read from the row in LDS, which
-                // balances the LDS pipe against the VALU (readlane)
-                const bool from_lds = kLdsEvery > 0 && q % (kLdsEvery > 0 ? kLdsEvery : 1) == kLdsEvery - 1;
-                const double uqv =
-                    from_lds ? (double)up[2 * q] : readlane_d(q < KP ? a[0][q] : yv[0], wl);
+                const double uqv = readlane_d(q < KP ? a[0][q] : yv[0], wl);
                 if (q < KP) a[0][q] = fma(-lm[0], uqv, a[0][q]);
                 else yv[0] = fma(-lm[0], uqv, yv[0]);
             }
