@@ -98,7 +98,11 @@ int rbffd_knn(const double *x, const double *y, int64_t n_nodes, int32_t k,
  *   M z  = rhs by LU with partial pivoting (first largest |entry| wins ties),
  *   w_ik = z_k / s^2   for k < n;   w_ik = 0 for n <= k < k_stride.
  * The FP64 path performs exactly this sequence of IEEE operations (the
- * elimination uses fma(-l, u, a) and the reciprocal of each pivot).
+ * elimination uses fma(-l, u, a) and the reciprocal of each pivot).  For
+ * (m, n) = (4, 30) and (6, 56) the elimination is blocked by four columns
+ * and the trailing updates run as FP64 matrix-core instructions, which
+ * apply the same fused updates in the same order, so the result is the
+ * same bits.
  *
  * Order: order == NULL -> every node uses (m, n), m in {2,4,6},
  *        (m+1)(m+2)/2 <= n <= k_stride, n + (m+1)(m+2)/2 <= 96.
