@@ -99,3 +99,29 @@ def test_pipeline_graph_capture_and_replay():
         torch.cuda.synchronize()
         same(captured, eager)
         same(other, eager)
+
+
+def test_batch_full_size_sampled():
+    # the 1M-node mixed-order square in the launch the benchmark times: every
+    # status clean, sampled rows equal to the oracle's weights bit for bit
+    ns = nodes.workload("square_1m_mixed")
+    X, Y, O = dev(ns.x), dev(ns.y), dev(ns.order)
+    NB = rb.rbffd_knn(X, Y, 56)
+    w, st, _ = rb.rbffd_weights(X, Y, NB, order=O)
+    torch.cuda.synchronize()
+    w, st, nbr = w.cpu().numpy(), st.cpu().numpy(), NB.cpu().numpy()
+    del X, Y, O, NB
+    print("mixed-order 1M: statuses", np.bincount(st), flush=True)
+    assert np.all(st == 0)
+    rows = np.unique(np.concatenate([np.arange(0, ns.n_nodes, 3331), [ns.n_nodes - 1]]))
+    nbr_ref = oracle.knn(ns.x, ns.y, 56, queries=rows)
+    assert np.array_equal(nbr[rows], nbr_ref)
+    full = np.zeros((ns.n_nodes, 56), dtype=np.int32)
+    full[rows] = nbr_ref
+    w_ref, st_ref = oracle.weights(ns.x, ns.y, full, order=ns.order, rows=rows)
+    assert np.all(st_ref == 0)
+    assert np.array_equal(w[rows], w_ref)
+    # zeros past each node's n
+    for m in (2, 4, 6):
+        sel = ns.order == m
+        assert np.all(w[sel][:, NFM[m]:] == 0.0)
