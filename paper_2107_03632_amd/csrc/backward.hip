@@ -11,9 +11,12 @@
 // scale s is held fixed: w does not depend on it).
 //
 // Kernels:
-//   1. adjoint_stencil: one block per stencil; the saved K x K factors are
-//      staged in LDS, the two triangular solves walk the columns (one row per
-//      lane), then each support lane evaluates its dL/du_k.  Per-slot
+//   1. adjoint_stencil (K <= 64): one wavefront per stencil; the saved
+//      K x K factors are staged in LDS, the right-hand side and solution
+//      stay in registers (lane p: row p) and the two triangular solves walk
+//      the columns, each column's value reaching the lanes by readlane
+//      (adjoint_stencil_blk for K > 64: two wavefronts, the vector in LDS);
+//      then each support lane evaluates its dL/du_k.  Per-slot
 //      contributions go to contrib[i][k]; the stencil's own term (minus the
 //      sum over its slots, reduced in a fixed order) to self[i].
 //   2. reverse adjacency of the supports (counting sort, then each node's
@@ -41,7 +44,8 @@ __device__ __forceinline__ void order_of(const int8_t *order, int m_u, int n_u, 
         return;
     }
     m = order[i];
-    n = (m == 2 || m == 4 || m == 6) ? t.n[m / 2 - 1] : 0;
+    // selects, not an index: a runtime index would put the table in scratch
+    n = m == 2 ? t.n[0] : (m == 4 ? t.n[1] : (m == 6 ? t.n[2] : 0));
 }
 
 // graded monomial order: j -> (a, b)
@@ -58,8 +62,153 @@ __device__ __forceinline__ double rep_pow(double u, int e) {
     return p;
 }
 
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Dynamic LDS: A[K][K] (saved factors), then v[K] (unused), mu[K], z[K],
+// ux[K], uy[K].  One wavefront (64 threads) per block, K <= 64 (two rows
+// per lane would also cover K <= 128).
+__global__ __launch_bounds__(64) void adjoint_stencil(
+    const double *__restrict__ x, const double *__restrict__ y, int64_t n_nodes,
+    const int32_t *__restrict__ nbr, int32_t k_stride, const int8_t *__restrict__ order,
+    int32_t m_u, int32_t n_u, BwdTable tab, const double *__restrict__ G,
+    const double *__restrict__ sv_lu, const double *__restrict__ sv_z,
+    const double *__restrict__ sv_s, const uint8_t *__restrict__ sv_perm, int32_t kmax,
+    const int32_t *__restrict__ status, double *__restrict__ contrib, double *__restrict__ self) {
+    extern __shared__ double lds[];
+    const int64_t i = blockIdx.x;
+    const int tid = threadIdx.x;
+    int m, n;
+    order_of(order, m_u, n_u, tab, i, m, n);
+    const int NM = (m + 1) * (m + 2) / 2;
+    const int K = n + NM;
+    const bool ok = n > 0 && (!status || status[i] == RBFFD_OK);
+    double *cst = contrib + i * (int64_t)k_stride * 2;
+    if (!ok) {  // failed stencil: contributes nothing
+        for (int k = tid; k < k_stride; k += blockDim.x) {
+            cst[2 * k] = 0.0;
+            cst[2 * k + 1] = 0.0;
+        }
+        if (tid == 0) {
+            self[2 * i] = 0.0;
+            self[2 * i + 1] = 0.0;
+        }
+        return;
+    }
+    double *A = lds;
+    double *v = A + K * K;
+    double *mu = v + K;
+    double *zs = mu + K;
+    double *ux = zs + K;
+    double *uy = ux + K;
+    __shared__ double red[2][64];
+
+    const double s = sv_s[i];
+    const double s2 = s * s;
+    const double *src = sv_lu + i * (int64_t)kmax * kmax;
+    for (int e = tid; e < K * K; e += blockDim.x) A[e] = src[e];
+    const double xi = x[i], yi = y[i];
+    double vr[2] = {0.0, 0.0};  // rows tid, tid + 64 of (P b), then of the solves
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int p = tid + 64 * q;
+        if (p >= K) continue;
+        zs[p] = sv_z[i * (int64_t)kmax + p];
+        // (P b)[p] = b[perm[p]], b = [G_i / s^2 ; 0]
+        const int r = sv_perm[i * (int64_t)kmax + p];
+        vr[q] = (r < n) ? G[i * (int64_t)k_stride + r] / s2 : 0.0;
+        if (p < n) {
+            const int32_t j = nbr[i * (int64_t)k_stride + p];
+            ux[p] = (x[j] - xi) / s;
+            uy[p] = (y[j] - yi) / s;
+        }
+    }
+    __syncthreads();
+    // forward substitution with unit L, column by column: v_p -= L_pc v_c
+    for (int c = 0; c < K; ++c) {
+        const double vc = readlane_f64(c < 64 ? vr[0] : vr[1], c & 63);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int p = tid + 64 * q;
+            if (p > c && p < K) vr[q] = fma(-A[p * K + c], vc, vr[q]);
+        }
+    }
+    // back substitution: mu_c = v_c * (1 / U_cc), then eliminate column c
+    for (int c = K - 1; c >= 0; --c) {
+        const double mc = readlane_f64(c < 64 ? vr[0] : vr[1], c & 63) * (1.0 / A[c * K + c]);
+        if (tid == 0) mu[c] = mc;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int p = tid + 64 * q;
+            if (p < c) vr[q] = fma(-A[p * K + c], mc, vr[q]);
+        }
+    }
+    __syncthreads();
+
+    // dL/du_k for the support slots
+    double sx = 0.0, sy = 0.0;
+    for (int k = tid; k < k_stride; k += blockDim.x) {
+        double gx = 0.0, gy = 0.0;
+        if (k < n && nbr[i * (int64_t)k_stride + k] != (int32_t)i) {
+            const double uxk = ux[k], uyk = uy[k], mk = mu[k], wk = zs[k];
+            const double rk = sqrt(uxk * uxk + uyk * uyk);
+            if (rk > 0.0) {
+                gx += 9.0 * mk * uxk / rk;
+                gy += 9.0 * mk * uyk / rk;
+            }
+            for (int l = 0; l < n; ++l) {
+                const double ex = uxk - ux[l];
+                const double ey = uyk - uy[l];
+                const double r = sqrt(ex * ex + ey * ey);
+                const double c = 3.0 * r * (mk * zs[l] + mu[l] * wk);
+                gx -= c * ex;
+                gy -= c * ey;
+            }
+            for (int j = 0; j < NM; ++j) {
+                int a, b;
+                mono_ab(j, a, b);
+                double dpx = 0.0, dpy = 0.0;
+                if (a > 0) dpx = (double)a * rep_pow(uxk, a - 1) * rep_pow(uyk, b);
+                if (b > 0) dpy = (double)b * rep_pow(uxk, a) * rep_pow(uyk, b - 1);
+                const double c = mk * zs[n + j] + wk * mu[n + j];
+                gx -= dpx * c;
+                gy -= dpy * c;
+            }
+            gx /= s;
+            gy /= s;
+        }
+        cst[2 * k] = gx;
+        cst[2 * k + 1] = gy;
+        sx += gx;
+        sy += gy;
+    }
+    // self term: minus the sum over the slots, reduced in a fixed order
+    red[0][tid] = sx;
+    red[1][tid] = sy;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if (tid < o) {
+            red[0][tid] += red[0][tid + o];
+            red[1][tid] += red[1][tid + o];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        self[2 * i] = -red[0][0];
+        self[2 * i + 1] = -red[1][0];
+    }
+}
+
+// The same for K > 64 with 128 threads (two wavefronts, so that a system of
+// K = 84 whose 59 KB of LDS allow two blocks per CU still has four
+// wavefronts there): the solves run through v[] in LDS with a block barrier
+// per column.  Same operations in the same order, so the same bits.
 // Dynamic LDS: A[K][K] (saved factors), then v[K], mu[K], z[K], ux[K], uy[K].
-__global__ __launch_bounds__(128) void adjoint_stencil(
+__global__ __launch_bounds__(128) void adjoint_stencil_blk(
     const double *__restrict__ x, const double *__restrict__ y, int64_t n_nodes,
     const int32_t *__restrict__ nbr, int32_t k_stride, const int8_t *__restrict__ order,
     int32_t m_u, int32_t n_u, BwdTable tab, const double *__restrict__ G,
@@ -323,14 +472,18 @@ extern "C" int rbffd_weights_backward(const double *x, const double *y, int64_t 
 
     const size_t lds = ((size_t)kmax * kmax + 5 * (size_t)kmax) * sizeof(double);
     if (lds > 65536) {  // systems above K = 88 need more than the default 64 KiB
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&adjoint_stencil),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&adjoint_stencil_blk),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return hip_rc(e);
     }
-    const int threads = kmax > 64 ? 128 : 64;
-    hipLaunchKernelGGL(adjoint_stencil, dim3((unsigned)n_nodes), dim3(threads), lds, s, x, y,
-                       n_nodes, nbr, k_stride, order, m, n, tab, grad_w, sv.lu, sv.z, sv.s,
-                       sv.perm, (int32_t)kmax, status, w.contrib, w.self);
+    if (kmax <= 64)
+        hipLaunchKernelGGL(adjoint_stencil, dim3((unsigned)n_nodes), dim3(64), lds, s, x, y,
+                           n_nodes, nbr, k_stride, order, m, n, tab, grad_w, sv.lu, sv.z, sv.s,
+                           sv.perm, (int32_t)kmax, status, w.contrib, w.self);
+    else
+        hipLaunchKernelGGL(adjoint_stencil_blk, dim3((unsigned)n_nodes), dim3(128), lds, s, x,
+                           y, n_nodes, nbr, k_stride, order, m, n, tab, grad_w, sv.lu, sv.z,
+                           sv.s, sv.perm, (int32_t)kmax, status, w.contrib, w.self);
     int rc = last_launch_rc();
     if (rc) return rc;
     if ((rc = fill_i32(w.cnt, 0, n_nodes + 1, s))) return rc;
