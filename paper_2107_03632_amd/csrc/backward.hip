@@ -109,8 +109,12 @@ __global__ __launch_bounds__(64) void adjoint_stencil(
 
     const double s = sv_s[i];
     const double s2 = s * s;
+    // the factors in pivot order: the saved row perm[p] is row p of PM = LU
     const double *src = sv_lu + i * (int64_t)kmax * kmax;
-    for (int e = tid; e < K * K; e += blockDim.x) A[e] = src[e];
+    for (int p = 0; p < K; ++p) {
+        const int r = sv_perm[i * (int64_t)kmax + p];
+        for (int q = tid; q < K; q += blockDim.x) A[p * K + q] = src[(int64_t)r * K + q];
+    }
     const double xi = x[i], yi = y[i];
     double vr[2] = {0.0, 0.0};  // rows tid, tid + 64 of (P b), then of the solves
 #pragma unroll
@@ -245,8 +249,12 @@ __global__ __launch_bounds__(128) void adjoint_stencil_blk(
 
     const double s = sv_s[i];
     const double s2 = s * s;
+    // the factors in pivot order: the saved row perm[p] is row p of PM = LU
     const double *src = sv_lu + i * (int64_t)kmax * kmax;
-    for (int e = tid; e < K * K; e += blockDim.x) A[e] = src[e];
+    for (int p = 0; p < K; ++p) {
+        const int r = sv_perm[i * (int64_t)kmax + p];
+        for (int q = tid; q < K; q += blockDim.x) A[p * K + q] = src[(int64_t)r * K + q];
+    }
     const double xi = x[i], yi = y[i];
     for (int p = tid; p < K; p += blockDim.x) {
         zs[p] = sv_z[i * (int64_t)kmax + p];

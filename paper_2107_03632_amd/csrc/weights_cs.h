@@ -270,19 +270,21 @@ __device__ __forceinline__ void weights_cs_wave(
     __syncthreads();  // the rows of U and the flags are visible
 
     if constexpr (SAVE) {
-        // this wavefront's columns of every row, in pivot order
+        // this wavefront's columns of every row, at the row's own index; the
+        // position of each row in perm
         const int64_t kk = (int64_t)sv_kmax * sv_kmax;
 #pragma unroll
         for (int s = 0; s < SL; ++s) {
-            if (pos[s] < K) {
-                double *dst = sv_lu + i * kk + (int64_t)pos[s] * K;
+            const int r = lane + SEG * s;
+            if (r < K) {
+                double *dst = sv_lu + i * kk + (int64_t)r * K;
 #pragma unroll
                 for (int jj = 0; jj < KC; ++jj) {
                     const int q = 2 * jj + wv;
                     if (q < K) dst[q] = a[s][jj];
                 }
-                if (wv == 0) sv_perm[i * (int64_t)sv_kmax + pos[s]] = (uint8_t)(lane + SEG * s);
             }
+            if (wv == 0 && pos[s] < K) sv_perm[i * (int64_t)sv_kmax + pos[s]] = (uint8_t)r;
         }
     }
     if (wv != 0) return;

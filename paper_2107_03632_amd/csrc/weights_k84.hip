@@ -13,7 +13,7 @@
 namespace rbffd {
 int weights_fp64_k84(const double *x, const double *y, int64_t n_nodes, const int32_t *nbr, int32_t k_stride, const int32_t *rows, const int32_t *n_rows_dev, int64_t n_rows, int n, int m, double *w, int32_t *status, const wk::SaveView &sv, int32_t ok_code, hipStream_t stream) {
     if (RBFFD_K84_MFMA && !sv.lu)
-        return wk::launch_mf<84, 56, 6, 2, 2>(x, y, n_nodes, nbr, k_stride, rows, n_rows_dev, n_rows, w, status, ok_code, stream);
+        return wk::launch_mf<84, 56, 6, 2, 2>(x, y, n_nodes, nbr, k_stride, rows, n_rows_dev, n_rows, w, status, sv, ok_code, stream);
     return wk::launch_cs<84, 56, 6>(x, y, n_nodes, nbr, k_stride, rows, n_rows_dev, n_rows, n, m, w, status, sv, ok_code, stream);
 }
 }  // namespace rbffd

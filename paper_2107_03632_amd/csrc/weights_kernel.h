@@ -446,15 +446,20 @@ __device__ __forceinline__ void weights_fp64_body(
     if (pos < n) wi[pos] = good ? zmine / (s * s) : __builtin_nan("");
     for (int q = n + r; q < k_stride; q += G) wi[q] = 0.0;
     if (r == 0 && status) status[i] = good ? ok_code : st;
-    if (sv_lu && r < KP && pos < K) {
+    if (sv_lu) {
+        // row r of the factors at row r; the position of each row in perm
         const int64_t kk = (int64_t)sv_kmax * sv_kmax;
-        double *dst = sv_lu + i * kk + (int64_t)pos * K;
+        if (r < K) {
+            double *dst = sv_lu + i * kk + (int64_t)r * K;
 #pragma unroll
-        for (int q = 0; q < KP; ++q)
-            if (q < K) dst[q] = a[q];
-        sv_z[i * (int64_t)sv_kmax + pos] = zmine;
-        sv_perm[i * (int64_t)sv_kmax + pos] = (uint8_t)r;
-        if (pos == 0) sv_s[i] = s;
+            for (int q = 0; q < KP; ++q)
+                if (q < K) dst[q] = a[q];
+        }
+        if (r < KP && pos < K) {
+            sv_z[i * (int64_t)sv_kmax + pos] = zmine;
+            sv_perm[i * (int64_t)sv_kmax + pos] = (uint8_t)r;
+            if (pos == 0) sv_s[i] = s;
+        }
     }
 }
 

@@ -74,11 +74,16 @@ struct MfLds {
     static constexpr int BYTES = 8 * DBL + 4 * INTS;
 };
 
-template <int KP, int NFIX, int MFIX, int NW, int WV>
+// SAVE (one wavefront per stencil only) also writes the factors for the
+// adjoint: row r of the factors (its multipliers left of its final
+// position, its row of U from there on) at row r, the row at each position,
+// the unit-scale solution z and the scale s.
+template <int KP, int NFIX, int MFIX, int NW, int WV, bool SAVE>
 __device__ __forceinline__ void weights_mf_wave(
     const double *__restrict__ x, const double *__restrict__ y, int64_t n_nodes,
     const int32_t *__restrict__ nbr, int32_t k_stride, int64_t i, double *__restrict__ w,
-    int32_t *__restrict__ status, int32_t ok_code, char *lds) {
+    int32_t *__restrict__ status, const SaveView &sv, int32_t ok_code, char *lds) {
+    static_assert(!SAVE || NW == 1, "the factors are saved by the one-wavefront instance");
     constexpr int MM = (MFIX + 1) * (MFIX + 2) / 2, n = NFIX, K = NFIX + MM;
     static_assert(K == KP, "no identity padding in the blocked kernel");
     constexpr int NT = (KP + 1 + 15) / 16;  // tiles per dimension (rhs included)
@@ -237,6 +242,9 @@ __device__ __forceinline__ void weights_mf_wave(
 #pragma unroll
                 for (int j = 0; j < 4; ++j) pc[s][j] = r < NP ? s_pan[pb][r < NP ? r : 0][j] : 0.0;
             }
+            uint32_t updm[SL];  // bit j: the row took a multiplier in column c0 + j
+#pragma unroll
+            for (int s = 0; s < SL; ++s) updm[s] = 0u;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 if (k >= nk) break;
@@ -289,6 +297,7 @@ __device__ __forceinline__ void weights_mf_wave(
                     const bool upd = !done[s] && !(lane == win && bs == s);
                     const double lmv = upd ? pc[s][k] * inv : 0.0;
                     pc[s][k] = lmv;
+                    if constexpr (SAVE) updm[s] |= (upd ? 1u : 0u) << k;
 #pragma unroll
                     for (int j = k + 1; j < 4; ++j)
                         if (c0 + j <= KP) pc[s][j] = fma(-lmv, uq[j], pc[s][j]);
@@ -314,6 +323,15 @@ __device__ __forceinline__ void weights_mf_wave(
                 if (r < NP) {
 #pragma unroll
                     for (int j = 0; j < 4; ++j) s_pan[pb][r][j] = pc[s][j];
+                }
+                if constexpr (SAVE) {
+                    // the multipliers of L, where the row took them
+                    if (r < K) {
+                        double *dst = sv.lu + i * (int64_t)sv.kmax * sv.kmax + (int64_t)r * K;
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            if (j < nk && ((updm[s] >> j) & 1u)) dst[c0 + j] = pc[s][j];
+                    }
                 }
             }
         }
@@ -471,23 +489,44 @@ __device__ __forceinline__ void weights_mf_wave(
     }
     for (int q = n + lane; q < k_stride; q += kWave) wi[q] = 0.0;
     if (lane == 0 && status) status[i] = good ? ok_code : st;
+    if constexpr (SAVE) {
+        // the row at each position (in the free panel buffer), then each
+        // row of U at its row's index, lanes along the columns
+        int32_t *s_row = reinterpret_cast<int32_t *>(s_pan);
+#pragma unroll
+        for (int s = 0; s < SL; ++s)
+            if (pos[s] < K) s_row[pos[s]] = lane + kWave * s;
+        lds_order();
+        double *lu = sv.lu + i * (int64_t)sv.kmax * sv.kmax;
+        for (int p = 0; p < K; ++p) {
+            const int r = __builtin_amdgcn_readfirstlane(s_row[p]);
+            for (int q = p + lane; q < K; q += kWave) lu[(int64_t)r * K + q] = sU[L::ubase(p) + 2 * q];
+            if (lane == 0) sv.perm[i * (int64_t)sv.kmax + p] = (uint8_t)r;
+        }
+#pragma unroll
+        for (int s = 0; s < SL; ++s) {
+            const int c = lane + kWave * s;
+            if (c < K) sv.z[i * (int64_t)sv.kmax + c] = zm[s];
+        }
+        if (lane == 0) sv.s[i] = sc;
+    }
 }
 
 // One block (NW wavefronts) computes stencil `t` of the row list.
-template <int KP, int NFIX, int MFIX, int NW>
+template <int KP, int NFIX, int MFIX, int NW, bool SAVE = false>
 __device__ __forceinline__ void weights_mf_body(
     const double *__restrict__ x, const double *__restrict__ y, int64_t n_nodes,
     const int32_t *__restrict__ nbr, int32_t k_stride, const int32_t *__restrict__ rows,
     int64_t n_rows, double *__restrict__ w, int32_t *__restrict__ status, int32_t ok_code,
-    int64_t t, char *lds) {
+    int64_t t, char *lds, const SaveView &sv = SaveView{}) {
     if (t >= n_rows) return;  // whole block idle
     const int64_t i = rows ? (int64_t)rows[t] : t;
     if (NW > 1 && ((threadIdx.x >> 6) & 1))
-        weights_mf_wave<KP, NFIX, MFIX, NW, NW - 1>(x, y, n_nodes, nbr, k_stride, i, w, status,
-                                                   ok_code, lds);
+        weights_mf_wave<KP, NFIX, MFIX, NW, NW - 1, SAVE>(x, y, n_nodes, nbr, k_stride, i, w,
+                                                         status, sv, ok_code, lds);
     else
-        weights_mf_wave<KP, NFIX, MFIX, NW, 0>(x, y, n_nodes, nbr, k_stride, i, w, status,
-                                               ok_code, lds);
+        weights_mf_wave<KP, NFIX, MFIX, NW, 0, SAVE>(x, y, n_nodes, nbr, k_stride, i, w, status,
+                                                     sv, ok_code, lds);
 }
 
 template <int KP, int NFIX, int MFIX>
@@ -497,29 +536,41 @@ __host__ __device__ constexpr int mf_lds_bytes(int nw) {
     return nw > 1 ? MfLds<KP, MM, NT, 2>::BYTES : MfLds<KP, MM, NT, 1>::BYTES;
 }
 
-template <int KP, int NFIX, int MFIX, int NW, int OCC>
+template <int KP, int NFIX, int MFIX, int NW, int OCC, bool SAVE>
 __global__ __launch_bounds__(NW * kWave)
 __attribute__((amdgpu_waves_per_eu(OCC))) void weights_mf_kernel(
     const double *__restrict__ x, const double *__restrict__ y, int64_t n_nodes,
     const int32_t *__restrict__ nbr, int32_t k_stride, const int32_t *__restrict__ rows,
     const int32_t *__restrict__ n_rows_dev, int64_t n_rows, double *__restrict__ w,
-    int32_t *__restrict__ status, int32_t ok_code) {
+    int32_t *__restrict__ status, SaveView sv, int32_t ok_code) {
     __shared__ __align__(16) char lds[mf_lds_bytes<KP, NFIX, MFIX>(NW)];
     if (n_rows_dev) n_rows = *n_rows_dev;
-    weights_mf_body<KP, NFIX, MFIX, NW>(x, y, n_nodes, nbr, k_stride, rows, n_rows, w, status,
-                                        ok_code, (int64_t)blockIdx.x, lds);
+    weights_mf_body<KP, NFIX, MFIX, NW, SAVE>(x, y, n_nodes, nbr, k_stride, rows, n_rows, w,
+                                              status, ok_code, (int64_t)blockIdx.x, lds, sv);
 }
 
+// sv.lu set: the saving instance (one wavefront per stencil only).
 template <int KP, int NFIX, int MFIX, int NW, int OCC>
 inline int launch_mf(const double *x, const double *y, int64_t n_nodes, const int32_t *nbr,
                      int32_t k_stride, const int32_t *rows, const int32_t *n_rows_dev,
-                     int64_t n_rows, double *w, int32_t *status, int32_t ok_code,
-                     hipStream_t stream) {
+                     int64_t n_rows, double *w, int32_t *status, const SaveView &sv,
+                     int32_t ok_code, hipStream_t stream) {
     if (n_rows <= 0) return RBFFD_SUCCESS;
     if (n_rows > 0x7fffffff) return RBFFD_ERR_UNSUPPORTED;
-    hipLaunchKernelGGL((weights_mf_kernel<KP, NFIX, MFIX, NW, OCC>), dim3((unsigned)n_rows),
-                       dim3(NW * kWave), 0, stream, x, y, n_nodes, nbr, k_stride, rows,
-                       n_rows_dev, n_rows, w, status, ok_code);
+    if constexpr (NW == 1) {
+        if (sv.lu) {
+            hipLaunchKernelGGL((weights_mf_kernel<KP, NFIX, MFIX, NW, OCC, true>),
+                               dim3((unsigned)n_rows), dim3(NW * kWave), 0, stream, x, y,
+                               n_nodes, nbr, k_stride, rows, n_rows_dev, n_rows, w, status, sv,
+                               ok_code);
+            return last_launch_rc();
+        }
+    } else {
+        if (sv.lu) return RBFFD_ERR_UNSUPPORTED;
+    }
+    hipLaunchKernelGGL((weights_mf_kernel<KP, NFIX, MFIX, NW, OCC, false>),
+                       dim3((unsigned)n_rows), dim3(NW * kWave), 0, stream, x, y, n_nodes, nbr,
+                       k_stride, rows, n_rows_dev, n_rows, w, status, SaveView{}, ok_code);
     return last_launch_rc();
 }
 

@@ -340,7 +340,7 @@ __device__ __forceinline__ void weights_ms_body(
         pos[s] = l0 + SEG * s;
         done[s] = pos[s] >= KP;
     }
-    const uint64_t segmask = SEG == 64 ? ~0ull : ((1ull << SEG) - 1ull);
+    const uint64_t segmask = SEG == 64 ? ~0ull : ((1ull << (SEG & 63)) - 1ull);
     const int segbase = g * SEG;
 #pragma unroll
     for (int c = 0; c < KP; ++c) {
@@ -538,15 +538,17 @@ __device__ __forceinline__ void weights_ms_body(
         const int64_t kk = (int64_t)sv_kmax * sv_kmax;
 #pragma unroll
         for (int s = 0; s < SL; ++s) {
-            if (pos[s] < K) {
-                double *dst = sv_lu + i * kk + (int64_t)pos[s] * K;
+            // row r of the factors (its multipliers left of its position,
+            // U from there on) at row r; the position of each row in perm
+            const int r = l0 + SEG * s;
+            if (r < K) {
+                double *dst = sv_lu + i * kk + (int64_t)r * K;
 #pragma unroll
                 for (int q = 0; q < KP; ++q)
                     if (q < K) dst[q] = a[s][q];
-                sv_perm[i * (int64_t)sv_kmax + pos[s]] = (uint8_t)(l0 + SEG * s);
+                sv_z[i * (int64_t)sv_kmax + r] = zm[s];
             }
-            const int r = l0 + SEG * s;
-            if (r < K) sv_z[i * (int64_t)sv_kmax + r] = zm[s];
+            if (pos[s] < K) sv_perm[i * (int64_t)sv_kmax + pos[s]] = (uint8_t)r;
         }
         if (l0 == 0) sv_s[i] = sc;
     }
