@@ -11,11 +11,12 @@
 // scale s is held fixed: w does not depend on it).
 //
 // Kernels:
-//   1. adjoint_stencil (K <= 64): one wavefront per stencil; the saved
-//      K x K factors are staged in LDS, the right-hand side and solution
-//      stay in registers (lane p: row p) and the two triangular solves walk
-//      the columns, each column's value reaching the lanes by readlane
-//      (adjoint_stencil_blk for K > 64: two wavefronts, the vector in LDS);
+//   1. adjoint_stencil (K <= 64): one wavefront per stencil; lane p reads
+//      row p of the saved factors (pivot order) straight from memory, the
+//      right-hand side and solution stay in registers, and the two
+//      triangular solves walk the columns, each column's value reaching the
+//      lanes by readlane (adjoint_stencil_blk for K > 64: two wavefronts,
+//      the factors staged in LDS, the vector in LDS);
 //      then each support lane evaluates its dL/du_k.  Per-slot
 //      contributions go to contrib[i][k]; the stencil's own term (minus the
 //      sum over its slots, reduced in a fixed order) to self[i].
@@ -69,9 +70,10 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
     return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
-// Dynamic LDS: A[K][K] (saved factors), then v[K] (unused), mu[K], z[K],
-// ux[K], uy[K].  One wavefront (64 threads) per block, K <= 64 (two rows
-// per lane would also cover K <= 128).
+// Dynamic LDS: mu[K], z[K], ux[K], uy[K].  One wavefront (64 threads) per
+// block, K <= 64: lane p takes position p, reads its saved row of the
+// factors straight from memory (each element once) and keeps its entry of
+// the right-hand side and of the solution in a register.
 __global__ __launch_bounds__(64) void adjoint_stencil(
     const double *__restrict__ x, const double *__restrict__ y, int64_t n_nodes,
     const int32_t *__restrict__ nbr, int32_t k_stride, const int8_t *__restrict__ order,
@@ -99,9 +101,7 @@ __global__ __launch_bounds__(64) void adjoint_stencil(
         }
         return;
     }
-    double *A = lds;
-    double *v = A + K * K;
-    double *mu = v + K;
+    double *mu = lds;
     double *zs = mu + K;
     double *ux = zs + K;
     double *uy = ux + K;
@@ -109,22 +109,19 @@ __global__ __launch_bounds__(64) void adjoint_stencil(
 
     const double s = sv_s[i];
     const double s2 = s * s;
-    // the factors in pivot order: the saved row perm[p] is row p of PM = LU
+    // lane p: row p of PM = LU is the saved row perm[p]
     const double *src = sv_lu + i * (int64_t)kmax * kmax;
-    for (int p = 0; p < K; ++p) {
-        const int r = sv_perm[i * (int64_t)kmax + p];
-        for (int q = tid; q < K; q += blockDim.x) A[p * K + q] = src[(int64_t)r * K + q];
-    }
+    const int p = tid;
+    const int rp = p < K ? sv_perm[i * (int64_t)kmax + p] : 0;
+    const double *rowp = src + (int64_t)rp * K;
     const double xi = x[i], yi = y[i];
-    double vr[2] = {0.0, 0.0};  // rows tid, tid + 64 of (P b), then of the solves
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const int p = tid + 64 * q;
-        if (p >= K) continue;
+    double vr = 0.0;   // (P b)_p, then the solves' entry p
+    double upp = 1.0;  // U_pp
+    if (p < K) {
         zs[p] = sv_z[i * (int64_t)kmax + p];
         // (P b)[p] = b[perm[p]], b = [G_i / s^2 ; 0]
-        const int r = sv_perm[i * (int64_t)kmax + p];
-        vr[q] = (r < n) ? G[i * (int64_t)k_stride + r] / s2 : 0.0;
+        vr = (rp < n) ? G[i * (int64_t)k_stride + rp] / s2 : 0.0;
+        upp = rowp[p];
         if (p < n) {
             const int32_t j = nbr[i * (int64_t)k_stride + p];
             ux[p] = (x[j] - xi) / s;
@@ -134,22 +131,14 @@ __global__ __launch_bounds__(64) void adjoint_stencil(
     __syncthreads();
     // forward substitution with unit L, column by column: v_p -= L_pc v_c
     for (int c = 0; c < K; ++c) {
-        const double vc = readlane_f64(c < 64 ? vr[0] : vr[1], c & 63);
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int p = tid + 64 * q;
-            if (p > c && p < K) vr[q] = fma(-A[p * K + c], vc, vr[q]);
-        }
+        const double vc = readlane_f64(vr, c);
+        if (p > c && p < K) vr = fma(-rowp[c], vc, vr);
     }
     // back substitution: mu_c = v_c * (1 / U_cc), then eliminate column c
     for (int c = K - 1; c >= 0; --c) {
-        const double mc = readlane_f64(c < 64 ? vr[0] : vr[1], c & 63) * (1.0 / A[c * K + c]);
+        const double mc = readlane_f64(vr, c) * (1.0 / readlane_f64(upp, c));
         if (tid == 0) mu[c] = mc;
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int p = tid + 64 * q;
-            if (p < c) vr[q] = fma(-A[p * K + c], mc, vr[q]);
-        }
+        if (p < c) vr = fma(-rowp[c], mc, vr);
     }
     __syncthreads();
 
@@ -250,10 +239,14 @@ __global__ __launch_bounds__(128) void adjoint_stencil_blk(
     const double s = sv_s[i];
     const double s2 = s * s;
     // the factors in pivot order: the saved row perm[p] is row p of PM = LU
+    // (the row index of each position through LDS, then one flat copy)
     const double *src = sv_lu + i * (int64_t)kmax * kmax;
-    for (int p = 0; p < K; ++p) {
-        const int r = sv_perm[i * (int64_t)kmax + p];
-        for (int q = tid; q < K; q += blockDim.x) A[p * K + q] = src[(int64_t)r * K + q];
+    __shared__ int32_t s_perm[128];
+    for (int p = tid; p < K; p += blockDim.x) s_perm[p] = sv_perm[i * (int64_t)kmax + p];
+    __syncthreads();
+    for (int e = tid; e < K * K; e += blockDim.x) {
+        const int p = e / K, q = e - p * K;
+        A[e] = src[(int64_t)s_perm[p] * K + q];
     }
     const double xi = x[i], yi = y[i];
     for (int p = tid; p < K; p += blockDim.x) {
@@ -485,7 +478,8 @@ extern "C" int rbffd_weights_backward(const double *x, const double *y, int64_t 
         if (e != hipSuccess) return hip_rc(e);
     }
     if (kmax <= 64)
-        hipLaunchKernelGGL(adjoint_stencil, dim3((unsigned)n_nodes), dim3(64), lds, s, x, y,
+        hipLaunchKernelGGL(adjoint_stencil, dim3((unsigned)n_nodes), dim3(64),
+                           4 * (size_t)kmax * sizeof(double), s, x, y,
                            n_nodes, nbr, k_stride, order, m, n, tab, grad_w, sv.lu, sv.z, sv.s,
                            sv.perm, (int32_t)kmax, status, w.contrib, w.self);
     else
