@@ -60,7 +60,7 @@ WEIGHTS_SOURCES = ["paper_2107_03632_amd/csrc/common.h",
                    "paper_2107_03632_amd/csrc/weights_ms.h",
                    "paper_2107_03632_amd/csrc/weights_mf.h",
                    "paper_2107_03632_amd/csrc/weights_k45.hip"]
-WEIGHTS_KERNEL = "weights_mf_kernel<45, 30, 4, 1, 4>"
+WEIGHTS_KERNEL = "weights_mf_kernel<45, 30, 4, 1, 4, false>"
 
 
 def read_traffic(kernel_tag: str):
