@@ -67,6 +67,8 @@ def _load():
             lib.oracle_lu_solve.restype = None
             lib.oracle_weights.argtypes = [I64, P, P, P, I32, P, I32, I32, P,
                                            P, I64, P, P]
+            lib.oracle_weights_op.argtypes = [I64, P, P, P, I32, P, I32, I32, P,
+                                              P, I64, I32, P, P]
             lib.oracle_weights_mixed.argtypes = [I64, P, P, P, I32, P, I32, I32, P,
                                                  P, I64, P, P, P]
             lib.oracle_adjoint.argtypes = [I64, P, P, P, I32, P, I32, I32, P,
@@ -171,6 +173,28 @@ def weights(x, y, nbr, m: int | None = None, n: int | None = None, order=None,
                             _p(nfm), _p(r), nr, _p(w), _p(st))
     if rc != 0:
         raise ValueError(f"oracle_weights: error {rc}")
+    return w, st
+
+
+LAPLACIAN, D_DX, D_DY = 0, 1, 2
+
+
+def weights_op(x, y, nbr, m: int, n: int, op: int, rows=None):
+    """Weights of eq. (1) for the operator op (LAPLACIAN, D_DX, D_DY: the
+    right-hand side [L phi_k; L p_j] of that operator at the centre), uniform
+    (m, n).  Returns (w [rows, k], status [rows])."""
+    lib = _load()
+    x, y, nbr = _f64(x), _f64(y), _i32(nbr)
+    _check_supports(x, y, nbr)
+    N, ks = x.shape[0], nbr.shape[1]
+    r = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    nr = N if r is None else r.shape[0]
+    w = np.empty((nr, ks))
+    st = np.empty(nr, dtype=np.int32)
+    rc = lib.oracle_weights_op(N, _p(x), _p(y), _p(nbr), ks, None, m, n, None, _p(r), nr,
+                               int(op), _p(w), _p(st))
+    if rc != 0:
+        raise ValueError(f"oracle_weights_op: error {rc}")
     return w, st
 
 

@@ -173,13 +173,36 @@ static void monomials_at(int m, double u, double v, double *out)
  *   rhs_k     = 9 * sqrt(fl(fl(u_kx^2) + fl(u_ky^2)))     (lap r^3 = 9 r in 2-D)
  *   rhs_{n+j} = lap p_j(0) = 2 for x^2 and y^2, else 0
  */
+/*
+ * The same for other operators L (the extension to further operators of the
+ * conclusions; eq. (1) changes only in its right-hand side [L phi_k; L p_j]):
+ *   op 0: Laplacian, as above
+ *   op 1: d/dx.  The r^3 of node k, differentiated at the centre (where the
+ *         offset variable is 0) in unit-scale coordinates: 3 |0 - u_k|
+ *         (0 - u_kx), computed as -3 * sqrt(fl(fl(u_kx^2) + fl(u_ky^2))) * u_kx
+ *         (left to right); rhs_{n+j} = d/dx p_j(0) = 1 for p = x, else 0
+ *   op 2: d/dy, likewise with u_ky and p = y
+ * The weights are then z_k / s^2 for op 0 and z_k / s for ops 1 and 2
+ * (a first derivative scales with 1/s).
+ */
+int oracle_assemble_op(int64_t n_nodes, const double *x, const double *y,
+                       int64_t i, const int32_t *idx, int n, int m, int op,
+                       double *M, double *rhs, double *s_out);
+
 int oracle_assemble(int64_t n_nodes, const double *x, const double *y,
                     int64_t i, const int32_t *idx, int n, int m,
                     double *M, double *rhs, double *s_out)
 {
+    return oracle_assemble_op(n_nodes, x, y, i, idx, n, m, 0, M, rhs, s_out);
+}
+
+int oracle_assemble_op(int64_t n_nodes, const double *x, const double *y,
+                       int64_t i, const int32_t *idx, int n, int m, int op,
+                       double *M, double *rhs, double *s_out)
+{
     const int NM = n_monomials(m);
     const int K = n + NM;
-    if (m < 0 || m > 12 || n < 1 || n > 1024)
+    if (m < 0 || m > 12 || n < 1 || n > 1024 || op < 0 || op > 2)
         return OR_EARG;
     for (int k = 0; k < n; ++k)
         if (idx[k] < 0 || (int64_t)idx[k] >= n_nodes || i < 0 || i >= n_nodes)
@@ -236,12 +259,21 @@ int oracle_assemble(int64_t n_nodes, const double *x, const double *y,
             M[(n + j) * K + k] = pk[j];   /* P^T */
         }
         double r0 = ux[k] * ux[k] + uy[k] * uy[k];
-        rhs[k] = 9.0 * sqrt(r0);
+        if (op == 0)
+            rhs[k] = 9.0 * sqrt(r0);
+        else
+            rhs[k] = -3.0 * sqrt(r0) * (op == 1 ? ux[k] : uy[k]);
     }
     int ea[136], eb[136];
     monomial_exponents(m, ea, eb);
-    for (int j = 0; j < NM; ++j)
-        rhs[n + j] = ((ea[j] == 2 && eb[j] == 0) || (ea[j] == 0 && eb[j] == 2)) ? 2.0 : 0.0;
+    for (int j = 0; j < NM; ++j) {
+        if (op == 0)
+            rhs[n + j] = ((ea[j] == 2 && eb[j] == 0) || (ea[j] == 0 && eb[j] == 2)) ? 2.0 : 0.0;
+        else if (op == 1)
+            rhs[n + j] = (ea[j] == 1 && eb[j] == 0) ? 1.0 : 0.0;
+        else
+            rhs[n + j] = (ea[j] == 0 && eb[j] == 1) ? 1.0 : 0.0;
+    }
     free(ux);
     if (dup)
         return OR_DUPLICATE;
@@ -339,12 +371,12 @@ static int support_of(const int8_t *order, int32_t m_uniform, int32_t n_uniform,
 
 /* One stencil: z (K) and s.  Returns the status. */
 static int stencil_solve(int64_t n_nodes, const double *x, const double *y,
-                         int64_t i, const int32_t *idx, int n, int m,
+                         int64_t i, const int32_t *idx, int n, int m, int op,
                          double *M, double *z, int32_t *perm, double *dinv,
                          double *s)
 {
     const int K = n + n_monomials(m);
-    int st = oracle_assemble(n_nodes, x, y, i, idx, n, m, M, z, s);
+    int st = oracle_assemble_op(n_nodes, x, y, i, idx, n, m, op, M, z, s);
     if (st != OR_OK)
         return st;
     st = oracle_lu(K, M, perm, dinv);
@@ -365,11 +397,41 @@ static int stencil_solve(int64_t n_nodes, const double *x, const double *y,
  * The order comes from order[i] (m in {2,4,6}, n = n_for_m[m/2-1]) or, when
  * order is NULL, from (m_uniform, n_uniform).
  */
+static int weights_any(int64_t n_nodes, const double *x, const double *y,
+                       const int32_t *nbr, int32_t k_stride,
+                       const int8_t *order, int32_t m_uniform, int32_t n_uniform,
+                       const int32_t *n_for_m, const int64_t *rows, int64_t n_rows,
+                       int op, double *w, int32_t *status);
+
 int oracle_weights(int64_t n_nodes, const double *x, const double *y,
                    const int32_t *nbr, int32_t k_stride,
                    const int8_t *order, int32_t m_uniform, int32_t n_uniform,
                    const int32_t *n_for_m, const int64_t *rows, int64_t n_rows,
                    double *w, int32_t *status)
+{
+    return weights_any(n_nodes, x, y, nbr, k_stride, order, m_uniform, n_uniform, n_for_m,
+                       rows, n_rows, 0, w, status);
+}
+
+/* The weights of eq. (1) for the operator op of oracle_assemble_op (0, 1, 2);
+ * otherwise as oracle_weights. */
+int oracle_weights_op(int64_t n_nodes, const double *x, const double *y,
+                      const int32_t *nbr, int32_t k_stride,
+                      const int8_t *order, int32_t m_uniform, int32_t n_uniform,
+                      const int32_t *n_for_m, const int64_t *rows, int64_t n_rows,
+                      int32_t op, double *w, int32_t *status)
+{
+    if (op < 0 || op > 2)
+        return OR_EARG;
+    return weights_any(n_nodes, x, y, nbr, k_stride, order, m_uniform, n_uniform, n_for_m,
+                       rows, n_rows, op, w, status);
+}
+
+static int weights_any(int64_t n_nodes, const double *x, const double *y,
+                       const int32_t *nbr, int32_t k_stride,
+                       const int8_t *order, int32_t m_uniform, int32_t n_uniform,
+                       const int32_t *n_for_m, const int64_t *rows, int64_t n_rows,
+                       int op, double *w, int32_t *status)
 {
     int kmax = 0;
     if (order) {
@@ -405,12 +467,12 @@ int oracle_weights(int64_t n_nodes, const double *x, const double *y,
         }
         double s = 0.0;
         int st = stencil_solve(n_nodes, x, y, i, nbr + i * (int64_t)k_stride,
-                               n, m, M, z, perm, dinv, &s);
+                               n, m, op, M, z, perm, dinv, &s);
         double *wr = w + t * (int64_t)k_stride;
         if (st == OR_OK) {
-            double s2 = s * s;
+            double sl = op == 0 ? s * s : s;
             for (int k = 0; k < n; ++k)
-                wr[k] = z[k] / s2;
+                wr[k] = z[k] / sl;
         } else {
             for (int k = 0; k < n; ++k)
                 wr[k] = NAN;
@@ -551,7 +613,7 @@ static int stencil_solve_mixed(int64_t n_nodes, const double *x, const double *y
         return OR_OK;
     *iters = 0;
     /* FP64 path from scratch */
-    st = stencil_solve(n_nodes, x, y, i, idx, n, m, M, z, perm, dinv, s);
+    st = stencil_solve(n_nodes, x, y, i, idx, n, m, 0, M, z, perm, dinv, s);
     return st == OR_OK ? OR_FELL_BACK : st;
 }
 
@@ -682,7 +744,7 @@ int oracle_adjoint(int64_t n_nodes, const double *x, const double *y,
         const int K = n + NM;
         const int32_t *idx = nbr + i * (int64_t)k_stride;
         double s = 0.0;
-        int st = stencil_solve(n_nodes, x, y, i, idx, n, m, M, z, perm, dinv, &s);
+        int st = stencil_solve(n_nodes, x, y, i, idx, n, m, 0, M, z, perm, dinv, &s);
         if (st != OR_OK) {
             ++failed;
             continue;
