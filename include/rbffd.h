@@ -139,6 +139,30 @@ int rbffd_weights(const double *x, const double *y, int64_t n_nodes,
                   void *workspace, size_t workspace_bytes, void *stream);
 
 /* ==========================================================================
+ * Weights of eq. (1) for other operators L (an extension the conclusions
+ * name): the same system M, the right-hand side [L phi_k; L p_j] at the
+ * centre in unit-scale coordinates, and the scale's power of L:
+ *   RBFFD_OP_LAPLACIAN  exactly rbffd_weights with (m, n), FP64;
+ *   RBFFD_OP_DX         rhs_k = -3 * sqrt(fl(u_kx^2 + u_ky^2)) * u_kx
+ *                       (d/dx of r^3 at the centre), rhs_{n+j} = 1 for the
+ *                       monomial x, else 0; w_ik = z_k / s;
+ *   RBFFD_OP_DY         likewise with u_ky and the monomial y.
+ * Same operation sequence, pivoting, status codes and layouts as
+ * rbffd_weights (x, y [n_nodes]; nbr [n_nodes][k_stride]; w out
+ * [n_nodes][k_stride], zero past n; status [n_nodes] or NULL).  The
+ * derivative operators exist for the standard supports (m, n) = (2, 12),
+ * (4, 30), (6, 56) (RBFFD_ERR_UNSUPPORTED otherwise), FP64, all nodes.
+ * Errors: RBFFD_ERR_ARG for null pointers, an op outside the list, m not in
+ * {2, 4, 6}, n < (m+1)(m+2)/2 or n > k_stride.  No workspace.
+ * ======================================================================== */
+#define RBFFD_OP_LAPLACIAN 0
+#define RBFFD_OP_DX 1
+#define RBFFD_OP_DY 2
+int rbffd_weights_op(const double *x, const double *y, int64_t n_nodes, const int32_t *nbr,
+                     int32_t k_stride, int32_t m, int32_t n, int32_t op, double *w,
+                     int32_t *status, void *stream);
+
+/* ==========================================================================
  * Tuning of the mixed-order batch (rbffd_weights with a per-node order and
  * the standard supports n = 12/30/56, FP64), which runs as one persistent
  * launch: blocks_per_cu blocks of 128 threads per compute unit pull tiles

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "librbffd.so")
 FP64, MIXED = 0, 1
 OK, SINGULAR, FELL_BACK_FP64, NONFINITE, BAD_INDEX, DUPLICATE, BAD_ORDER = range(7)
 SOLVE_CONVERGED, SOLVE_MAX_ITER, SOLVE_BREAKDOWN, SOLVE_NONFINITE = range(4)
+OP_LAPLACIAN, OP_DX, OP_DY = range(3)
 DEFAULT_N_FOR_ORDER = (12, 30, 56)
 
 _lock = threading.Lock()
@@ -59,6 +60,7 @@ def _load():
             "rbffd_time_steps_workspace_size": ([I64, I32, PSZ], ctypes.c_int),
             "rbffd_time_steps": ([I64, P, I32, I32, P, P, P, ctypes.c_double, I64, P, P, P, SZ,
                                   P], ctypes.c_int),
+            "rbffd_weights_op": ([P, P, I64, P, I32, I32, I32, I32, P, P, P], ctypes.c_int),
             "rbffd_solve_workspace_size": ([I64, PSZ], ctypes.c_int),
             "rbffd_solve": ([I64, P, P, P, P, P, ctypes.c_double, I32,
                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
@@ -207,6 +209,21 @@ def rbffd_weights(x, y, nbr, m=None, n=None, order=None, n_for_order=DEFAULT_N_F
                              _p(w), _p(st), _p(rs), _p(sv), 0 if sv is None else sv.numel(),
                              _p(ws), ws.numel(), _stream(x.device)), "rbffd_weights")
     return w, st, sv
+
+
+def rbffd_weights_op(x, y, nbr, m: int, n: int, op: int, out=None, status=None):
+    """Weights of eq. (1) for the operator op (OP_LAPLACIAN, OP_DX, OP_DY),
+    FP64, uniform (m, n).  Returns (w [N, k_stride], status [N])."""
+    lib = _load()
+    x = _dev(x, torch.float64, "x")
+    y = _dev(y, torch.float64, "y")
+    nbr = _dev(nbr, torch.int32, "nbr")
+    N, ks = nbr.shape
+    w = out if out is not None else torch.empty((N, ks), dtype=torch.float64, device=x.device)
+    st = status if status is not None else torch.empty(N, dtype=torch.int32, device=x.device)
+    _check(lib.rbffd_weights_op(_p(x), _p(y), N, _p(nbr), ks, int(m), int(n), int(op), _p(w),
+                                _p(st), _stream(x.device)), "rbffd_weights_op")
+    return w, st
 
 
 def rbffd_weights_backward(x, y, nbr, grad_w, save, status=None, m=None, n=None, order=None,

@@ -78,7 +78,8 @@ struct MfLds {
 // adjoint: row r of the factors (its multipliers left of its final
 // position, its row of U from there on) at row r, the row at each position,
 // the unit-scale solution z and the scale s.
-template <int KP, int NFIX, int MFIX, int NW, int WV, bool SAVE>
+// OP: 0 the Laplacian, 1 d/dx, 2 d/dy (right-hand side and power of the scale).
+template <int KP, int NFIX, int MFIX, int NW, int WV, bool SAVE, int OP = 0>
 __device__ __forceinline__ void weights_mf_wave(
     const double *__restrict__ x, const double *__restrict__ y, int64_t n_nodes,
     const int32_t *__restrict__ nbr, int32_t k_stride, int64_t i, double *__restrict__ w,
@@ -196,8 +197,11 @@ __device__ __forceinline__ void weights_mf_wave(
                     v = prow ? s_P[prow ? R : 0][C - n] : 0.0;
                 } else if (16 * J + 15 >= KP && 16 * J <= KP && C == KP) {
                     const double r0 = uxr * uxr + uyr * uyr;
-                    const double rb = 9.0 * sqrt(r0);
-                    v = prow ? rb : ((qrow && (jr == 3 || jr == 5)) ? 2.0 : 0.0);
+                    const double rb =
+                        OP == 0 ? 9.0 * sqrt(r0) : -3.0 * sqrt(r0) * (OP == 1 ? uxr : uyr);
+                    const double rq =
+                        OP == 0 ? ((jr == 3 || jr == 5) ? 2.0 : 0.0) : (jr == OP ? 1.0 : 0.0);
+                    v = prow ? rb : (qrow ? rq : 0.0);
                 }
                 T[I][jt][r] = v;
             }
@@ -480,7 +484,7 @@ __device__ __forceinline__ void weights_mf_wave(
     else if (luflag == L_SING) st = RBFFD_SINGULAR;
     else if (fl & F_ZBAD) st = RBFFD_NONFINITE;
     double *wi = w + i * (int64_t)k_stride;
-    const double s2 = sc * sc;
+    const double s2 = OP == 0 ? sc * sc : sc;  // the operator's power of the scale
     const bool good = st == RBFFD_OK;
 #pragma unroll
     for (int s = 0; s < SL; ++s) {
@@ -513,7 +517,7 @@ __device__ __forceinline__ void weights_mf_wave(
 }
 
 // One block (NW wavefronts) computes stencil `t` of the row list.
-template <int KP, int NFIX, int MFIX, int NW, bool SAVE = false>
+template <int KP, int NFIX, int MFIX, int NW, bool SAVE = false, int OP = 0>
 __device__ __forceinline__ void weights_mf_body(
     const double *__restrict__ x, const double *__restrict__ y, int64_t n_nodes,
     const int32_t *__restrict__ nbr, int32_t k_stride, const int32_t *__restrict__ rows,
@@ -522,10 +526,10 @@ __device__ __forceinline__ void weights_mf_body(
     if (t >= n_rows) return;  // whole block idle
     const int64_t i = rows ? (int64_t)rows[t] : t;
     if (NW > 1 && ((threadIdx.x >> 6) & 1))
-        weights_mf_wave<KP, NFIX, MFIX, NW, NW - 1, SAVE>(x, y, n_nodes, nbr, k_stride, i, w,
+        weights_mf_wave<KP, NFIX, MFIX, NW, NW - 1, SAVE, OP>(x, y, n_nodes, nbr, k_stride, i, w,
                                                          status, sv, ok_code, lds);
     else
-        weights_mf_wave<KP, NFIX, MFIX, NW, 0, SAVE>(x, y, n_nodes, nbr, k_stride, i, w, status,
+        weights_mf_wave<KP, NFIX, MFIX, NW, 0, SAVE, OP>(x, y, n_nodes, nbr, k_stride, i, w, status,
                                                      sv, ok_code, lds);
 }
 
@@ -536,7 +540,7 @@ __host__ __device__ constexpr int mf_lds_bytes(int nw) {
     return nw > 1 ? MfLds<KP, MM, NT, 2>::BYTES : MfLds<KP, MM, NT, 1>::BYTES;
 }
 
-template <int KP, int NFIX, int MFIX, int NW, int OCC, bool SAVE>
+template <int KP, int NFIX, int MFIX, int NW, int OCC, bool SAVE, int OP = 0>
 __global__ __launch_bounds__(NW * kWave)
 __attribute__((amdgpu_waves_per_eu(OCC))) void weights_mf_kernel(
     const double *__restrict__ x, const double *__restrict__ y, int64_t n_nodes,
@@ -545,18 +549,19 @@ __attribute__((amdgpu_waves_per_eu(OCC))) void weights_mf_kernel(
     int32_t *__restrict__ status, SaveView sv, int32_t ok_code) {
     __shared__ __align__(16) char lds[mf_lds_bytes<KP, NFIX, MFIX>(NW)];
     if (n_rows_dev) n_rows = *n_rows_dev;
-    weights_mf_body<KP, NFIX, MFIX, NW, SAVE>(x, y, n_nodes, nbr, k_stride, rows, n_rows, w,
+    weights_mf_body<KP, NFIX, MFIX, NW, SAVE, OP>(x, y, n_nodes, nbr, k_stride, rows, n_rows, w,
                                               status, ok_code, (int64_t)blockIdx.x, lds, sv);
 }
 
 // sv.lu set: the saving instance (one wavefront per stencil only).
-template <int KP, int NFIX, int MFIX, int NW, int OCC>
+template <int KP, int NFIX, int MFIX, int NW, int OCC, int OP = 0>
 inline int launch_mf(const double *x, const double *y, int64_t n_nodes, const int32_t *nbr,
                      int32_t k_stride, const int32_t *rows, const int32_t *n_rows_dev,
                      int64_t n_rows, double *w, int32_t *status, const SaveView &sv,
                      int32_t ok_code, hipStream_t stream) {
     if (n_rows <= 0) return RBFFD_SUCCESS;
     if (n_rows > 0x7fffffff) return RBFFD_ERR_UNSUPPORTED;
+    if (sv.lu && OP != 0) return RBFFD_ERR_UNSUPPORTED;  // factors: the Laplacian only
     if constexpr (NW == 1) {
         if (sv.lu) {
             hipLaunchKernelGGL((weights_mf_kernel<KP, NFIX, MFIX, NW, OCC, true>),
@@ -568,7 +573,7 @@ inline int launch_mf(const double *x, const double *y, int64_t n_nodes, const in
     } else {
         if (sv.lu) return RBFFD_ERR_UNSUPPORTED;
     }
-    hipLaunchKernelGGL((weights_mf_kernel<KP, NFIX, MFIX, NW, OCC, false>),
+    hipLaunchKernelGGL((weights_mf_kernel<KP, NFIX, MFIX, NW, OCC, false, OP>),
                        dim3((unsigned)n_rows), dim3(NW * kWave), 0, stream, x, y, n_nodes, nbr,
                        k_stride, rows, n_rows_dev, n_rows, w, status, SaveView{}, ok_code);
     return last_launch_rc();

@@ -196,7 +196,9 @@ __device__ __forceinline__ void bc_step(const double *sU, const int *ub, const d
 // grp*GPB .. grp*GPB+GPB-1 of the row list).  WPB wavefronts of a block run
 // independent groups; `wave` selects this wavefront's LDS.  SAVE keeps the
 // multipliers of L in registers and writes the factors for the adjoint.
-template <int KP, int SEG, int SL, int NFIX, int MFIX, int WPB, bool SAVE>
+// OP: 0 the Laplacian, 1 d/dx, 2 d/dy (the right-hand side of eq. (1) and
+// the power of the scale; see rbffd_weights_op).
+template <int KP, int SEG, int SL, int NFIX, int MFIX, int WPB, bool SAVE, int OP = 0>
 __device__ __forceinline__ void weights_ms_body(
     const double *__restrict__ x, const double *__restrict__ y, int64_t n_nodes,
     const int32_t *__restrict__ nbr, int32_t k_stride, const int32_t *__restrict__ rows,
@@ -324,8 +326,10 @@ __device__ __forceinline__ void weights_ms_body(
             if ((l & 1) == 1) __builtin_amdgcn_sched_barrier(0);
         }
         const double r0 = ux[s] * ux[s] + uy[s] * uy[s];
-        const double rb = 9.0 * sqrt(r0);
-        yv[s] = prow ? rb : ((qrow && (jr == 3 || jr == 5)) ? 2.0 : 0.0);
+        const double rb =
+            OP == 0 ? 9.0 * sqrt(r0) : -3.0 * sqrt(r0) * (OP == 1 ? ux[s] : uy[s]);
+        const double rq = OP == 0 ? ((jr == 3 || jr == 5) ? 2.0 : 0.0) : (jr == OP ? 1.0 : 0.0);
+        yv[s] = prow ? rb : (qrow ? rq : 0.0);
     }
     // materialise the flags here: otherwise the duplicate checks sink to the
     // end of the kernel and keep every squared distance alive through the LU
@@ -525,7 +529,7 @@ __device__ __forceinline__ void weights_ms_body(
 
     if (!valid) return;
     double *wi = w + i * (int64_t)k_stride;
-    const double s2 = sc * sc;
+    const double s2 = OP == 0 ? sc * sc : sc;  // the operator's power of the scale
     const bool good = st == RBFFD_OK;
 #pragma unroll
     for (int s = 0; s < SL; ++s) {
@@ -554,7 +558,7 @@ __device__ __forceinline__ void weights_ms_body(
     }
 }
 
-template <int KP, int SEG, int SL, int NFIX, int MFIX, int OCC, bool SAVE>
+template <int KP, int SEG, int SL, int NFIX, int MFIX, int OCC, bool SAVE, int OP = 0>
 __global__ __launch_bounds__(kWave)
 __attribute__((amdgpu_waves_per_eu(OCC <= 0 ? 1 : (SAVE && OCC > 2 ? 2 : OCC)))) void
 weights_ms_kernel(
@@ -566,13 +570,13 @@ weights_ms_kernel(
     int32_t sv_kmax, int32_t ok_code) {
     __shared__ __align__(16) char lds[ms_lds_bytes<KP, SEG, MFIX, 1>()];
     if (n_rows_dev) n_rows = *n_rows_dev;
-    weights_ms_body<KP, SEG, SL, NFIX, MFIX, 1, SAVE>(x, y, n_nodes, nbr, k_stride, rows, n_rows,
+    weights_ms_body<KP, SEG, SL, NFIX, MFIX, 1, SAVE, OP>(x, y, n_nodes, nbr, k_stride, rows, n_rows,
                                                       n_arg, m_arg, w, status, sv_lu, sv_z, sv_s,
                                                       sv_perm, sv_kmax, ok_code,
                                                       (int64_t)blockIdx.x, 0, lds);
 }
 
-template <int KP, int SEG, int SL, int NFIX, int MFIX, int OCC = 0>
+template <int KP, int SEG, int SL, int NFIX, int MFIX, int OCC = 0, int OP = 0>
 inline int launch_ms(const double *x, const double *y, int64_t n_nodes, const int32_t *nbr,
                      int32_t k_stride, const int32_t *rows, const int32_t *n_rows_dev,
                      int64_t n_rows, int n, int m, double *w, int32_t *status,
@@ -581,13 +585,14 @@ inline int launch_ms(const double *x, const double *y, int64_t n_nodes, const in
     if (n_rows <= 0) return RBFFD_SUCCESS;
     const int64_t blocks = ceil_div(n_rows, GPB);
     if (blocks > 0x7fffffff) return RBFFD_ERR_UNSUPPORTED;
+    if (sv.lu && OP != 0) return RBFFD_ERR_UNSUPPORTED;  // factors: the Laplacian only
     if (sv.lu)
-        hipLaunchKernelGGL((weights_ms_kernel<KP, SEG, SL, NFIX, MFIX, OCC, true>),
+        hipLaunchKernelGGL((weights_ms_kernel<KP, SEG, SL, NFIX, MFIX, OCC, true, OP>),
                            dim3((unsigned)blocks), dim3(kWave), 0, stream, x, y, n_nodes, nbr,
                            k_stride, rows, n_rows_dev, n_rows, n, m, w, status, sv.lu, sv.z, sv.s,
                            sv.perm, sv.kmax, ok_code);
     else
-        hipLaunchKernelGGL((weights_ms_kernel<KP, SEG, SL, NFIX, MFIX, OCC, false>),
+        hipLaunchKernelGGL((weights_ms_kernel<KP, SEG, SL, NFIX, MFIX, OCC, false, OP>),
                            dim3((unsigned)blocks), dim3(kWave), 0, stream, x, y, n_nodes, nbr,
                            k_stride, rows, n_rows_dev, n_rows, n, m, w, status, nullptr, nullptr,
                            nullptr, nullptr, 0, ok_code);

@@ -1,0 +1,58 @@
+// First-derivative weights (d/dx, d/dy) of eq. (1) for the standard supports
+// of m = 2 and 4, and the C entry point rbffd_weights_op.  The kernels are
+// the Laplacian's (one row per lane for K = 18, the blocked LU for K = 45
+// and 84) with the operator's right-hand side and scale; K = 84 lives in
+// weights_op_k84.hip.
+#include "weights_ms.h"
+#include "weights_mf.h"
+
+namespace rbffd {
+
+int weights_fp64_class(const double *x, const double *y, int64_t n_nodes, const int32_t *nbr,
+                       int32_t k_stride, const int32_t *rows, const int32_t *n_rows_dev,
+                       int64_t n_rows, int n, int m, double *w, int32_t *status,
+                       double *sv_lu, double *sv_z, double *sv_s, uint8_t *sv_perm,
+                       int32_t sv_kmax, int32_t ok_code, hipStream_t stream);
+int weights_op_k84(const double *x, const double *y, int64_t n_nodes, const int32_t *nbr,
+                   int32_t k_stride, int64_t n_rows, int op, double *w, int32_t *status,
+                   hipStream_t stream);
+
+namespace {
+
+template <int OP>
+int op_small(const double *x, const double *y, int64_t n_nodes, const int32_t *nbr,
+             int32_t k_stride, int64_t n_rows, int m, double *w, int32_t *status,
+             hipStream_t stream) {
+    const wk::SaveView none;
+    if (m == 2)
+        return wk::launch_ms<18, 8, 3, 12, 2, 3, OP>(x, y, n_nodes, nbr, k_stride, nullptr,
+                                                     nullptr, n_rows, 12, 2, w, status, none,
+                                                     RBFFD_OK, stream);
+    return wk::launch_mf<45, 30, 4, 1, 4, OP>(x, y, n_nodes, nbr, k_stride, nullptr, nullptr,
+                                              n_rows, w, status, none, RBFFD_OK, stream);
+}
+
+}  // namespace
+}  // namespace rbffd
+
+using namespace rbffd;
+
+extern "C" int rbffd_weights_op(const double *x, const double *y, int64_t n_nodes,
+                                const int32_t *nbr, int32_t k_stride, int32_t m, int32_t n,
+                                int32_t op, double *w, int32_t *status, void *stream) {
+    if (!x || !y || !nbr || !w || n_nodes < 1 || n_nodes >= INT32_MAX || k_stride < 1 ||
+        n > k_stride || (m != 2 && m != 4 && m != 6) || n < n_monomials(m) ||
+        op < RBFFD_OP_LAPLACIAN || op > RBFFD_OP_DY)
+        return RBFFD_ERR_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (op == RBFFD_OP_LAPLACIAN)
+        return weights_fp64_class(x, y, n_nodes, nbr, k_stride, nullptr, nullptr, n_nodes, n, m,
+                                  w, status, nullptr, nullptr, nullptr, nullptr, 0, RBFFD_OK, s);
+    const bool standard = (m == 2 && n == 12) || (m == 4 && n == 30) || (m == 6 && n == 56);
+    if (!standard) return RBFFD_ERR_UNSUPPORTED;
+    if (m == 6) return weights_op_k84(x, y, n_nodes, nbr, k_stride, n_nodes, op, w, status, s);
+    return op == RBFFD_OP_DX ? op_small<RBFFD_OP_DX>(x, y, n_nodes, nbr, k_stride, n_nodes, m, w,
+                                                     status, s)
+                             : op_small<RBFFD_OP_DY>(x, y, n_nodes, nbr, k_stride, n_nodes, m, w,
+                                                     status, s);
+}

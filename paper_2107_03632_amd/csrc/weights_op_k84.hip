@@ -1,0 +1,18 @@
+// First-derivative weights (d/dx, d/dy) for m = 6, n = 56: the blocked LU
+// of the Laplacian with the operator's right-hand side and scale.
+#include "weights_mf.h"
+
+namespace rbffd {
+int weights_op_k84(const double *x, const double *y, int64_t n_nodes, const int32_t *nbr,
+                   int32_t k_stride, int64_t n_rows, int op, double *w, int32_t *status,
+                   hipStream_t stream) {
+    const wk::SaveView none;
+    if (op == RBFFD_OP_DX)
+        return wk::launch_mf<84, 56, 6, 2, 2, RBFFD_OP_DX>(x, y, n_nodes, nbr, k_stride, nullptr,
+                                                           nullptr, n_rows, w, status, none,
+                                                           RBFFD_OK, stream);
+    return wk::launch_mf<84, 56, 6, 2, 2, RBFFD_OP_DY>(x, y, n_nodes, nbr, k_stride, nullptr,
+                                                       nullptr, n_rows, w, status, none,
+                                                       RBFFD_OK, stream);
+}
+}  // namespace rbffd

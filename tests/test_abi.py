@@ -29,7 +29,7 @@ def lib():
 def test_header_declares_the_boundary():
     names = declared()
     for fn in ["rbffd_knn", "rbffd_weights", "rbffd_weights_backward", "rbffd_assemble_csr",
-               "rbffd_spmv", "rbffd_time_steps", "rbffd_solve"]:
+               "rbffd_spmv", "rbffd_time_steps", "rbffd_solve", "rbffd_weights_op"]:
         assert fn in names
 
 
@@ -76,6 +76,9 @@ def test_argument_errors_before_any_launch(lib):
     it, rr, info = ctypes.c_int32(), ctypes.c_double(), ctypes.c_int32()
     assert lib.rbffd_solve(10, None, None, None, None, None, 1e-10, 100, ctypes.byref(it),
                            ctypes.byref(rr), ctypes.byref(info), None, 0, None) == -1
+    lib.rbffd_weights_op.argtypes = [P, P, ctypes.c_int64, P, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_int32, ctypes.c_int32, P, P, P]
+    assert lib.rbffd_weights_op(None, None, 10, None, 12, 2, 12, 1, None, None, None) == -1
     sz = ctypes.c_size_t(0)
     lib.rbffd_solve_workspace_size.argtypes = [ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]
     assert lib.rbffd_solve_workspace_size(1000, ctypes.byref(sz)) == 0
