@@ -83,3 +83,43 @@ def test_laplacian_operator_is_the_weights():
     w0, s0 = oracle.weights(ns.x, ns.y, nbr, m=4, n=30)
     w1, s1 = oracle.weights_op(ns.x, ns.y, nbr, 4, 30, oracle.LAPLACIAN)
     assert np.array_equal(w0, w1) and np.array_equal(s0, s1)
+
+
+@pytest.mark.parametrize("m,n", [(2, 12), (4, 30)])
+def test_derivative_of_phs_interpolant(m, n):
+    """w . f equals d/dx (d/dy) of s_f at the centre, where s_f is the r^3 +
+    monomial interpolant of f on the stencil, taken by 30-digit numerical
+    differentiation.  Polynomial reproduction holds whatever the r^3 part of
+    the right-hand side is; this pins that part (its constant, sign and
+    which offset component it takes)."""
+    import mpmath
+    ns = nodes.unit_square(12, seed=17)
+    nbr = oracle.knn(ns.x, ns.y, n)
+    rng = np.random.default_rng(6)
+    ex = monos(m)
+    for i in [30, 77]:
+        idx = nbr[i]
+        px, py = ns.x[idx], ns.y[idx]
+        cx, cy = ns.x[i], ns.y[i]
+        f = rng.standard_normal(n)
+        A = np.sqrt((px[:, None] - px[None]) ** 2 + (py[:, None] - py[None]) ** 2) ** 3
+        P = np.array([[(a_ - cx) ** e[0] * (b_ - cy) ** e[1] for e in ex]
+                      for a_, b_ in zip(px, py)])
+        M = np.block([[A, P], [P.T, np.zeros((len(ex), len(ex)))]])
+        coef = np.linalg.solve(M, np.concatenate([f, np.zeros(len(ex))]))
+        with mpmath.workdps(30):
+            def s_f(X, Y):
+                acc = mpmath.mpf(0)
+                for k in range(n):
+                    acc += coef[k] * mpmath.sqrt((X - px[k]) ** 2 + (Y - py[k]) ** 2) ** 3
+                for j, e in enumerate(ex):
+                    acc += coef[n + j] * (X - cx) ** e[0] * (Y - cy) ** e[1]
+                return acc
+            X0, Y0 = mpmath.mpf(cx), mpmath.mpf(cy)
+            ddx = mpmath.diff(lambda t: s_f(t, Y0), X0, 1)
+            ddy = mpmath.diff(lambda t: s_f(X0, t), Y0, 1)
+        for op, want in ((oracle.D_DX, float(ddx)), (oracle.D_DY, float(ddy))):
+            w, st = oracle.weights_op(ns.x, ns.y, nbr, m, n, op, rows=[i])
+            assert st[0] == 0
+            got = float(np.dot(w[0, :n], f))
+            assert abs(got - want) <= 1e-8 * np.abs(w[0, :n] * f).sum(), (op, got, want)
