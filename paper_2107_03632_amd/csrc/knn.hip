@@ -25,6 +25,12 @@ namespace {
 
 constexpr int kBBoxBlocks = 512;
 constexpr int kThreads = 256;
+// Queries per block.  One wavefront per block spreads the few query
+// wavefronts of a 100k-node set evenly over the 256 compute units.
+#ifndef RBFFD_KNN_QUERY_THREADS
+#define RBFFD_KNN_QUERY_THREADS 64
+#endif
+constexpr int kQueryThreads = RBFFD_KNN_QUERY_THREADS;
 
 struct GridParams {
     double xmin, ymin, cs, inv_cs;
@@ -174,43 +180,40 @@ __device__ __forceinline__ bool key_less(double d1, int32_t j1, double d2, int32
     return d1 < d2 || (d1 == d2 && j1 < j2);
 }
 
+// The k best keys, ascending, in slots KMAX - k .. KMAX - 1.  The slots below
+// hold the key (-1, -1), which precedes every candidate's (d2 >= 0 or NaN),
+// so nothing is ever inserted there and the current k-th key is always the
+// last slot: no slot depends on k at run time.
 template <int KMAX>
 struct TopK {
     double d[KMAX];
     int32_t j[KMAX];
-    double wd;   // key of slot k-1 (the current k-th)
-    int32_t wj;
 
-    __device__ __forceinline__ void init() {
+    __device__ __forceinline__ void init(int k) {
 #pragma unroll
         for (int s = 0; s < KMAX; ++s) {
-            d[s] = __builtin_inf();
-            j[s] = INT32_MAX;
+            const bool live = s >= KMAX - k;
+            d[s] = live ? __builtin_inf() : -1.0;
+            j[s] = live ? INT32_MAX : -1;
         }
-        wd = __builtin_inf();
-        wj = INT32_MAX;
     }
+    __device__ __forceinline__ double wd() const { return d[KMAX - 1]; }
+    __device__ __forceinline__ int32_t wj() const { return j[KMAX - 1]; }
 
-    // insert a key known to precede slot k-1; keys are unique (distinct j)
-    __device__ __forceinline__ void insert(double cd, int32_t cj, int k) {
+    // insert a key known to precede the last slot; keys are unique (distinct
+    // j).  The list is sorted, so the slots the key precedes form a suffix:
+    // each of them takes its left neighbour, and the first takes the key.
+    __device__ __forceinline__ void insert(double cd, int32_t cj) {
+        bool lt[KMAX];
 #pragma unroll
-        for (int s = KMAX - 1; s >= 0; --s) {
-            if (s < k) {
-                if (s > 0 && key_less(cd, cj, d[s - 1], j[s - 1])) {
-                    d[s] = d[s - 1];
-                    j[s] = j[s - 1];
-                } else if (key_less(cd, cj, d[s], j[s])) {
-                    d[s] = cd;
-                    j[s] = cj;
-                }
-            }
+        for (int s = 0; s < KMAX; ++s) lt[s] = key_less(cd, cj, d[s], j[s]);
+#pragma unroll
+        for (int s = KMAX - 1; s > 0; --s) {
+            d[s] = lt[s - 1] ? d[s - 1] : (lt[s] ? cd : d[s]);
+            j[s] = lt[s - 1] ? j[s - 1] : (lt[s] ? cj : j[s]);
         }
-#pragma unroll
-        for (int s = 0; s < KMAX; ++s)
-            if (s == k - 1) {
-                wd = d[s];
-                wj = j[s];
-            }
+        d[0] = lt[0] ? cd : d[0];
+        j[0] = lt[0] ? cj : j[0];
     }
 };
 
@@ -225,7 +228,7 @@ constexpr int knn_batch() {
 }
 
 template <int KMAX>
-__device__ __forceinline__ void scan_range(TopK<KMAX> &top, int k, int p0, int p1, double qx,
+__device__ __forceinline__ void scan_range(TopK<KMAX> &top, int p0, int p1, double qx,
                                            double qy, const int32_t *__restrict__ ids,
                                            const double *__restrict__ xs,
                                            const double *__restrict__ ys) {
@@ -246,7 +249,7 @@ __device__ __forceinline__ void scan_range(TopK<KMAX> &top, int k, int p0, int p
                 const double dx = cx[u] - qx;
                 const double dy = cy[u] - qy;
                 const double dd = dx * dx + dy * dy;
-                if (key_less(dd, cj[u], top.wd, top.wj)) top.insert(dd, cj[u], k);
+                if (key_less(dd, cj[u], top.wd(), top.wj())) top.insert(dd, cj[u]);
             }
         }
     }
@@ -255,22 +258,22 @@ __device__ __forceinline__ void scan_range(TopK<KMAX> &top, int k, int p0, int p
         const double dy = ys[p] - qy;
         const double dd = dx * dx + dy * dy;
         const int32_t cj = ids[p];
-        if (key_less(dd, cj, top.wd, top.wj)) top.insert(dd, cj, k);
+        if (key_less(dd, cj, top.wd(), top.wj())) top.insert(dd, cj);
     }
 }
 
 template <int KMAX>
-__global__ __launch_bounds__(kThreads) void knn_query(
+__global__ __launch_bounds__(kQueryThreads) void knn_query(
     const GridParams *__restrict__ gpp, const int32_t *__restrict__ start,
     const int32_t *__restrict__ ids, const double *__restrict__ xs,
     const double *__restrict__ ys, int64_t n, int32_t k, int32_t *__restrict__ nbr) {
-    const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const int64_t t = (int64_t)blockIdx.x * kQueryThreads + threadIdx.x;
     if (t >= n) return;
     const GridParams gp = *gpp;
     const int32_t qi = ids[t];
     const double qx = xs[t], qy = ys[t];
     TopK<KMAX> top;
-    top.init();
+    top.init(k);
     const int cx = cell_coord(qx, gp.xmin, gp.inv_cs, gp.gx);
     const int cy = cell_coord(qy, gp.ymin, gp.inv_cs, gp.gy);
     const int max_r = gp.gx > gp.gy ? gp.gx : gp.gy;
@@ -284,14 +287,14 @@ __global__ __launch_bounds__(kThreads) void knn_query(
         for (int yy = ya; yy <= yb; ++yy) {
             const int row = yy * gp.gx;
             if (yy == y0 || yy == y1) {
-                scan_range<KMAX>(top, k, start[row + xa], start[row + xb + 1], qx, qy, ids, xs,
+                scan_range<KMAX>(top, start[row + xa], start[row + xb + 1], qx, qy, ids, xs,
                                  ys);
             } else {
                 if (x0 >= 0)
-                    scan_range<KMAX>(top, k, start[row + x0], start[row + x0 + 1], qx, qy, ids,
+                    scan_range<KMAX>(top, start[row + x0], start[row + x0 + 1], qx, qy, ids,
                                      xs, ys);
                 if (x1 < gp.gx)
-                    scan_range<KMAX>(top, k, start[row + x1], start[row + x1 + 1], qx, qy, ids,
+                    scan_range<KMAX>(top, start[row + x1], start[row + x1 + 1], qx, qy, ids,
                                      xs, ys);
             }
         }
@@ -303,12 +306,12 @@ __global__ __launch_bounds__(kThreads) void knn_query(
         if (y1 < gp.gy - 1) lb = fmin(lb, (gp.ymin + (y1 + 1) * gp.cs) - qy);
         if (lb == __builtin_inf()) break;  // the whole grid has been visited
         lb -= margin;
-        if (top.wj != INT32_MAX && lb > 0.0 && top.wd < lb * lb) break;
+        if (top.wj() != INT32_MAX && lb > 0.0 && top.wd() < lb * lb) break;
     }
     int32_t *out = nbr + (int64_t)qi * k;
 #pragma unroll
     for (int s = 0; s < KMAX; ++s)
-        if (s < k) out[s] = top.j[s] == INT32_MAX ? -1 : top.j[s];
+        if (s >= KMAX - k) out[s - (KMAX - k)] = top.j[s] == INT32_MAX ? -1 : top.j[s];
 }
 
 struct KnnWs {
@@ -377,20 +380,35 @@ extern "C" int rbffd_knn(const double *x, const double *y, int64_t n_nodes, int3
     hipLaunchKernelGGL(cell_scatter, dim3(nb), dim3(kThreads), 0, s, x, y, n_nodes,
                        (const int32_t *)w.cell_of, (const int32_t *)w.counts, w.fill, w.ids, w.xs,
                        w.ys);
-    if (k <= 16)
-        hipLaunchKernelGGL(knn_query<16>, dim3(nb), dim3(kThreads), 0, s,
-                           (const GridParams *)w.gp, (const int32_t *)w.counts,
-                           (const int32_t *)w.ids, (const double *)w.xs, (const double *)w.ys,
-                           n_nodes, k, nbr);
-    else if (k <= 32)
-        hipLaunchKernelGGL(knn_query<32>, dim3(nb), dim3(kThreads), 0, s,
-                           (const GridParams *)w.gp, (const int32_t *)w.counts,
-                           (const int32_t *)w.ids, (const double *)w.xs, (const double *)w.ys,
-                           n_nodes, k, nbr);
-    else
-        hipLaunchKernelGGL(knn_query<64>, dim3(nb), dim3(kThreads), 0, s,
-                           (const GridParams *)w.gp, (const int32_t *)w.counts,
-                           (const int32_t *)w.ids, (const double *)w.xs, (const double *)w.ys,
-                           n_nodes, k, nbr);
+    const unsigned nq = (unsigned)ceil_div(n_nodes, kQueryThreads);
+    const GridParams *gp = w.gp;
+    const int32_t *start = w.counts, *ids = w.ids;
+    const double *xs = w.xs, *ys = w.ys;
+    // exact list lengths for the standard supports (12, 30, 56), else the
+    // next of 16, 32, 64
+    switch (k) {
+    case 12:
+        hipLaunchKernelGGL(knn_query<12>, dim3(nq), dim3(kQueryThreads), 0, s, gp, start, ids, xs,
+                           ys, n_nodes, k, nbr);
+        break;
+    case 30:
+        hipLaunchKernelGGL(knn_query<30>, dim3(nq), dim3(kQueryThreads), 0, s, gp, start, ids, xs,
+                           ys, n_nodes, k, nbr);
+        break;
+    case 56:
+        hipLaunchKernelGGL(knn_query<56>, dim3(nq), dim3(kQueryThreads), 0, s, gp, start, ids, xs,
+                           ys, n_nodes, k, nbr);
+        break;
+    default:
+        if (k <= 16)
+            hipLaunchKernelGGL(knn_query<16>, dim3(nq), dim3(kQueryThreads), 0, s, gp, start, ids,
+                               xs, ys, n_nodes, k, nbr);
+        else if (k <= 32)
+            hipLaunchKernelGGL(knn_query<32>, dim3(nq), dim3(kQueryThreads), 0, s, gp, start, ids,
+                               xs, ys, n_nodes, k, nbr);
+        else
+            hipLaunchKernelGGL(knn_query<64>, dim3(nq), dim3(kQueryThreads), 0, s, gp, start, ids,
+                               xs, ys, n_nodes, k, nbr);
+    }
     return last_launch_rc();
 }
