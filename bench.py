@@ -17,6 +17,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -60,7 +61,7 @@ WEIGHTS_SOURCES = ["paper_2107_03632_amd/csrc/common.h",
                    "paper_2107_03632_amd/csrc/weights_ms.h",
                    "paper_2107_03632_amd/csrc/weights_mf.h",
                    "paper_2107_03632_amd/csrc/weights_k45.hip"]
-WEIGHTS_KERNEL = "weights_mf_kernel<45, 30, 4, 1, 4, false>"
+WEIGHTS_KERNEL = "weights_mf_kernel<45, 30, 4, 1, 4, false, 0>"
 
 
 def read_traffic(kernel_tag: str):
@@ -243,6 +244,7 @@ def main():
         out["per_order_1M_square"] = extras_per_order(torch, rb, nodes, dev, stream)
         out["adjoint_annulus_200k_m4"] = extras_adjoint(torch, rb, nodes, dev, stream)
         out["time_loop_unit_disk"] = extras_time_loop(torch, rb, nodes, dev, stream)
+        out["derivative_weights_unit_disk"] = extras_ops(torch, rb, stream, X, Y, ns, m, n)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(ns, m, n, args.cpu_stride)
@@ -359,6 +361,29 @@ def extras_solve(torch, rb, nodes, dev, X, Y, B, U, F, ns, m, n, rtol=1e-10):
             "model_bytes_per_iteration": per_it,
             "model_gb_per_s": per_it * it / (ms * 1e-3) / 1e9,
             "max_err_vs_exact": (x - U).abs().max().item(), "nnz": nnz}
+
+
+def extras_ops(torch, rb, stream, X, Y, ns, m, n):
+    """First-derivative weights (rbffd_weights_op, d/dx and d/dy) on the bench
+    disk: time per launch, the fraction of the FP64 peak on the Laplacian's
+    flop count (the same factorisation and solves), and the largest error of
+    the differentiated u = sin(pi x) sin(pi y) over all nodes."""
+    nbr = rb.rbffd_knn(X, Y, n)
+    N = ns.n_nodes
+    u = torch.sin(math.pi * X) * torch.sin(math.pi * Y)
+    exact = {rb.OP_DX: math.pi * torch.cos(math.pi * X) * torch.sin(math.pi * Y),
+             rb.OP_DY: math.pi * torch.sin(math.pi * X) * torch.cos(math.pi * Y)}
+    res = {"n_nodes": N, "m": m, "n": n}
+    for name, op in (("d_dx", rb.OP_DX), ("d_dy", rb.OP_DY)):
+        ms = timed(torch, stream, lambda: rb.rbffd_weights_op(X, Y, nbr, m, n, op))
+        w, st = rb.rbffd_weights_op(X, Y, nbr, m, n, op)
+        approx = (w * u[nbr.long()]).sum(1)
+        res[name] = {"ms": ms, "stencils_per_s": N / (ms * 1e-3),
+                     "frac_fp64_peak": weights_flops(m, n) * N / 1e12 / (ms * 1e-3)
+                     / FP64_PEAK_TFLOPS,
+                     "failed": int((st != 0).sum().item()),
+                     "max_abs_err": (approx - exact[op]).abs().max().item()}
+    return res
 
 
 def extras_adjoint(torch, rb, nodes, dev, stream):
