@@ -75,6 +75,10 @@ def _load():
                                            P, P, P]
             lib.oracle_csr.argtypes = [I64, P, I32, P, I32, P, P, P, P, P, P]
             lib.oracle_spmv.argtypes = [I64, P, P, P, P, P, P]
+            lib.oracle_knn3.argtypes = [I64, P, P, P, I32, P, I64, P]
+            lib.oracle_assemble3.argtypes = [I64, P, P, P, I64, P, ctypes.c_int,
+                                             ctypes.c_int, P, P, P]
+            lib.oracle_weights3.argtypes = [I64, P, P, P, P, I32, I32, I32, P, I64, P, P]
             lib.oracle_time_steps.argtypes = [I64, P, I32, I32, P, P, P, ctypes.c_double,
                                               I64, P]
             _lib = lib
@@ -117,6 +121,58 @@ def knn(x, y, k: int, queries=None) -> np.ndarray:
     if rc != 0:
         raise ValueError(f"oracle_knn: error {rc}")
     return out
+
+
+def n_monomials3(m: int) -> int:
+    return (m + 1) * (m + 2) * (m + 3) // 6
+
+
+def knn3(x, y, z, k: int, queries=None) -> np.ndarray:
+    """N(x) of eq. (1) for nodes in R^3: the k nearest nodes, ascending by
+    (d^2, index), brute force.  Returns int32 [len(queries) or N, k]."""
+    lib = _load()
+    x, y, z = _f64(x), _f64(y), _f64(z)
+    q = None if queries is None else np.ascontiguousarray(queries, dtype=np.int64)
+    nq = x.shape[0] if q is None else q.shape[0]
+    out = np.empty((nq, k), dtype=np.int32)
+    rc = lib.oracle_knn3(x.shape[0], _p(x), _p(y), _p(z), k, _p(q), nq, _p(out))
+    if rc != 0:
+        raise ValueError(f"oracle_knn3: error {rc}")
+    return out
+
+
+def assemble3(x, y, z, i: int, idx, m: int):
+    """The 3-D augmented system of node i on support idx (r^3, monomials of
+    degree <= m in x, y, z).  Returns (status, M [K,K], rhs [K], s)."""
+    lib = _load()
+    x, y, z, idx = _f64(x), _f64(y), _f64(z), _i32(idx)
+    n = idx.shape[0]
+    K = n + n_monomials3(m)
+    M = np.zeros((K, K))
+    rhs = np.zeros(K)
+    s = np.zeros(1)
+    st = lib.oracle_assemble3(x.shape[0], _p(x), _p(y), _p(z), i, _p(idx), n, m,
+                              _p(M), _p(rhs), _p(s))
+    return st, M, rhs, float(s[0])
+
+
+def weights3(x, y, z, nbr, m: int, n: int, rows=None):
+    """Laplacian weights of eq. (1) in three dimensions, uniform (m, n).
+    Returns (w [rows, k_stride], status [rows])."""
+    lib = _load()
+    x, y, z, nbr = _f64(x), _f64(y), _f64(z), _i32(nbr)
+    if nbr.ndim != 2 or nbr.shape[0] != x.shape[0] or y.shape != x.shape or z.shape != x.shape:
+        raise ValueError("x, y, z must be [N] and nbr [N, k_stride]")
+    N, ks = x.shape[0], nbr.shape[1]
+    r = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    nr = N if r is None else r.shape[0]
+    w = np.empty((nr, ks))
+    st = np.empty(nr, dtype=np.int32)
+    rc = lib.oracle_weights3(N, _p(x), _p(y), _p(z), _p(nbr), ks, m, n, _p(r), nr,
+                             _p(w), _p(st))
+    if rc != 0:
+        raise ValueError(f"oracle_weights3: error {rc}")
+    return w, st
 
 
 def assemble(x, y, i: int, idx, m: int):

@@ -898,3 +898,227 @@ int oracle_time_steps(int64_t n_nodes, const int32_t *nbr, int32_t k_stride, int
     free(next);
     return 0;
 }
+
+/* ---------------------------------------------------------------------- */
+/* Three dimensions (eq. (1) and eq. (2) are written for any d)            */
+/* ---------------------------------------------------------------------- */
+
+/*
+ *   oracle_knn3       N(x) for nodes in R^3, keys (d2, j) with
+ *                     d2 = fl(fl(fl(dx*dx) + fl(dy*dy)) + fl(dz*dz)).
+ *   oracle_weights3   w of eq. (1) for L = Laplacian in d = 3: phi(r) = r^3
+ *                     (lap r^3 = (3d + 3) r = 12 r), all 3-D monomials of
+ *                     degree <= m in graded order (inside a degree the x
+ *                     exponent descending, then the y exponent descending:
+ *                     1, x, y, z, x^2, xy, xz, y^2, yz, z^2, ...), evaluated
+ *                     as (u^a * v^b) * t^c with powers by repeated
+ *                     multiplication; rhs_{n+j} = lap p_j(0) = 2 for x^2,
+ *                     y^2, z^2, else 0.  Scale, LU, solves, w = z / s^2 and
+ *                     the status rules as in two dimensions.
+ */
+
+static int n_monomials3(int m) { return (m + 1) * (m + 2) * (m + 3) / 6; }
+
+int oracle_knn3(int64_t n_nodes, const double *x, const double *y, const double *z,
+                int32_t k, const int64_t *queries, int64_t nq, int32_t *nbr)
+{
+    if (n_nodes < 1 || k < 1 || k > n_nodes || nq < 0)
+        return OR_EARG;
+    double *bd = (double *)malloc(sizeof(double) * (size_t)k);
+    int64_t *bj = (int64_t *)malloc(sizeof(int64_t) * (size_t)k);
+    if (!bd || !bj) {
+        free(bd);
+        free(bj);
+        return OR_ENOMEM;
+    }
+    for (int64_t t = 0; t < nq; ++t) {
+        int64_t i = queries ? queries[t] : t;
+        if (i < 0 || i >= n_nodes) {
+            free(bd);
+            free(bj);
+            return OR_EARG;
+        }
+        int cnt = 0;
+        for (int64_t j = 0; j < n_nodes; ++j) {
+            double dx = x[j] - x[i];
+            double dy = y[j] - y[i];
+            double dz = z[j] - z[i];
+            double ax = dx * dx;
+            double ay = dy * dy;
+            double az = dz * dz;
+            double d2 = (ax + ay) + az;
+            if (isnan(d2))
+                continue;
+            if (cnt == k && !key_before(d2, j, bd[k - 1], bj[k - 1]))
+                continue;
+            int p = (cnt < k) ? cnt : k - 1;
+            while (p > 0 && key_before(d2, j, bd[p - 1], bj[p - 1])) {
+                bd[p] = bd[p - 1];
+                bj[p] = bj[p - 1];
+                --p;
+            }
+            bd[p] = d2;
+            bj[p] = j;
+            if (cnt < k)
+                ++cnt;
+        }
+        for (int s = 0; s < k; ++s)
+            nbr[t * k + s] = (s < cnt) ? (int32_t)bj[s] : -1;
+    }
+    free(bd);
+    free(bj);
+    return 0;
+}
+
+static void monomial_exponents3(int m, int *ea, int *eb, int *ec)
+{
+    int j = 0;
+    for (int deg = 0; deg <= m; ++deg)
+        for (int a = deg; a >= 0; --a)
+            for (int b = deg - a; b >= 0; --b) {
+                ea[j] = a;
+                eb[j] = b;
+                ec[j] = deg - a - b;
+                ++j;
+            }
+}
+
+/* M (K x K, K = n + M3(m)) and rhs for node i of a 3-D node set; returns the
+ * status and, on OR_OK, the scale s.  Same definitions as oracle_assemble
+ * with a third coordinate. */
+int oracle_assemble3(int64_t n_nodes, const double *x, const double *y, const double *z,
+                     int64_t i, const int32_t *idx, int n, int m,
+                     double *M, double *rhs, double *s_out)
+{
+    const int NM = n_monomials3(m);
+    const int K = n + NM;
+    if (m < 0 || m > 6 || n < 1 || n > 1024)
+        return OR_EARG;
+    for (int k = 0; k < n; ++k)
+        if (idx[k] < 0 || (int64_t)idx[k] >= n_nodes || i < 0 || i >= n_nodes)
+            return OR_BAD_INDEX;
+    double *u = (double *)malloc(sizeof(double) * (size_t)n * 3);
+    double *v = u + n, *t = u + 2 * n;
+    double d2max = 0.0;
+    int finite = 1;
+    for (int k = 0; k < n; ++k) {
+        double dx = x[idx[k]] - x[i];
+        double dy = y[idx[k]] - y[i];
+        double dz = z[idx[k]] - z[i];
+        if (!isfinite(dx) || !isfinite(dy) || !isfinite(dz))
+            finite = 0;
+        double d2 = (dx * dx + dy * dy) + dz * dz;
+        if (d2 > d2max)
+            d2max = d2;
+        u[k] = dx;
+        v[k] = dy;
+        t[k] = dz;
+    }
+    if (!finite) {
+        free(u);
+        return OR_NONFINITE;
+    }
+    double s = sqrt(d2max);
+    if (!isfinite(s)) {
+        free(u);
+        return OR_NONFINITE;
+    }
+    if (s == 0.0) {
+        free(u);
+        return OR_DUPLICATE;
+    }
+    for (int k = 0; k < n; ++k) {
+        u[k] = u[k] / s;
+        v[k] = v[k] / s;
+        t[k] = t[k] / s;
+    }
+    int ea[84], eb[84], ec[84];
+    monomial_exponents3(m, ea, eb, ec);
+    int dup = 0;
+    memset(M, 0, sizeof(double) * (size_t)K * (size_t)K);
+    for (int k = 0; k < n; ++k) {
+        for (int l = 0; l < n; ++l) {
+            double ex = u[k] - u[l];
+            double ey = v[k] - v[l];
+            double ez = t[k] - t[l];
+            double rr = (ex * ex + ey * ey) + ez * ez;
+            if (l != k && rr == 0.0)
+                dup = 1;
+            M[k * K + l] = rr * sqrt(rr);
+        }
+        double pu[8], pv[8], pt[8];
+        pu[0] = pv[0] = pt[0] = 1.0;
+        for (int a = 1; a <= m; ++a) {
+            pu[a] = pu[a - 1] * u[k];
+            pv[a] = pv[a - 1] * v[k];
+            pt[a] = pt[a - 1] * t[k];
+        }
+        for (int j = 0; j < NM; ++j) {
+            double p = (pu[ea[j]] * pv[eb[j]]) * pt[ec[j]];
+            M[k * K + n + j] = p;
+            M[(n + j) * K + k] = p;
+        }
+        double r0 = (u[k] * u[k] + v[k] * v[k]) + t[k] * t[k];
+        rhs[k] = 12.0 * sqrt(r0);
+    }
+    for (int j = 0; j < NM; ++j) {
+        int sq = (ea[j] == 2 && eb[j] == 0 && ec[j] == 0) ||
+                 (ea[j] == 0 && eb[j] == 2 && ec[j] == 0) ||
+                 (ea[j] == 0 && eb[j] == 0 && ec[j] == 2);
+        rhs[n + j] = sq ? 2.0 : 0.0;
+    }
+    free(u);
+    if (dup)
+        return OR_DUPLICATE;
+    *s_out = s;
+    return OR_OK;
+}
+
+/* Weights of eq. (1) (Laplacian, d = 3) for every listed node: node
+ * i = rows[t] (or t) uses nbr[i*k_stride ..][0..n) and writes
+ * w[t*k_stride + k] = z_k / (s*s) for k < n, 0 up to k_stride, NaN and the
+ * status code for a failed stencil. */
+int oracle_weights3(int64_t n_nodes, const double *x, const double *y, const double *z,
+                    const int32_t *nbr, int32_t k_stride, int32_t m, int32_t n,
+                    const int64_t *rows, int64_t n_rows, double *w, int32_t *status)
+{
+    if (m < 0 || m > 6 || n < n_monomials3(m) || n > k_stride || n > 1024)
+        return OR_EARG;
+    const int K = n + n_monomials3(m);
+    double *M = (double *)malloc(sizeof(double) * (size_t)K * (size_t)K);
+    double *b = (double *)malloc(sizeof(double) * (size_t)K);
+    double *dinv = (double *)malloc(sizeof(double) * (size_t)K);
+    int32_t *perm = (int32_t *)malloc(sizeof(int32_t) * (size_t)K);
+    if (!M || !b || !dinv || !perm) {
+        free(M); free(b); free(dinv); free(perm);
+        return OR_ENOMEM;
+    }
+    int rc = 0;
+    for (int64_t t = 0; t < n_rows; ++t) {
+        int64_t i = rows ? rows[t] : t;
+        if (i < 0 || i >= n_nodes) {
+            rc = OR_EARG;
+            break;
+        }
+        double s = 0.0;
+        int st = oracle_assemble3(n_nodes, x, y, z, i, nbr + i * (int64_t)k_stride, n, m,
+                                  M, b, &s);
+        if (st == OR_OK)
+            st = oracle_lu(K, M, perm, dinv);
+        if (st == OR_OK) {
+            oracle_lu_solve(K, M, perm, dinv, b);
+            for (int q = 0; q < K; ++q)
+                if (!isfinite(b[q]))
+                    st = OR_NONFINITE;
+        }
+        double *wr = w + t * (int64_t)k_stride;
+        for (int k = 0; k < n; ++k)
+            wr[k] = st == OR_OK ? b[k] / (s * s) : NAN;
+        for (int k = n; k < k_stride; ++k)
+            wr[k] = 0.0;
+        if (status)
+            status[t] = st;
+    }
+    free(M); free(b); free(dinv); free(perm);
+    return rc;
+}
