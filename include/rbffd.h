@@ -163,6 +163,38 @@ int rbffd_weights_op(const double *x, const double *y, int64_t n_nodes, const in
                      int32_t *status, void *stream);
 
 /* ==========================================================================
+ * Three-dimensional nodes (eq. (1) and eq. (2) hold for any dimension d; the
+ * paper's experiments are 2-D).  Node coordinates x, y, z: [n_nodes] FP64,
+ * device.
+ *
+ * rbffd_knn3: N(x) in R^3, as rbffd_knn: the k nearest nodes (self first),
+ * ascending by (d2, index) with d2 = fl(fl(fl(dx^2) + fl(dy^2)) + fl(dz^2)),
+ * NaN keys never taken, -1 for unfillable slots.  nbr: [n_nodes][k] int32
+ * out.  1 <= k <= min(64, n_nodes) (k > 64: RBFFD_ERR_UNSUPPORTED).
+ * Workspace from rbffd_knn3_workspace_size (cell grid, cell-sorted copy of
+ * the nodes).
+ *
+ * rbffd_weights3: Laplacian weights of eq. (1) in d = 3: phi(r) = r^3 with
+ * lap r^3 = 12 r, the ten monomials of degree <= m = 2 in graded order
+ * (1, x, y, z, x^2, xy, xz, y^2, yz, z^2; rhs 2 for x^2, y^2, z^2), the
+ * scale s = max |x_k - x_i| (IEEE division by s, w_ik = z_k / s^2), dense
+ * LU with partial pivoting (first maximum |entry| in the current order),
+ * multipliers a * (1 / pivot), fma updates, the rhs carried along, back
+ * substitution with the pivot reciprocals, as in two dimensions.  Status
+ * codes and their precedence as in rbffd_weights.  nbr: [n_nodes][k_stride]
+ * int32, first n columns used; w: [n_nodes][k_stride] FP64 out, zero past n;
+ * status: [n_nodes] int32 out or NULL.  m must be 2 and 10 <= n <= k_stride
+ * (RBFFD_ERR_ARG otherwise); n > 54 (K = n + 10 > 64) returns
+ * RBFFD_ERR_UNSUPPORTED.  No workspace.
+ * ======================================================================== */
+int rbffd_knn3_workspace_size(int64_t n_nodes, int32_t k, size_t *bytes /* host */);
+int rbffd_knn3(const double *x, const double *y, const double *z, int64_t n_nodes, int32_t k,
+               int32_t *nbr, void *workspace, size_t workspace_bytes, void *stream);
+int rbffd_weights3(const double *x, const double *y, const double *z, int64_t n_nodes,
+                   const int32_t *nbr, int32_t k_stride, int32_t m, int32_t n, double *w,
+                   int32_t *status, void *stream);
+
+/* ==========================================================================
  * Tuning of the mixed-order batch (rbffd_weights with a per-node order and
  * the standard supports n = 12/30/56, FP64), which runs as one persistent
  * launch: blocks_per_cu blocks of 128 threads per compute unit pull tiles

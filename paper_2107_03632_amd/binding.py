@@ -61,6 +61,9 @@ def _load():
             "rbffd_time_steps": ([I64, P, I32, I32, P, P, P, ctypes.c_double, I64, P, P, P, SZ,
                                   P], ctypes.c_int),
             "rbffd_weights_op": ([P, P, I64, P, I32, I32, I32, I32, P, P, P], ctypes.c_int),
+            "rbffd_knn3_workspace_size": ([I64, I32, PSZ], ctypes.c_int),
+            "rbffd_knn3": ([P, P, P, I64, I32, P, P, ctypes.c_size_t, P], ctypes.c_int),
+            "rbffd_weights3": ([P, P, P, I64, P, I32, I32, I32, P, P, P], ctypes.c_int),
             "rbffd_solve_workspace_size": ([I64, PSZ], ctypes.c_int),
             "rbffd_solve": ([I64, P, P, P, P, P, ctypes.c_double, I32,
                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
@@ -223,6 +226,41 @@ def rbffd_weights_op(x, y, nbr, m: int, n: int, op: int, out=None, status=None):
     st = status if status is not None else torch.empty(N, dtype=torch.int32, device=x.device)
     _check(lib.rbffd_weights_op(_p(x), _p(y), N, _p(nbr), ks, int(m), int(n), int(op), _p(w),
                                 _p(st), _stream(x.device)), "rbffd_weights_op")
+    return w, st
+
+
+def rbffd_knn3(x, y, z, k: int, out=None):
+    """Supports of nodes in R^3: nbr [N, k] int32 (self first, ascending
+    (d^2, index))."""
+    lib = _load()
+    x = _dev(x, torch.float64, "x")
+    y = _dev(y, torch.float64, "y")
+    z = _dev(z, torch.float64, "z")
+    N = x.shape[0]
+    if y.shape[0] != N or z.shape[0] != N:
+        raise RbffdError("x, y and z must have the same length")
+    ws = _workspace(_size(lib.rbffd_knn3_workspace_size, N, int(k)), x.device)
+    nbr = out if out is not None else torch.empty((N, k), dtype=torch.int32, device=x.device)
+    _check(lib.rbffd_knn3(_p(x), _p(y), _p(z), N, int(k), _p(nbr), _p(ws), ws.numel(),
+                          _stream(x.device)), "rbffd_knn3")
+    return nbr
+
+
+def rbffd_weights3(x, y, z, nbr, m: int = 2, n: int = 20, out=None, status=None):
+    """Laplacian weights of eq. (1) for nodes in R^3 (r^3 + monomials of
+    degree <= 2), FP64.  Returns (w [N, k_stride], status [N])."""
+    lib = _load()
+    x = _dev(x, torch.float64, "x")
+    y = _dev(y, torch.float64, "y")
+    z = _dev(z, torch.float64, "z")
+    nbr = _dev(nbr, torch.int32, "nbr")
+    N, ks = nbr.shape
+    if x.shape[0] != N or y.shape[0] != N or z.shape[0] != N:
+        raise RbffdError("x, y, z must be [N] and nbr [N, k_stride]")
+    w = out if out is not None else torch.empty((N, ks), dtype=torch.float64, device=x.device)
+    st = status if status is not None else torch.empty(N, dtype=torch.int32, device=x.device)
+    _check(lib.rbffd_weights3(_p(x), _p(y), _p(z), N, _p(nbr), ks, int(m), int(n), _p(w),
+                              _p(st), _stream(x.device)), "rbffd_weights3")
     return w, st
 
 

@@ -1,0 +1,285 @@
+// Laplacian stencil weights of eq. (1) for nodes in three dimensions: the
+// polyharmonic spline r^3 (lap r^3 = 12 r in 3-D) augmented with the ten
+// monomials of degree <= 2 in (x, y, z), on the node's n nearest neighbours
+// (10 <= n <= 54, so K = n + 10 <= 64), shifted to the node and scaled to a
+// unit stencil.
+//
+// One wavefront per stencil, one row of [A P; P^T 0 | rhs] per lane, in
+// registers.  Rows never move: each lane tracks the position its row holds
+// in the partially pivoted order.  Per column: the pivot is the not yet
+// pivoted row with the largest |a| (ties to the lowest position), its
+// entries are broadcast with readlane, the multipliers a * (1 / pivot)
+// replace the column and every other live row takes fma(-l, u, a), the
+// right-hand side carried along.  Back substitution runs from the last
+// position to the first, multiplying by the pivot's reciprocal and
+// broadcasting each solved unknown.  The operations and their order are
+// those of a partial-pivoting LU followed by the two triangular solves, so
+// the weights are the same doubles as a sequential evaluation of that
+// definition.
+
+#include "common.h"
+#include "weights_ms.h"
+
+namespace rbffd {
+namespace {
+
+constexpr int kMono3 = 10;   // monomials of degree <= 2 in three variables
+constexpr int kWaves3 = 4;   // stencils (wavefronts) per block
+
+enum : uint32_t { G_BADIDX = 1u, G_NONFIN = 2u, G_DUP = 4u, G_ZBAD = 8u };
+enum : uint32_t { G_LU_SING = 1u, G_LU_NONFIN = 2u };
+
+__device__ __forceinline__ double bcast_d(double v, int lane) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+    return wk::seg_all<kWave, wk::OpMax>(v, 0);
+}
+
+__device__ __forceinline__ uint32_t wave_or_u32(uint32_t v) {
+    return wk::seg_all<kWave, wk::OpOr>(v, 0);
+}
+
+// the ten monomials at (u, v, t): 1, x, y, z, x^2, xy, xz, y^2, yz, z^2
+__device__ __forceinline__ double mono3(int j, double u, double v, double t) {
+    switch (j) {
+    case 0: return 1.0;
+    case 1: return u;
+    case 2: return v;
+    case 3: return t;
+    case 4: return u * u;
+    case 5: return u * v;
+    case 6: return u * t;
+    case 7: return v * v;
+    case 8: return v * t;
+    default: return t * t;
+    }
+}
+
+// occupancy target: 4 wavefronts per SIMD (at most 128 VGPRs) with 32 rows,
+// 1 with 64 (its 130 KB of LDS per block allow no more)
+template <int KP>
+__global__ __launch_bounds__(kWave * kWaves3)
+__attribute__((amdgpu_waves_per_eu(KP == 32 ? 4 : 1))) void weights3_kernel(
+    const double *__restrict__ x, const double *__restrict__ y, const double *__restrict__ z,
+    int64_t n_nodes, const int32_t *__restrict__ nbr, int32_t k_stride, int n, int64_t n_rows,
+    double *__restrict__ w, int32_t *__restrict__ status) {
+    static_assert(KP == 32 || KP == 64, "rows per wavefront");
+    // per wavefront: the scaled offsets and monomials during assembly, then
+    // the rows of U (stride KP + 1) for the back substitution
+    constexpr int kAsm = 3 * KP + KP * (kMono3 + 1), kRows = KP * (KP + 1);
+    __shared__ double s_buf[kWaves3][kAsm > kRows ? kAsm : kRows];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
+    double(*s_u)[KP] = reinterpret_cast<double(*)[KP]>(&s_buf[wv][0]);
+    double(*s_p)[kMono3 + 1] = reinterpret_cast<double(*)[kMono3 + 1]>(&s_buf[wv][3 * KP]);
+    double *s_U = &s_buf[wv][0];
+    const int64_t i = (int64_t)blockIdx.x * kWaves3 + wv;
+    if (i >= n_rows) return;  // whole wavefronts only; no block barrier below
+    const int K = n + kMono3;
+
+    // ---- shift and scale -------------------------------------------------
+    uint32_t flags = 0;
+    double dx = 0.0, dy = 0.0, dz = 0.0, d2 = 0.0;
+    const double xi = x[i], yi = y[i], zi = z[i];
+    if (lane < n) {
+        const int32_t j = nbr[i * (int64_t)k_stride + lane];
+        if (j < 0 || (int64_t)j >= n_nodes) {
+            flags |= G_BADIDX;
+        } else {
+            const double ex = x[j] - xi, ey = y[j] - yi, ez = z[j] - zi;
+            if (!isfinite(ex) || !isfinite(ey) || !isfinite(ez)) {
+                flags |= G_NONFIN;
+            } else {
+                dx = ex;
+                dy = ey;
+                dz = ez;
+                d2 = (ex * ex + ey * ey) + ez * ez;
+            }
+        }
+    }
+    // d2 >= 0 (or +inf), so its bit pattern orders like its value
+    const uint64_t d2b = (uint64_t)__double_as_longlong(d2);
+    const uint32_t mh = wave_max_u32((uint32_t)(d2b >> 32));
+    const uint32_t ml = wave_max_u32((uint32_t)(d2b >> 32) == mh ? (uint32_t)d2b : 0u);
+    const double sc = sqrt(__longlong_as_double((long long)(((uint64_t)mh << 32) | ml)));
+    if (!isfinite(sc)) flags |= G_NONFIN;
+    if (sc == 0.0) flags |= G_DUP;
+    const double ux = dx / sc, uy = dy / sc, uz = dz / sc;
+    if (lane < KP) {
+        s_u[0][lane] = lane < n ? ux : 0.0;
+        s_u[1][lane] = lane < n ? uy : 0.0;
+        s_u[2][lane] = lane < n ? uz : 0.0;
+#pragma unroll
+        for (int j = 0; j < kMono3; ++j) s_p[lane][j] = lane < n ? mono3(j, ux, uy, uz) : 0.0;
+    }
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_wave_barrier();  // one wavefront: its LDS accesses are in order
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+
+    // ---- this lane's row ---------------------------------------------------
+    const bool prow = lane < n;
+    const bool qrow = lane >= n && lane < K;
+    const int jr = qrow ? lane - n : 0;
+    double a[KP];
+    double b = 0.0;
+#pragma unroll
+    for (int q = 0; q < KP; ++q) {
+        double v = 0.0;
+        if (q < n) {
+            if (prow) {
+                const double ex = ux - s_u[0][q];
+                const double ey = uy - s_u[1][q];
+                const double ez = uz - s_u[2][q];
+                const double rr = (ex * ex + ey * ey) + ez * ez;
+                if (q != lane && rr == 0.0) flags |= G_DUP;
+                v = rr * sqrt(rr);
+            } else if (qrow) {
+                v = s_p[q][jr];
+            }
+        } else if (q < K) {
+            v = prow ? s_p[lane][q - n] : 0.0;
+        } else if (q == lane) {
+            v = 1.0;  // identity padding up to KP
+        }
+        a[q] = v;
+        // one column at a time: hoisting every column's loads would hold
+        // 3 KP offsets in registers at once
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (prow) {
+        const double r0 = (ux * ux + uy * uy) + uz * uz;
+        b = 12.0 * sqrt(r0);
+    } else if (qrow) {
+        b = (jr == 4 || jr == 7 || jr == 9) ? 2.0 : 0.0;  // lap of x^2, y^2, z^2
+    }
+
+    // ---- LU with partial pivoting, right-hand side carried along ----------
+    // Rows K .. KP-1 are identity padding: they take no multiplier in the
+    // first K columns (their entries there are 0, and a lower position wins
+    // ties), and the real rows are all pivoted by then, so the padding
+    // columns change nothing of the real solution.  Lanes past KP sit out.
+    int pos = lane;             // position of this lane's row
+    bool done = lane >= KP;     // pivoted already (or outside the system)
+    double my_inv = 0.0, my_piv = 1.0;
+#pragma unroll
+    for (int c = 0; c < KP; ++c) {
+        const uint64_t bits = (uint64_t)__double_as_longlong(a[c]) & 0x7fffffffffffffffull;
+        const uint32_t kh = done ? 0u : (uint32_t)(bits >> 32) + 1u;
+        const uint32_t hmax = wave_max_u32(kh);
+        uint64_t cand = __ballot(!done && kh == hmax);
+        if ((cand & (cand - 1ull)) != 0ull) {
+            // equal high words: the low words, then the lowest position
+            const bool in = (cand >> lane) & 1ull;
+            const uint32_t kl = in ? (uint32_t)bits : 0u;
+            const uint32_t lmax = wave_max_u32(kl);
+            const bool in2 = in && kl == lmax;
+            const uint32_t pk = in2 ? (uint32_t)(KP - pos) : 0u;
+            const uint32_t pmax = wave_max_u32(pk);
+            cand = __ballot(in2 && pk == pmax);
+        }
+        const int win = __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)cand) - 1);
+        const int kp = __builtin_amdgcn_readlane(pos, win);
+        const double piv = bcast_d(a[c], win);
+        const double inv = 1.0 / piv;
+        const bool isp = lane == win;
+        my_inv = isp ? inv : my_inv;
+        my_piv = isp ? piv : my_piv;
+        pos = isp ? c : ((!done && pos == c) ? kp : pos);
+        done = done || isp;
+        // in place, as above: deferred, every column's pivot and mask would
+        // stay live to the end
+        int dn = done ? 1 : 0;
+        asm volatile("" : "+v"(my_inv), "+v"(my_piv), "+v"(pos), "+v"(dn));
+        done = dn != 0;
+        const double l = done ? 0.0 : a[c] * inv;
+        a[c] = done ? a[c] : l;
+        asm volatile("" : "+v"(a[c]));
+#pragma unroll
+        for (int q = c + 1; q < KP; ++q) {
+            const double u = bcast_d(a[q], win);
+            const double nv = fma(-l, u, a[q]);
+            a[q] = done ? a[q] : nv;
+            // the select happens here: deferred to the entry's next use, it
+            // would keep both values and every column's mask alive
+            asm volatile("" : "+v"(a[q]));
+        }
+        const double ub = bcast_d(b, win);
+        const double nb = fma(-l, ub, b);
+        b = done ? b : nb;
+        asm volatile("" : "+v"(b));
+    }
+
+    // ---- back substitution: z_c = y_c / U_cc, from the last position -------
+    // the rows of U (and of L, unused here) to LDS by position: keeping them
+    // in registers through the substitution doubles the register count
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_wave_barrier();  // the assembly tables are dead
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    const int prow_u = pos < KP ? pos : 0;
+    if (lane < KP) {
+#pragma unroll
+        for (int q = 0; q < KP; ++q) s_U[prow_u * (KP + 1) + q] = a[q];
+    }
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_wave_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    double zf = 0.0;
+#pragma unroll
+    for (int c = KP - 1; c >= 0; --c) {
+        const uint64_t at = __ballot(pos == c);
+        const int wl = __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)at) - 1);
+        const double zc = bcast_d(b * my_inv, wl);
+        if (lane == wl) zf = zc;
+        if (pos < c) b = fma(-s_U[prow_u * (KP + 1) + c], zc, b);
+    }
+
+    // ---- status and output ------------------------------------------------
+    uint32_t lukey = 0;
+    if (pos < K) {
+        const uint32_t f = !isfinite(my_piv) ? G_LU_NONFIN : (my_piv == 0.0 ? G_LU_SING : 0u);
+        if (f) lukey = ((uint32_t)(KP - pos) << 2) | f;
+        if (!isfinite(zf)) flags |= G_ZBAD;
+    }
+    const uint32_t luflag = wave_max_u32(lukey) & 3u;
+    const uint32_t fl = wave_or_u32(flags);
+    int st = RBFFD_OK;
+    if (fl & G_BADIDX) st = RBFFD_BAD_INDEX;
+    else if (fl & G_NONFIN) st = RBFFD_NONFINITE;
+    else if (fl & G_DUP) st = RBFFD_DUPLICATE;
+    else if (luflag == G_LU_NONFIN) st = RBFFD_NONFINITE;
+    else if (luflag == G_LU_SING) st = RBFFD_SINGULAR;
+    else if (fl & G_ZBAD) st = RBFFD_NONFINITE;
+    const bool good = st == RBFFD_OK;
+    double *wi = w + i * (int64_t)k_stride;
+    const double s2 = sc * sc;
+    if (pos < n) wi[pos] = good ? zf / s2 : __builtin_nan("");
+    for (int q = n + lane; q < k_stride; q += kWave) wi[q] = 0.0;
+    if (lane == 0 && status) status[i] = st;
+}
+
+}  // namespace
+}  // namespace rbffd
+
+using namespace rbffd;
+
+extern "C" int rbffd_weights3(const double *x, const double *y, const double *z,
+                              int64_t n_nodes, const int32_t *nbr, int32_t k_stride, int32_t m,
+                              int32_t n, double *w, int32_t *status, void *stream) {
+    if (!x || !y || !z || !nbr || !w || n_nodes < 1 || n_nodes >= INT32_MAX || k_stride < 1 ||
+        n > k_stride || m != 2 || n < kMono3)
+        return RBFFD_ERR_ARG;
+    if (n + kMono3 > 64) return RBFFD_ERR_UNSUPPORTED;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const unsigned nb = (unsigned)ceil_div(n_nodes, kWaves3);
+    if (n + kMono3 <= 32)
+        hipLaunchKernelGGL(weights3_kernel<32>, dim3(nb), dim3(kWave * kWaves3), 0, s, x, y, z,
+                           n_nodes, nbr, k_stride, (int)n, n_nodes, w, status);
+    else
+        hipLaunchKernelGGL(weights3_kernel<64>, dim3(nb), dim3(kWave * kWaves3), 0, s, x, y, z,
+                           n_nodes, nbr, k_stride, (int)n, n_nodes, w, status);
+    return last_launch_rc();
+}

@@ -143,6 +143,20 @@ def annulus(n_target: int = 200_000, r_in: float = 0.3, r_out: float = 1.0,
     return _pack(f"annulus_{n_target}", xi, yi, xb, yb, h, seed=seed)
 
 
+def jittered_cube(cells: int = 100, seed: int = 6, jitter: float = 0.25):
+    """Three-dimensional nodes: the cell-centred cells^3 lattice of [0,1]^3
+    (spacing h = 1/cells), each coordinate jittered by U(-jitter h, jitter h),
+    in lattice order (x fastest).  Returns (x, y, z) float64 arrays."""
+    rng = _rng(seed)
+    h = 1.0 / cells
+    g = (np.arange(cells) + 0.5) * h
+    Z, Y, X = np.meshgrid(g, g, g, indexing="ij")
+    pts = np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1)
+    pts += rng.uniform(-jitter * h, jitter * h, pts.shape)
+    return (np.ascontiguousarray(pts[:, 0]), np.ascontiguousarray(pts[:, 1]),
+            np.ascontiguousarray(pts[:, 2]))
+
+
 def manufactured(x: np.ndarray, y: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
     """Manufactured Poisson data: u = sin(pi x) sin(pi y) and
     f = lap u = -2 pi^2 sin(pi x) sin(pi y)."""

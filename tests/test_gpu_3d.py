@@ -1,0 +1,177 @@
+"""Three-dimensional supports (rbffd_knn3) and Laplacian weights
+(rbffd_weights3) against the oracle's knn3 / weights3.
+
+kNN is compared index for index.  The weights take the same operations in
+the same order as the oracle's LU and solves, so they are compared double
+for double (NaN where the stencil failed), status for status.  At the full
+size (a jittered 100^3 lattice, one launch of every row) the oracle runs on
+sampled rows, and every row is checked for exact reproduction of the
+quadratics (the polynomial part of eq. (1)).
+"""
+
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2107_03632_amd import binding as rb
+from paper_2107_03632_amd import nodes
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible GPU")
+    rb.library_path()
+
+
+def lattice_with_ties():
+    g = np.arange(7, dtype=np.float64)
+    Z, Y, X = np.meshgrid(g, g, g, indexing="ij")
+    x, y, z = X.ravel().copy(), Y.ravel().copy(), Z.ravel().copy()
+    x[5], y[5], z[5] = x[9], y[9], z[9]   # a duplicate node
+    z[11] = np.nan                        # never selected
+    return x, y, z
+
+
+@pytest.mark.parametrize("k", [1, 10, 20, 27, 45, 64])
+def test_knn3_bit_exact(k):
+    x, y, z = nodes.jittered_cube(12, seed=21)
+    say("knn3 cube 1728", k)
+    ref = oracle.knn3(x, y, z, k)
+    got = host(rb.rbffd_knn3(dev(x), dev(y), dev(z), k))
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("k", [7, 20, 33])
+def test_knn3_ties_dups_nan(k):
+    x, y, z = lattice_with_ties()
+    say("knn3 lattice 343 with ties", k)
+    ref = oracle.knn3(x, y, z, k)
+    got = host(rb.rbffd_knn3(dev(x), dev(y), dev(z), k))
+    assert np.array_equal(got, ref)
+
+
+def test_knn3_flat_and_tiny():
+    # coplanar nodes (a flat bounding box) and a set of exactly k nodes
+    rng = np.random.default_rng(5)
+    x, y = rng.random(500), rng.random(500)
+    z = np.zeros(500)
+    say("knn3 flat 500")
+    assert np.array_equal(host(rb.rbffd_knn3(dev(x), dev(y), dev(z), 20)),
+                          oracle.knn3(x, y, z, 20))
+    x, y, z = rng.random((3, 6))
+    assert np.array_equal(host(rb.rbffd_knn3(dev(x), dev(y), dev(z), 6)),
+                          oracle.knn3(x, y, z, 6))
+
+
+def check_weights3(x, y, z, nbr, n, label):
+    w_ref, st_ref = oracle.weights3(x, y, z, nbr, 2, n)
+    say(label, "n", n, "stencils", nbr.shape[0], "statuses", np.bincount(st_ref))
+    w, st = rb.rbffd_weights3(dev(x), dev(y), dev(z), dev(nbr), 2, n)
+    w, st = host(w), host(st)
+    assert np.array_equal(st, st_ref)
+    ok = st_ref == 0
+    assert np.array_equal(w[ok], w_ref[ok])
+    assert np.all(np.isnan(w[~ok][:, :n]))
+    assert np.all(w[:, n:] == 0.0)
+    return w, st
+
+
+@pytest.mark.parametrize("n", [10, 20, 22, 23, 40, 54])
+def test_weights3_bit_exact(n):
+    x, y, z = nodes.jittered_cube(11, seed=22)
+    nbr = oracle.knn3(x, y, z, 64)
+    check_weights3(x, y, z, np.ascontiguousarray(nbr[:, :n]), n, "cube 1331, k_stride n")
+    check_weights3(x, y, z, nbr, n, "cube 1331, k_stride 64")
+
+
+@pytest.mark.parametrize("n", [20, 40])
+def test_weights3_lattice_ties(n):
+    g = np.arange(9, dtype=np.float64) / 8.0
+    Z, Y, X = np.meshgrid(g, g, g, indexing="ij")
+    x, y, z = X.ravel().copy(), Y.ravel().copy(), Z.ravel().copy()
+    nbr = np.ascontiguousarray(oracle.knn3(x, y, z, n))
+    check_weights3(x, y, z, nbr, n, "exact lattice 729")
+
+
+@pytest.mark.parametrize("n", [20, 40])
+def test_weights3_status_codes(n):
+    x, y, z = nodes.jittered_cube(6, seed=23)
+    nbr = oracle.knn3(x, y, z, n)
+    nb = nbr.copy()
+    nb[3, 4] = nb[3, 2]             # duplicate support node
+    nb[4, 7] = len(x) + 1           # out of range
+    nb[5, n - 1] = -1
+    xx = x.copy()
+    xx[nbr[6, 5]] = np.inf          # non-finite coordinate
+    w, st = check_weights3(xx, y, z, nb, n, "status codes")
+    assert np.all(st[3:7] != 0)
+    # coplanar supports: the z monomials vanish -> zero pivot
+    rng = np.random.default_rng(6)
+    xp, yp = rng.random(200), rng.random(200)
+    zp = np.full(200, 0.5)
+    nbp = np.ascontiguousarray(oracle.knn3(xp, yp, zp, n))
+    w, st = check_weights3(xp, yp, zp, nbp, n, "coplanar")
+    assert np.all(st == oracle.SINGULAR)
+
+
+def test_weights3_argument_errors():
+    x, y, z = nodes.jittered_cube(5, seed=24)
+    nbr = np.ascontiguousarray(oracle.knn3(x, y, z, 64))
+    X, Y, Z, NB = dev(x), dev(y), dev(z), dev(nbr)
+    with pytest.raises(rb.RbffdError, match=r"-3"):      # K = 70 > 64
+        rb.rbffd_weights3(X, Y, Z, NB, 2, 60)
+    with pytest.raises(rb.RbffdError, match=r"-1"):      # only m = 2
+        rb.rbffd_weights3(X, Y, Z, NB, 4, 40)
+    with pytest.raises(rb.RbffdError, match=r"-1"):      # n below the monomial count
+        rb.rbffd_weights3(X, Y, Z, NB, 2, 9)
+    with pytest.raises(rb.RbffdError, match=r"-1"):      # n above the row stride
+        rb.rbffd_weights3(X, Y, Z, NB[:, :12].contiguous(), 2, 20)
+
+
+def test_3d_full_size_sampled():
+    x, y, z = nodes.jittered_cube(100, seed=6)
+    N = x.shape[0]
+    say("3-D cube", N, "k = n = 20")
+    X, Y, Z = dev(x), dev(y), dev(z)
+    nb_t = rb.rbffd_knn3(X, Y, Z, 20)
+    nbr = host(nb_t)
+    rng = np.random.default_rng(25)
+    rows = np.sort(rng.choice(N, 200, replace=False))
+    assert np.array_equal(nbr[rows], oracle.knn3(x, y, z, 20, queries=rows))
+    w_t, st_t = rb.rbffd_weights3(X, Y, Z, nb_t, 2, 20)
+    w, st = host(w_t), host(st_t)
+    assert np.all(st == 0)
+    w_ref, st_ref = oracle.weights3(x, y, z, nbr, 2, 20, rows=rows)
+    assert np.array_equal(st[rows], st_ref)
+    assert np.array_equal(w[rows], w_ref)
+    # every row: the quadratics about the centre, exactly up to rounding
+    dx = (x[nbr] - x[:, None]).astype(np.float64)
+    dy = y[nbr] - y[:, None]
+    dz = z[nbr] - z[:, None]
+    for (a, b, c) in [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1), (2, 0, 0), (1, 1, 0),
+                      (1, 0, 1), (0, 2, 0), (0, 1, 1), (0, 0, 2)]:
+        f = dx ** a * dy ** b * dz ** c
+        want = 2.0 if sorted((a, b, c)) == [0, 0, 2] else 0.0
+        got = (w * f).sum(1)
+        rel = np.abs(got - want) / ((np.abs(w * f)).sum(1) + want)
+        assert rel.max() < 1e-9, ((a, b, c), rel.max())
