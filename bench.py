@@ -47,6 +47,18 @@ def weights_flops(m: int, n: int) -> int:
     return lu + solves + assembly
 
 
+def weights3_flops(n: int) -> int:
+    """The same count for the 3-D stencil (m = 2, M = 10, K = n + 10): LU and
+    solves as above; assembly 5 n (n - 1) (half the pairs, 3 differences,
+    3 squares, 2 sums, a square root and a product each), 18 (n - 1) for the
+    offsets, scale and right-hand side, n (M - 1) monomial products, n."""
+    K = n + 10
+    lu = (K - 1) * K // 2 + (K - 1) * K * (2 * K - 1) // 3
+    solves = 2 * K * (K - 1) + K
+    assembly = 5 * n * (n - 1) + 18 * (n - 1) + n * 9 + n
+    return lu + solves + assembly
+
+
 def source_digest(paths) -> str:
     h = hashlib.sha256()
     for p in paths:
@@ -245,6 +257,7 @@ def main():
         out["adjoint_annulus_200k_m4"] = extras_adjoint(torch, rb, nodes, dev, stream)
         out["time_loop_unit_disk"] = extras_time_loop(torch, rb, nodes, dev, stream)
         out["derivative_weights_unit_disk"] = extras_ops(torch, rb, stream, X, Y, ns, m, n)
+        out["laplacian_3d_cube_1m"] = extras_3d(torch, rb, nodes, dev, stream)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(ns, m, n, args.cpu_stride)
@@ -384,6 +397,30 @@ def extras_ops(torch, rb, stream, X, Y, ns, m, n):
                      "failed": int((st != 0).sum().item()),
                      "max_abs_err": (approx - exact[op]).abs().max().item()}
     return res
+
+
+def extras_3d(torch, rb, nodes, dev, stream, n=20):
+    """Three-dimensional nodes: the jittered 100^3 lattice of [0,1]^3, m = 2,
+    n = 20 (K = 30).  kNN and weights per launch, the weights' fraction of
+    the FP64 peak, and the largest error of the weights applied to
+    u = sin(pi x) sin(pi y) sin(pi z) (lap u = -3 pi^2 u) over nodes at least
+    3 h inside the cube."""
+    x, y, z = nodes.jittered_cube(100, seed=6)
+    X, Y, Z = (torch.as_tensor(a, device=dev) for a in (x, y, z))
+    N = x.shape[0]
+    knn_ms = timed(torch, stream, lambda: rb.rbffd_knn3(X, Y, Z, n))
+    nbr = rb.rbffd_knn3(X, Y, Z, n)
+    ms = timed(torch, stream, lambda: rb.rbffd_weights3(X, Y, Z, nbr, 2, n))
+    w, st = rb.rbffd_weights3(X, Y, Z, nbr, 2, n)
+    u = torch.sin(math.pi * X) * torch.sin(math.pi * Y) * torch.sin(math.pi * Z)
+    lap = (w * u[nbr.long()]).sum(1)
+    inner = ((X > 0.03) & (X < 0.97) & (Y > 0.03) & (Y < 0.97) & (Z > 0.03) & (Z < 0.97))
+    err = (lap - (-3.0 * math.pi ** 2) * u)[inner].abs().max().item()
+    fl = weights3_flops(n)
+    return {"n_nodes": N, "m": 2, "n": n, "knn_ms": knn_ms, "weights_ms": ms,
+            "stencils_per_s": N / (ms * 1e-3), "flops_per_stencil": fl,
+            "frac_fp64_peak": fl * N / 1e12 / (ms * 1e-3) / FP64_PEAK_TFLOPS,
+            "failed": int((st != 0).sum().item()), "max_abs_err_inner": err}
 
 
 def extras_adjoint(torch, rb, nodes, dev, stream):
