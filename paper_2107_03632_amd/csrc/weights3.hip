@@ -60,23 +60,21 @@ __device__ __forceinline__ double mono3(int j, double u, double v, double t) {
     }
 }
 
-// occupancy target: 4 wavefronts per SIMD (at most 128 VGPRs) with 32 rows,
-// 1 with 64 (its 130 KB of LDS per block allow no more)
+// occupancy target: 5 wavefronts per SIMD (at most 96 VGPRs) with 32 rows,
+// 3 with 64
 template <int KP>
 __global__ __launch_bounds__(kWave * kWaves3)
-__attribute__((amdgpu_waves_per_eu(KP == 32 ? 4 : 1))) void weights3_kernel(
+__attribute__((amdgpu_waves_per_eu(KP == 32 ? 5 : 3))) void weights3_kernel(
     const double *__restrict__ x, const double *__restrict__ y, const double *__restrict__ z,
     int64_t n_nodes, const int32_t *__restrict__ nbr, int32_t k_stride, int n, int64_t n_rows,
     double *__restrict__ w, int32_t *__restrict__ status) {
     static_assert(KP == 32 || KP == 64, "rows per wavefront");
-    // per wavefront: the scaled offsets and monomials during assembly, then
-    // the rows of U (stride KP + 1) for the back substitution
-    constexpr int kAsm = 3 * KP + KP * (kMono3 + 1), kRows = KP * (KP + 1);
-    __shared__ double s_buf[kWaves3][kAsm > kRows ? kAsm : kRows];
+    // per wavefront: the scaled offsets and monomials of the assembly
+    constexpr int kAsm = 3 * KP + KP * (kMono3 + 1);
+    __shared__ double s_buf[kWaves3][kAsm];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
     double(*s_u)[KP] = reinterpret_cast<double(*)[KP]>(&s_buf[wv][0]);
     double(*s_p)[kMono3 + 1] = reinterpret_cast<double(*)[kMono3 + 1]>(&s_buf[wv][3 * KP]);
-    double *s_U = &s_buf[wv][0];
     const int64_t i = (int64_t)blockIdx.x * kWaves3 + wv;
     if (i >= n_rows) return;  // whole wavefronts only; no block barrier below
     const int K = n + kMono3;
@@ -214,19 +212,6 @@ __attribute__((amdgpu_waves_per_eu(KP == 32 ? 4 : 1))) void weights3_kernel(
     }
 
     // ---- back substitution: z_c = y_c / U_cc, from the last position -------
-    // the rows of U (and of L, unused here) to LDS by position: keeping them
-    // in registers through the substitution doubles the register count
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    __builtin_amdgcn_wave_barrier();  // the assembly tables are dead
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    const int prow_u = pos < KP ? pos : 0;
-    if (lane < KP) {
-#pragma unroll
-        for (int q = 0; q < KP; ++q) s_U[prow_u * (KP + 1) + q] = a[q];
-    }
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    __builtin_amdgcn_wave_barrier();
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
     double zf = 0.0;
 #pragma unroll
     for (int c = KP - 1; c >= 0; --c) {
@@ -234,7 +219,7 @@ __attribute__((amdgpu_waves_per_eu(KP == 32 ? 4 : 1))) void weights3_kernel(
         const int wl = __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)at) - 1);
         const double zc = bcast_d(b * my_inv, wl);
         if (lane == wl) zf = zc;
-        if (pos < c) b = fma(-s_U[prow_u * (KP + 1) + c], zc, b);
+        if (pos < c) b = fma(-a[c], zc, b);
     }
 
     // ---- status and output ------------------------------------------------
