@@ -79,6 +79,8 @@ def _load():
             lib.oracle_assemble3.argtypes = [I64, P, P, P, I64, P, ctypes.c_int,
                                              ctypes.c_int, P, P, P]
             lib.oracle_weights3.argtypes = [I64, P, P, P, P, I32, I32, I32, P, I64, P, P]
+            lib.oracle_weights3_op.argtypes = [I64, P, P, P, P, I32, I32, I32, P, I64, I32,
+                                               P, P]
             lib.oracle_time_steps.argtypes = [I64, P, I32, I32, P, P, P, ctypes.c_double,
                                               I64, P]
             _lib = lib
@@ -172,6 +174,28 @@ def weights3(x, y, z, nbr, m: int, n: int, rows=None):
                              _p(w), _p(st))
     if rc != 0:
         raise ValueError(f"oracle_weights3: error {rc}")
+    return w, st
+
+
+D3_DX, D3_DY, D3_DZ = 1, 2, 3
+
+
+def weights3_op(x, y, z, nbr, m: int, n: int, op: int, rows=None):
+    """Weights of eq. (1) in three dimensions for op (0 Laplacian, D3_DX,
+    D3_DY, D3_DZ), uniform (m, n).  Returns (w [rows, k_stride], status)."""
+    lib = _load()
+    x, y, z, nbr = _f64(x), _f64(y), _f64(z), _i32(nbr)
+    if nbr.ndim != 2 or nbr.shape[0] != x.shape[0] or y.shape != x.shape or z.shape != x.shape:
+        raise ValueError("x, y, z must be [N] and nbr [N, k_stride]")
+    N, ks = x.shape[0], nbr.shape[1]
+    r = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    nr = N if r is None else r.shape[0]
+    w = np.empty((nr, ks))
+    st = np.empty(nr, dtype=np.int32)
+    rc = lib.oracle_weights3_op(N, _p(x), _p(y), _p(z), _p(nbr), ks, m, n, _p(r), nr, int(op),
+                                _p(w), _p(st))
+    if rc != 0:
+        raise ValueError(f"oracle_weights3_op: error {rc}")
     return w, st
 
 

@@ -985,14 +985,28 @@ static void monomial_exponents3(int m, int *ea, int *eb, int *ec)
 
 /* M (K x K, K = n + M3(m)) and rhs for node i of a 3-D node set; returns the
  * status and, on OR_OK, the scale s.  Same definitions as oracle_assemble
- * with a third coordinate. */
+ * with a third coordinate.  op 0 is the Laplacian; ops 1, 2, 3 are d/dx,
+ * d/dy, d/dz: rhs_k = -3 * sqrt(r0) * (u_k, v_k or t_k), left to right (the
+ * derivative of r^3 of node k at the centre), rhs_{n+j} = 1 for the monomial
+ * x, y or z, else 0. */
+int oracle_assemble3_op(int64_t n_nodes, const double *x, const double *y, const double *z,
+                        int64_t i, const int32_t *idx, int n, int m, int op,
+                        double *M, double *rhs, double *s_out);
+
 int oracle_assemble3(int64_t n_nodes, const double *x, const double *y, const double *z,
                      int64_t i, const int32_t *idx, int n, int m,
                      double *M, double *rhs, double *s_out)
 {
+    return oracle_assemble3_op(n_nodes, x, y, z, i, idx, n, m, 0, M, rhs, s_out);
+}
+
+int oracle_assemble3_op(int64_t n_nodes, const double *x, const double *y, const double *z,
+                        int64_t i, const int32_t *idx, int n, int m, int op,
+                        double *M, double *rhs, double *s_out)
+{
     const int NM = n_monomials3(m);
     const int K = n + NM;
-    if (m < 0 || m > 6 || n < 1 || n > 1024)
+    if (m < 0 || m > 6 || n < 1 || n > 1024 || op < 0 || op > 3)
         return OR_EARG;
     for (int k = 0; k < n; ++k)
         if (idx[k] < 0 || (int64_t)idx[k] >= n_nodes || i < 0 || i >= n_nodes)
@@ -1059,13 +1073,18 @@ int oracle_assemble3(int64_t n_nodes, const double *x, const double *y, const do
             M[(n + j) * K + k] = p;
         }
         double r0 = (u[k] * u[k] + v[k] * v[k]) + t[k] * t[k];
-        rhs[k] = 12.0 * sqrt(r0);
+        if (op == 0)
+            rhs[k] = 12.0 * sqrt(r0);
+        else
+            rhs[k] = -3.0 * sqrt(r0) * (op == 1 ? u[k] : (op == 2 ? v[k] : t[k]));
     }
     for (int j = 0; j < NM; ++j) {
         int sq = (ea[j] == 2 && eb[j] == 0 && ec[j] == 0) ||
                  (ea[j] == 0 && eb[j] == 2 && ec[j] == 0) ||
                  (ea[j] == 0 && eb[j] == 0 && ec[j] == 2);
-        rhs[n + j] = sq ? 2.0 : 0.0;
+        int lin = ea[j] + eb[j] + ec[j] == 1 &&
+                  ((op == 1 && ea[j] == 1) || (op == 2 && eb[j] == 1) || (op == 3 && ec[j] == 1));
+        rhs[n + j] = op == 0 ? (sq ? 2.0 : 0.0) : (lin ? 1.0 : 0.0);
     }
     free(u);
     if (dup)
@@ -1078,11 +1097,27 @@ int oracle_assemble3(int64_t n_nodes, const double *x, const double *y, const do
  * i = rows[t] (or t) uses nbr[i*k_stride ..][0..n) and writes
  * w[t*k_stride + k] = z_k / (s*s) for k < n, 0 up to k_stride, NaN and the
  * status code for a failed stencil. */
+int oracle_weights3_op(int64_t n_nodes, const double *x, const double *y, const double *z,
+                       const int32_t *nbr, int32_t k_stride, int32_t m, int32_t n,
+                       const int64_t *rows, int64_t n_rows, int32_t op, double *w,
+                       int32_t *status);
+
 int oracle_weights3(int64_t n_nodes, const double *x, const double *y, const double *z,
                     const int32_t *nbr, int32_t k_stride, int32_t m, int32_t n,
                     const int64_t *rows, int64_t n_rows, double *w, int32_t *status)
 {
-    if (m < 0 || m > 6 || n < n_monomials3(m) || n > k_stride || n > 1024)
+    return oracle_weights3_op(n_nodes, x, y, z, nbr, k_stride, m, n, rows, n_rows, 0, w,
+                              status);
+}
+
+/* The weights of the operator op of oracle_assemble3_op: z_k / s^2 for the
+ * Laplacian, z_k / s for the first derivatives. */
+int oracle_weights3_op(int64_t n_nodes, const double *x, const double *y, const double *z,
+                       const int32_t *nbr, int32_t k_stride, int32_t m, int32_t n,
+                       const int64_t *rows, int64_t n_rows, int32_t op, double *w,
+                       int32_t *status)
+{
+    if (m < 0 || m > 6 || n < n_monomials3(m) || n > k_stride || n > 1024 || op < 0 || op > 3)
         return OR_EARG;
     const int K = n + n_monomials3(m);
     double *M = (double *)malloc(sizeof(double) * (size_t)K * (size_t)K);
@@ -1101,8 +1136,8 @@ int oracle_weights3(int64_t n_nodes, const double *x, const double *y, const dou
             break;
         }
         double s = 0.0;
-        int st = oracle_assemble3(n_nodes, x, y, z, i, nbr + i * (int64_t)k_stride, n, m,
-                                  M, b, &s);
+        int st = oracle_assemble3_op(n_nodes, x, y, z, i, nbr + i * (int64_t)k_stride, n, m,
+                                     op, M, b, &s);
         if (st == OR_OK)
             st = oracle_lu(K, M, perm, dinv);
         if (st == OR_OK) {
@@ -1113,7 +1148,7 @@ int oracle_weights3(int64_t n_nodes, const double *x, const double *y, const dou
         }
         double *wr = w + t * (int64_t)k_stride;
         for (int k = 0; k < n; ++k)
-            wr[k] = st == OR_OK ? b[k] / (s * s) : NAN;
+            wr[k] = st == OR_OK ? b[k] / (op == 0 ? s * s : s) : NAN;
         for (int k = n; k < k_stride; ++k)
             wr[k] = 0.0;
         if (status)

@@ -169,3 +169,79 @@ def test_weights3_status_codes():
     nbp = oracle.knn3(xp, yp, zp, 20)
     w, st = oracle.weights3(xp, yp, zp, nbp, 2, 20)
     assert np.all(st == oracle.SINGULAR)
+
+
+# ---- first derivatives in three dimensions (oracle.weights3_op) -----------
+
+D3 = [(oracle.D3_DX, (1, 0, 0)), (oracle.D3_DY, (0, 1, 0)), (oracle.D3_DZ, (0, 0, 1))]
+
+
+@pytest.mark.parametrize("op,axis", D3)
+@pytest.mark.parametrize("m,n", [(2, 20), (3, 30)])
+def test_weights3_derivative_reproduce_polynomials(op, axis, m, n):
+    x, y, z = jittered_cube(8, seed=15)
+    nb = oracle.knn3(x, y, z, n)
+    rows = np.arange(0, len(x), 29)
+    w, st = oracle.weights3_op(x, y, z, nb, m, n, op, rows=rows)
+    assert np.all(st == oracle.OK)
+    for t, i in enumerate(rows):
+        idx = nb[i]
+        dx, dy, dz = x[idx] - x[i], y[idx] - y[i], z[idx] - z[i]
+        for e in monos3(m):
+            f = dx ** e[0] * dy ** e[1] * dz ** e[2]
+            want = 1.0 if e == axis else 0.0
+            got = np.dot(w[t], f)
+            assert abs(got - want) <= 1e-10 * (np.abs(w[t] * f).sum() + want), (i, e, got)
+
+
+def test_weights3_derivative_of_phs_interpolant():
+    """w . f equals the derivative of the r^3 + monomial interpolant of f at
+    the centre (30-digit numerical differentiation): pins -3 r u_axis, its
+    sign and its component, which polynomial reproduction cannot see."""
+    import mpmath
+    m, n = 2, 20
+    x, y, z = jittered_cube(7, seed=19)
+    nb = oracle.knn3(x, y, z, n)
+    rng = np.random.default_rng(18)
+    ex = monos3(m)
+    for i in [57, 200]:
+        idx = nb[i]
+        px, py, pz = x[idx], y[idx], z[idx]
+        cx, cy, cz = x[i], y[i], z[i]
+        f = rng.standard_normal(n)
+        A = np.sqrt((px[:, None] - px[None]) ** 2 + (py[:, None] - py[None]) ** 2 +
+                    (pz[:, None] - pz[None]) ** 2) ** 3
+        P = np.array([[(a_ - cx) ** e[0] * (b_ - cy) ** e[1] * (c_ - cz) ** e[2] for e in ex]
+                      for a_, b_, c_ in zip(px, py, pz)])
+        M = np.block([[A, P], [P.T, np.zeros((len(ex), len(ex)))]])
+        coef = np.linalg.solve(M, np.concatenate([f, np.zeros(len(ex))]))
+        with mpmath.workdps(30):
+            def s_f(X, Y, Z):
+                acc = mpmath.mpf(0)
+                for k in range(n):
+                    acc += coef[k] * mpmath.sqrt((X - px[k]) ** 2 + (Y - py[k]) ** 2 +
+                                                 (Z - pz[k]) ** 2) ** 3
+                for j, e in enumerate(ex):
+                    acc += coef[n + j] * (X - cx) ** e[0] * (Y - cy) ** e[1] * (Z - cz) ** e[2]
+                return acc
+            X0, Y0, Z0 = mpmath.mpf(cx), mpmath.mpf(cy), mpmath.mpf(cz)
+            want = {oracle.D3_DX: float(mpmath.diff(lambda t: s_f(t, Y0, Z0), X0, 1)),
+                    oracle.D3_DY: float(mpmath.diff(lambda t: s_f(X0, t, Z0), Y0, 1)),
+                    oracle.D3_DZ: float(mpmath.diff(lambda t: s_f(X0, Y0, t), Z0, 1))}
+        for op, _ in D3:
+            w, st = oracle.weights3_op(x, y, z, nb, m, n, op, rows=[i])
+            assert st[0] == 0
+            got = float(np.dot(w[0, :n], f))
+            assert abs(got - want[op]) <= 1e-8 * np.abs(w[0, :n] * f).sum(), (op, got, want[op])
+
+
+def test_weights3_derivative_scale_and_laplacian_op():
+    x, y, z = jittered_cube(6, seed=13)
+    nb = oracle.knn3(x, y, z, 20)
+    w, _ = oracle.weights3_op(x, y, z, nb, 2, 20, oracle.D3_DZ)
+    a = 2.5
+    w2, _ = oracle.weights3_op(a * x, a * y, a * z, nb, 2, 20, oracle.D3_DZ)
+    assert np.allclose(w2 * a, w, rtol=1e-9, atol=1e-9 * np.abs(w).max())
+    w0, st0 = oracle.weights3_op(x, y, z, nb, 2, 20, 0)
+    wl, stl = oracle.weights3(x, y, z, nb, 2, 20)
+    assert np.array_equal(w0, wl, equal_nan=True) and np.array_equal(st0, stl)
