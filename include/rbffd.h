@@ -186,13 +186,23 @@ int rbffd_weights_op(const double *x, const double *y, int64_t n_nodes, const in
  * status: [n_nodes] int32 out or NULL.  m must be 2 and 10 <= n <= k_stride
  * (RBFFD_ERR_ARG otherwise); n > 54 (K = n + 10 > 64) returns
  * RBFFD_ERR_UNSUPPORTED.  No workspace.
+ *
+ * rbffd_weights3_op: the same for the operator op: RBFFD_OP_LAPLACIAN (as
+ * rbffd_weights3), RBFFD_OP_DX, RBFFD_OP_DY, RBFFD_OP3_DZ: rhs_k =
+ * -3 * sqrt(fl(fl(u^2 + v^2) + t^2)) * (u_k, v_k or t_k) (the derivative of
+ * r^3 of node k at the centre), rhs_{n+j} = 1 for the monomial x, y or z,
+ * else 0; w_ik = z_k / s.  An op outside the list is RBFFD_ERR_ARG.
  * ======================================================================== */
+#define RBFFD_OP3_DZ 3
 int rbffd_knn3_workspace_size(int64_t n_nodes, int32_t k, size_t *bytes /* host */);
 int rbffd_knn3(const double *x, const double *y, const double *z, int64_t n_nodes, int32_t k,
                int32_t *nbr, void *workspace, size_t workspace_bytes, void *stream);
 int rbffd_weights3(const double *x, const double *y, const double *z, int64_t n_nodes,
                    const int32_t *nbr, int32_t k_stride, int32_t m, int32_t n, double *w,
                    int32_t *status, void *stream);
+int rbffd_weights3_op(const double *x, const double *y, const double *z, int64_t n_nodes,
+                      const int32_t *nbr, int32_t k_stride, int32_t m, int32_t n, int32_t op,
+                      double *w, int32_t *status, void *stream);
 
 /* ==========================================================================
  * Tuning of the mixed-order batch (rbffd_weights with a per-node order and

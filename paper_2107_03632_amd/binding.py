@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "librbffd.so")
 FP64, MIXED = 0, 1
 OK, SINGULAR, FELL_BACK_FP64, NONFINITE, BAD_INDEX, DUPLICATE, BAD_ORDER = range(7)
 SOLVE_CONVERGED, SOLVE_MAX_ITER, SOLVE_BREAKDOWN, SOLVE_NONFINITE = range(4)
-OP_LAPLACIAN, OP_DX, OP_DY = range(3)
+OP_LAPLACIAN, OP_DX, OP_DY, OP3_DZ = range(4)
 DEFAULT_N_FOR_ORDER = (12, 30, 56)
 
 _lock = threading.Lock()
@@ -64,6 +64,7 @@ def _load():
             "rbffd_knn3_workspace_size": ([I64, I32, PSZ], ctypes.c_int),
             "rbffd_knn3": ([P, P, P, I64, I32, P, P, ctypes.c_size_t, P], ctypes.c_int),
             "rbffd_weights3": ([P, P, P, I64, P, I32, I32, I32, P, P, P], ctypes.c_int),
+            "rbffd_weights3_op": ([P, P, P, I64, P, I32, I32, I32, I32, P, P, P], ctypes.c_int),
             "rbffd_solve_workspace_size": ([I64, PSZ], ctypes.c_int),
             "rbffd_solve": ([I64, P, P, P, P, P, ctypes.c_double, I32,
                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
@@ -246,9 +247,10 @@ def rbffd_knn3(x, y, z, k: int, out=None):
     return nbr
 
 
-def rbffd_weights3(x, y, z, nbr, m: int = 2, n: int = 20, out=None, status=None):
-    """Laplacian weights of eq. (1) for nodes in R^3 (r^3 + monomials of
-    degree <= 2), FP64.  Returns (w [N, k_stride], status [N])."""
+def rbffd_weights3(x, y, z, nbr, m: int = 2, n: int = 20, out=None, status=None, op=None):
+    """Weights of eq. (1) for nodes in R^3 (r^3 + monomials of degree <= 2),
+    FP64: the Laplacian, or with op one of OP_DX, OP_DY, OP3_DZ a first
+    derivative.  Returns (w [N, k_stride], status [N])."""
     lib = _load()
     x = _dev(x, torch.float64, "x")
     y = _dev(y, torch.float64, "y")
@@ -259,8 +261,13 @@ def rbffd_weights3(x, y, z, nbr, m: int = 2, n: int = 20, out=None, status=None)
         raise RbffdError("x, y, z must be [N] and nbr [N, k_stride]")
     w = out if out is not None else torch.empty((N, ks), dtype=torch.float64, device=x.device)
     st = status if status is not None else torch.empty(N, dtype=torch.int32, device=x.device)
-    _check(lib.rbffd_weights3(_p(x), _p(y), _p(z), N, _p(nbr), ks, int(m), int(n), _p(w),
-                              _p(st), _stream(x.device)), "rbffd_weights3")
+    if op is None:
+        _check(lib.rbffd_weights3(_p(x), _p(y), _p(z), N, _p(nbr), ks, int(m), int(n), _p(w),
+                                  _p(st), _stream(x.device)), "rbffd_weights3")
+    else:
+        _check(lib.rbffd_weights3_op(_p(x), _p(y), _p(z), N, _p(nbr), ks, int(m), int(n),
+                                     int(op), _p(w), _p(st), _stream(x.device)),
+               "rbffd_weights3_op")
     return w, st
 
 

@@ -62,7 +62,9 @@ __device__ __forceinline__ double mono3(int j, double u, double v, double t) {
 
 // occupancy target: 5 wavefronts per SIMD (at most 96 VGPRs) with 32 rows,
 // 3 with 64
-template <int KP>
+// OP: 0 the Laplacian, 1 d/dx, 2 d/dy, 3 d/dz (right-hand side and the
+// power of the scale).
+template <int KP, int OP>
 __global__ __launch_bounds__(kWave * kWaves3)
 __attribute__((amdgpu_waves_per_eu(KP == 32 ? 5 : 3))) void weights3_kernel(
     const double *__restrict__ x, const double *__restrict__ y, const double *__restrict__ z,
@@ -150,9 +152,12 @@ __attribute__((amdgpu_waves_per_eu(KP == 32 ? 5 : 3))) void weights3_kernel(
     }
     if (prow) {
         const double r0 = (ux * ux + uy * uy) + uz * uz;
-        b = 12.0 * sqrt(r0);
+        // lap r^3 = 12 r; d/dx r^3 of node k at the centre = -3 r u_kx
+        b = OP == 0 ? 12.0 * sqrt(r0)
+                    : -3.0 * sqrt(r0) * (OP == 1 ? ux : (OP == 2 ? uy : uz));
     } else if (qrow) {
-        b = (jr == 4 || jr == 7 || jr == 9) ? 2.0 : 0.0;  // lap of x^2, y^2, z^2
+        // lap of x^2, y^2, z^2 (j = 4, 7, 9); d/dx x, d/dy y, d/dz z (j = OP)
+        b = OP == 0 ? ((jr == 4 || jr == 7 || jr == 9) ? 2.0 : 0.0) : (jr == OP ? 1.0 : 0.0);
     }
 
     // ---- LU with partial pivoting, right-hand side carried along ----------
@@ -240,10 +245,24 @@ __attribute__((amdgpu_waves_per_eu(KP == 32 ? 5 : 3))) void weights3_kernel(
     else if (fl & G_ZBAD) st = RBFFD_NONFINITE;
     const bool good = st == RBFFD_OK;
     double *wi = w + i * (int64_t)k_stride;
-    const double s2 = sc * sc;
+    const double s2 = OP == 0 ? sc * sc : sc;  // the operator's power of the scale
     if (pos < n) wi[pos] = good ? zf / s2 : __builtin_nan("");
     for (int q = n + lane; q < k_stride; q += kWave) wi[q] = 0.0;
     if (lane == 0 && status) status[i] = st;
+}
+
+template <int OP>
+int launch3(const double *x, const double *y, const double *z, int64_t n_nodes,
+            const int32_t *nbr, int32_t k_stride, int32_t n, double *w, int32_t *status,
+            hipStream_t s) {
+    const unsigned nb = (unsigned)ceil_div(n_nodes, kWaves3);
+    if (n + kMono3 <= 32)
+        hipLaunchKernelGGL((weights3_kernel<32, OP>), dim3(nb), dim3(kWave * kWaves3), 0, s, x,
+                           y, z, n_nodes, nbr, k_stride, (int)n, n_nodes, w, status);
+    else
+        hipLaunchKernelGGL((weights3_kernel<64, OP>), dim3(nb), dim3(kWave * kWaves3), 0, s, x,
+                           y, z, n_nodes, nbr, k_stride, (int)n, n_nodes, w, status);
+    return last_launch_rc();
 }
 
 }  // namespace
@@ -251,20 +270,25 @@ __attribute__((amdgpu_waves_per_eu(KP == 32 ? 5 : 3))) void weights3_kernel(
 
 using namespace rbffd;
 
-extern "C" int rbffd_weights3(const double *x, const double *y, const double *z,
-                              int64_t n_nodes, const int32_t *nbr, int32_t k_stride, int32_t m,
-                              int32_t n, double *w, int32_t *status, void *stream) {
+extern "C" int rbffd_weights3_op(const double *x, const double *y, const double *z,
+                                 int64_t n_nodes, const int32_t *nbr, int32_t k_stride,
+                                 int32_t m, int32_t n, int32_t op, double *w, int32_t *status,
+                                 void *stream) {
     if (!x || !y || !z || !nbr || !w || n_nodes < 1 || n_nodes >= INT32_MAX || k_stride < 1 ||
-        n > k_stride || m != 2 || n < kMono3)
+        n > k_stride || m != 2 || n < kMono3 || op < 0 || op > 3)
         return RBFFD_ERR_ARG;
     if (n + kMono3 > 64) return RBFFD_ERR_UNSUPPORTED;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const unsigned nb = (unsigned)ceil_div(n_nodes, kWaves3);
-    if (n + kMono3 <= 32)
-        hipLaunchKernelGGL(weights3_kernel<32>, dim3(nb), dim3(kWave * kWaves3), 0, s, x, y, z,
-                           n_nodes, nbr, k_stride, (int)n, n_nodes, w, status);
-    else
-        hipLaunchKernelGGL(weights3_kernel<64>, dim3(nb), dim3(kWave * kWaves3), 0, s, x, y, z,
-                           n_nodes, nbr, k_stride, (int)n, n_nodes, w, status);
-    return last_launch_rc();
+    switch (op) {
+    case 0: return launch3<0>(x, y, z, n_nodes, nbr, k_stride, n, w, status, s);
+    case 1: return launch3<1>(x, y, z, n_nodes, nbr, k_stride, n, w, status, s);
+    case 2: return launch3<2>(x, y, z, n_nodes, nbr, k_stride, n, w, status, s);
+    default: return launch3<3>(x, y, z, n_nodes, nbr, k_stride, n, w, status, s);
+    }
+}
+
+extern "C" int rbffd_weights3(const double *x, const double *y, const double *z,
+                              int64_t n_nodes, const int32_t *nbr, int32_t k_stride, int32_t m,
+                              int32_t n, double *w, int32_t *status, void *stream) {
+    return rbffd_weights3_op(x, y, z, n_nodes, nbr, k_stride, m, n, 0, w, status, stream);
 }

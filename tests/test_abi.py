@@ -30,7 +30,7 @@ def test_header_declares_the_boundary():
     names = declared()
     for fn in ["rbffd_knn", "rbffd_weights", "rbffd_weights_backward", "rbffd_assemble_csr",
                "rbffd_spmv", "rbffd_time_steps", "rbffd_solve", "rbffd_weights_op",
-               "rbffd_knn3_workspace_size", "rbffd_knn3", "rbffd_weights3"]:
+               "rbffd_knn3_workspace_size", "rbffd_knn3", "rbffd_weights3", "rbffd_weights3_op"]:
         assert fn in names
 
 
@@ -83,6 +83,10 @@ def test_argument_errors_before_any_launch(lib):
     lib.rbffd_weights3.argtypes = [P, P, P, ctypes.c_int64, P, ctypes.c_int32, ctypes.c_int32,
                                    ctypes.c_int32, P, P, P]
     assert lib.rbffd_weights3(None, None, None, 10, None, 20, 2, 20, None, None, None) == -1
+    lib.rbffd_weights3_op.argtypes = [P, P, P, ctypes.c_int64, P, ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.c_int32, ctypes.c_int32, P, P, P]
+    assert lib.rbffd_weights3_op(None, None, None, 10, None, 20, 2, 20, 1, None, None,
+                                 None) == -1
     lib.rbffd_knn3.argtypes = [P, P, P, ctypes.c_int64, ctypes.c_int32, P, P, ctypes.c_size_t, P]
     assert lib.rbffd_knn3(None, None, None, 10, 5, None, None, 0, None) == -1
     lib.rbffd_knn3_workspace_size.argtypes = [ctypes.c_int64, ctypes.c_int32,

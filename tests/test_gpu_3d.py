@@ -1,5 +1,6 @@
-"""Three-dimensional supports (rbffd_knn3) and Laplacian weights
-(rbffd_weights3) against the oracle's knn3 / weights3.
+"""Three-dimensional supports (rbffd_knn3), Laplacian weights
+(rbffd_weights3) and first-derivative weights (rbffd_weights3_op) against the
+oracle's knn3 / weights3 / weights3_op.
 
 kNN is compared index for index.  The weights take the same operations in
 the same order as the oracle's LU and solves, so they are compared double
@@ -175,3 +176,53 @@ def test_3d_full_size_sampled():
         got = (w * f).sum(1)
         rel = np.abs(got - want) / ((np.abs(w * f)).sum(1) + want)
         assert rel.max() < 1e-9, ((a, b, c), rel.max())
+
+
+D3 = [(rb.OP_DX, oracle.D3_DX, (1, 0, 0)), (rb.OP_DY, oracle.D3_DY, (0, 1, 0)),
+      (rb.OP3_DZ, oracle.D3_DZ, (0, 0, 1))]
+
+
+@pytest.mark.parametrize("op,oop,axis", D3)
+@pytest.mark.parametrize("n", [20, 40])
+def test_weights3_derivatives_bit_exact(op, oop, axis, n):
+    x, y, z = nodes.jittered_cube(11, seed=26)
+    nbr = oracle.knn3(x, y, z, 64)
+    for nb, label in ((np.ascontiguousarray(nbr[:, :n]), "k_stride n"), (nbr, "k_stride 64")):
+        w_ref, st_ref = oracle.weights3_op(x, y, z, nb, 2, n, oop)
+        say("3-D derivative", axis, "n", n, label)
+        w, st = rb.rbffd_weights3(dev(x), dev(y), dev(z), dev(nb), 2, n, op=op)
+        w, st = host(w), host(st)
+        assert np.array_equal(st, st_ref)
+        assert np.array_equal(w, w_ref, equal_nan=True)
+
+
+def test_weights3_derivatives_full_size_sampled():
+    x, y, z = nodes.jittered_cube(100, seed=6)
+    N = x.shape[0]
+    X, Y, Z = dev(x), dev(y), dev(z)
+    nb_t = rb.rbffd_knn3(X, Y, Z, 20)
+    nbr = host(nb_t)
+    rows = np.sort(np.random.default_rng(27).choice(N, 150, replace=False))
+    dx = x[nbr] - x[:, None]
+    dy = y[nbr] - y[:, None]
+    dz = z[nbr] - z[:, None]
+    for op, oop, axis in D3:
+        say("3-D derivative full size", axis)
+        w_t, st_t = rb.rbffd_weights3(X, Y, Z, nb_t, 2, 20, op=op)
+        w, st = host(w_t), host(st_t)
+        assert np.all(st == 0)
+        w_ref, _ = oracle.weights3_op(x, y, z, nbr, 2, 20, oop, rows=rows)
+        assert np.array_equal(w[rows], w_ref)
+        for e in [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1), (2, 0, 0), (1, 1, 0), (1, 0, 1),
+                  (0, 2, 0), (0, 1, 1), (0, 0, 2)]:
+            f = dx ** e[0] * dy ** e[1] * dz ** e[2]
+            want = 1.0 if e == axis else 0.0
+            rel = np.abs((w * f).sum(1) - want) / (np.abs(w * f).sum(1) + want)
+            assert rel.max() < 1e-9, (axis, e, rel.max())
+
+
+def test_weights3_op_argument_errors():
+    x, y, z = nodes.jittered_cube(5, seed=24)
+    nbr = np.ascontiguousarray(oracle.knn3(x, y, z, 20))
+    with pytest.raises(rb.RbffdError, match=r"-1"):
+        rb.rbffd_weights3(dev(x), dev(y), dev(z), dev(nbr), 2, 20, op=4)
