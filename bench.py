@@ -404,7 +404,7 @@ def extras_3d(torch, rb, nodes, dev, stream, n=20):
     n = 20 (K = 30).  kNN and weights per launch, the weights' fraction of
     the FP64 peak, and the largest error of the weights applied to
     u = sin(pi x) sin(pi y) sin(pi z) (lap u = -3 pi^2 u) over nodes at least
-    3 h inside the cube."""
+    3 h inside the cube; the same for the d/dz weights."""
     x, y, z = nodes.jittered_cube(100, seed=6)
     X, Y, Z = (torch.as_tensor(a, device=dev) for a in (x, y, z))
     N = x.shape[0]
@@ -417,10 +417,17 @@ def extras_3d(torch, rb, nodes, dev, stream, n=20):
     inner = ((X > 0.03) & (X < 0.97) & (Y > 0.03) & (Y < 0.97) & (Z > 0.03) & (Z < 0.97))
     err = (lap - (-3.0 * math.pi ** 2) * u)[inner].abs().max().item()
     fl = weights3_flops(n)
+    # d/dz: du/dz = pi sin(pi x) sin(pi y) cos(pi z)
+    ms_dz = timed(torch, stream, lambda: rb.rbffd_weights3(X, Y, Z, nbr, 2, n, op=rb.OP3_DZ))
+    wz, stz = rb.rbffd_weights3(X, Y, Z, nbr, 2, n, op=rb.OP3_DZ)
+    dz_exact = math.pi * torch.sin(math.pi * X) * torch.sin(math.pi * Y) * torch.cos(math.pi * Z)
+    err_dz = ((wz * u[nbr.long()]).sum(1) - dz_exact)[inner].abs().max().item()
     return {"n_nodes": N, "m": 2, "n": n, "knn_ms": knn_ms, "weights_ms": ms,
             "stencils_per_s": N / (ms * 1e-3), "flops_per_stencil": fl,
             "frac_fp64_peak": fl * N / 1e12 / (ms * 1e-3) / FP64_PEAK_TFLOPS,
-            "failed": int((st != 0).sum().item()), "max_abs_err_inner": err}
+            "failed": int((st != 0).sum().item()), "max_abs_err_inner": err,
+            "d_dz": {"ms": ms_dz, "failed": int((stz != 0).sum().item()),
+                     "max_abs_err_inner": err_dz}}
 
 
 def extras_adjoint(torch, rb, nodes, dev, stream):
