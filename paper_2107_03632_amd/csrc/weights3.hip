@@ -36,12 +36,24 @@ __device__ __forceinline__ double bcast_d(double v, int lane) {
     return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
-__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
-    return wk::seg_all<kWave, wk::OpMax>(v, 0);
+// reductions over one stencil's SEG lanes (each lane receives the result)
+template <int SEG>
+__device__ __forceinline__ uint32_t seg_max_u32(uint32_t v) {
+    return wk::seg_all<SEG, wk::OpMax>(v, 0);
 }
 
-__device__ __forceinline__ uint32_t wave_or_u32(uint32_t v) {
-    return wk::seg_all<kWave, wk::OpOr>(v, 0);
+template <int SEG>
+__device__ __forceinline__ uint32_t seg_or_u32(uint32_t v) {
+    return wk::seg_all<SEG, wk::OpOr>(v, 0);
+}
+
+// v of lane w0 to the lanes of stencil 0, of lane w1 to those of stencil 1
+template <int SEG>
+__device__ __forceinline__ double bcast_seg(double v, int w0, int w1, int h) {
+    const double v0 = bcast_d(v, w0);
+    if constexpr (SEG == kWave) return v0;
+    const double v1 = bcast_d(v, w1);
+    return h ? v1 : v0;
 }
 
 // the ten monomials at (u, v, t): 1, x, y, z, x^2, xy, xz, y^2, yz, z^2
@@ -60,33 +72,45 @@ __device__ __forceinline__ double mono3(int j, double u, double v, double t) {
     }
 }
 
-// occupancy target: 5 wavefronts per SIMD (at most 96 VGPRs) with 32 rows,
-// 3 with 64
+// SEG lanes per stencil: 64 (one stencil per wavefront, KP = 32 or 64) or
+// 32 (two stencils per wavefront, KP = 32: the pivot searches, reciprocals
+// and bookkeeping of one instruction then serve two stencils).
+// Occupancy target: 5 wavefronts per SIMD (at most 96 VGPRs) with 32 rows,
+// 3 with 64.
 // OP: 0 the Laplacian, 1 d/dx, 2 d/dy, 3 d/dz (right-hand side and the
 // power of the scale).
-template <int KP, int OP>
+template <int KP, int SEG, int OP>
 __global__ __launch_bounds__(kWave * kWaves3)
 __attribute__((amdgpu_waves_per_eu(KP == 32 ? 5 : 3))) void weights3_kernel(
     const double *__restrict__ x, const double *__restrict__ y, const double *__restrict__ z,
     int64_t n_nodes, const int32_t *__restrict__ nbr, int32_t k_stride, int n, int64_t n_rows,
     double *__restrict__ w, int32_t *__restrict__ status) {
-    static_assert(KP == 32 || KP == 64, "rows per wavefront");
-    // per wavefront: the scaled offsets and monomials of the assembly
+    static_assert((SEG == kWave && (KP == 32 || KP == 64)) || (SEG == 32 && KP == 32),
+                  "rows per stencil");
+    constexpr int SPW = kWave / SEG;                            // stencils per wavefront
+    constexpr uint64_t kLo = SEG == kWave ? ~0ull : 0xffffffffull;  // stencil 0's lanes
+    // per stencil: the scaled offsets and monomials of the assembly
     constexpr int kAsm = 3 * KP + KP * (kMono3 + 1);
-    __shared__ double s_buf[kWaves3][kAsm];
+    __shared__ double s_buf[kWaves3 * SPW][kAsm];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
-    double(*s_u)[KP] = reinterpret_cast<double(*)[KP]>(&s_buf[wv][0]);
-    double(*s_p)[kMono3 + 1] = reinterpret_cast<double(*)[kMono3 + 1]>(&s_buf[wv][3 * KP]);
-    const int64_t i = (int64_t)blockIdx.x * kWaves3 + wv;
-    if (i >= n_rows) return;  // whole wavefronts only; no block barrier below
+    const int h = SEG == kWave ? 0 : lane / SEG;  // this lane's stencil in the wavefront
+    const int r = lane & (SEG - 1);               // its row
+    double(*s_u)[KP] = reinterpret_cast<double(*)[KP]>(&s_buf[wv * SPW + h][0]);
+    double(*s_p)[kMono3 + 1] =
+        reinterpret_cast<double(*)[kMono3 + 1]>(&s_buf[wv * SPW + h][3 * KP]);
+    const int64_t i0 = ((int64_t)blockIdx.x * kWaves3 + wv) * SPW;
+    if (i0 >= n_rows) return;  // whole wavefronts only; no block barrier below
+    // a stencil past the end repeats the last one and writes nothing
+    const bool live = i0 + h < n_rows;
+    const int64_t i = live ? i0 + h : n_rows - 1;
     const int K = n + kMono3;
 
     // ---- shift and scale -------------------------------------------------
     uint32_t flags = 0;
     double dx = 0.0, dy = 0.0, dz = 0.0, d2 = 0.0;
     const double xi = x[i], yi = y[i], zi = z[i];
-    if (lane < n) {
-        const int32_t j = nbr[i * (int64_t)k_stride + lane];
+    if (r < n) {
+        const int32_t j = nbr[i * (int64_t)k_stride + r];
         if (j < 0 || (int64_t)j >= n_nodes) {
             flags |= G_BADIDX;
         } else {
@@ -103,27 +127,27 @@ __attribute__((amdgpu_waves_per_eu(KP == 32 ? 5 : 3))) void weights3_kernel(
     }
     // d2 >= 0 (or +inf), so its bit pattern orders like its value
     const uint64_t d2b = (uint64_t)__double_as_longlong(d2);
-    const uint32_t mh = wave_max_u32((uint32_t)(d2b >> 32));
-    const uint32_t ml = wave_max_u32((uint32_t)(d2b >> 32) == mh ? (uint32_t)d2b : 0u);
+    const uint32_t mh = seg_max_u32<SEG>((uint32_t)(d2b >> 32));
+    const uint32_t ml = seg_max_u32<SEG>((uint32_t)(d2b >> 32) == mh ? (uint32_t)d2b : 0u);
     const double sc = sqrt(__longlong_as_double((long long)(((uint64_t)mh << 32) | ml)));
     if (!isfinite(sc)) flags |= G_NONFIN;
     if (sc == 0.0) flags |= G_DUP;
     const double ux = dx / sc, uy = dy / sc, uz = dz / sc;
-    if (lane < KP) {
-        s_u[0][lane] = lane < n ? ux : 0.0;
-        s_u[1][lane] = lane < n ? uy : 0.0;
-        s_u[2][lane] = lane < n ? uz : 0.0;
+    if (r < KP) {
+        s_u[0][r] = r < n ? ux : 0.0;
+        s_u[1][r] = r < n ? uy : 0.0;
+        s_u[2][r] = r < n ? uz : 0.0;
 #pragma unroll
-        for (int j = 0; j < kMono3; ++j) s_p[lane][j] = lane < n ? mono3(j, ux, uy, uz) : 0.0;
+        for (int j = 0; j < kMono3; ++j) s_p[r][j] = r < n ? mono3(j, ux, uy, uz) : 0.0;
     }
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     __builtin_amdgcn_wave_barrier();  // one wavefront: its LDS accesses are in order
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
 
     // ---- this lane's row ---------------------------------------------------
-    const bool prow = lane < n;
-    const bool qrow = lane >= n && lane < K;
-    const int jr = qrow ? lane - n : 0;
+    const bool prow = r < n;
+    const bool qrow = r >= n && r < K;
+    const int jr = qrow ? r - n : 0;
     double a[KP];
     double b = 0.0;
 #pragma unroll
@@ -135,14 +159,14 @@ __attribute__((amdgpu_waves_per_eu(KP == 32 ? 5 : 3))) void weights3_kernel(
                 const double ey = uy - s_u[1][q];
                 const double ez = uz - s_u[2][q];
                 const double rr = (ex * ex + ey * ey) + ez * ez;
-                if (q != lane && rr == 0.0) flags |= G_DUP;
+                if (q != r && rr == 0.0) flags |= G_DUP;
                 v = rr * sqrt(rr);
             } else if (qrow) {
                 v = s_p[q][jr];
             }
         } else if (q < K) {
-            v = prow ? s_p[lane][q - n] : 0.0;
-        } else if (q == lane) {
+            v = prow ? s_p[r][q - n] : 0.0;
+        } else if (q == r) {
             v = 1.0;  // identity padding up to KP
         }
         a[q] = v;
@@ -165,28 +189,36 @@ __attribute__((amdgpu_waves_per_eu(KP == 32 ? 5 : 3))) void weights3_kernel(
     // first K columns (their entries there are 0, and a lower position wins
     // ties), and the real rows are all pivoted by then, so the padding
     // columns change nothing of the real solution.  Lanes past KP sit out.
-    int pos = lane;             // position of this lane's row
-    bool done = lane >= KP;     // pivoted already (or outside the system)
+    int pos = r;                // position of this lane's row
+    bool done = r >= KP;        // pivoted already (or outside the system)
     double my_inv = 0.0, my_piv = 1.0;
 #pragma unroll
     for (int c = 0; c < KP; ++c) {
         const uint64_t bits = (uint64_t)__double_as_longlong(a[c]) & 0x7fffffffffffffffull;
         const uint32_t kh = done ? 0u : (uint32_t)(bits >> 32) + 1u;
-        const uint32_t hmax = wave_max_u32(kh);
+        const uint32_t hmax = seg_max_u32<SEG>(kh);
         uint64_t cand = __ballot(!done && kh == hmax);
-        if ((cand & (cand - 1ull)) != 0ull) {
+        bool multi = ((cand & kLo) & ((cand & kLo) - 1ull)) != 0ull;
+        if constexpr (SEG != kWave) multi = multi || ((cand >> 32) & ((cand >> 32) - 1ull)) != 0ull;
+        if (multi) {
             // equal high words: the low words, then the lowest position
             const bool in = (cand >> lane) & 1ull;
             const uint32_t kl = in ? (uint32_t)bits : 0u;
-            const uint32_t lmax = wave_max_u32(kl);
+            const uint32_t lmax = seg_max_u32<SEG>(kl);
             const bool in2 = in && kl == lmax;
             const uint32_t pk = in2 ? (uint32_t)(KP - pos) : 0u;
-            const uint32_t pmax = wave_max_u32(pk);
+            const uint32_t pmax = seg_max_u32<SEG>(pk);
             cand = __ballot(in2 && pk == pmax);
         }
-        const int win = __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)cand) - 1);
-        const int kp = __builtin_amdgcn_readlane(pos, win);
-        const double piv = bcast_d(a[c], win);
+        // the pivot lane of each stencil
+        const int win0 = __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)(cand & kLo)) - 1);
+        const int win1 = SEG == kWave ? win0
+                                      : __builtin_amdgcn_readfirstlane(
+                                            32 + __ffsll((unsigned long long)(cand >> 32)) - 1);
+        const int win = h ? win1 : win0;
+        const int kp0 = __builtin_amdgcn_readlane(pos, win0);
+        const int kp = SEG == kWave ? kp0 : (h ? __builtin_amdgcn_readlane(pos, win1) : kp0);
+        const double piv = bcast_seg<SEG>(a[c], win0, win1, h);
         const double inv = 1.0 / piv;
         const bool isp = lane == win;
         my_inv = isp ? inv : my_inv;
@@ -203,14 +235,14 @@ __attribute__((amdgpu_waves_per_eu(KP == 32 ? 5 : 3))) void weights3_kernel(
         asm volatile("" : "+v"(a[c]));
 #pragma unroll
         for (int q = c + 1; q < KP; ++q) {
-            const double u = bcast_d(a[q], win);
+            const double u = bcast_seg<SEG>(a[q], win0, win1, h);
             const double nv = fma(-l, u, a[q]);
             a[q] = done ? a[q] : nv;
             // the select happens here: deferred to the entry's next use, it
             // would keep both values and every column's mask alive
             asm volatile("" : "+v"(a[q]));
         }
-        const double ub = bcast_d(b, win);
+        const double ub = bcast_seg<SEG>(b, win0, win1, h);
         const double nb = fma(-l, ub, b);
         b = done ? b : nb;
         asm volatile("" : "+v"(b));
@@ -221,9 +253,12 @@ __attribute__((amdgpu_waves_per_eu(KP == 32 ? 5 : 3))) void weights3_kernel(
 #pragma unroll
     for (int c = KP - 1; c >= 0; --c) {
         const uint64_t at = __ballot(pos == c);
-        const int wl = __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)at) - 1);
-        const double zc = bcast_d(b * my_inv, wl);
-        if (lane == wl) zf = zc;
+        const int wl0 = __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)(at & kLo)) - 1);
+        const int wl1 = SEG == kWave ? wl0
+                                     : __builtin_amdgcn_readfirstlane(
+                                           32 + __ffsll((unsigned long long)(at >> 32)) - 1);
+        const double zc = bcast_seg<SEG>(b * my_inv, wl0, wl1, h);
+        if (lane == (h ? wl1 : wl0)) zf = zc;
         if (pos < c) b = fma(-a[c], zc, b);
     }
 
@@ -234,8 +269,8 @@ __attribute__((amdgpu_waves_per_eu(KP == 32 ? 5 : 3))) void weights3_kernel(
         if (f) lukey = ((uint32_t)(KP - pos) << 2) | f;
         if (!isfinite(zf)) flags |= G_ZBAD;
     }
-    const uint32_t luflag = wave_max_u32(lukey) & 3u;
-    const uint32_t fl = wave_or_u32(flags);
+    const uint32_t luflag = seg_max_u32<SEG>(lukey) & 3u;
+    const uint32_t fl = seg_or_u32<SEG>(flags);
     int st = RBFFD_OK;
     if (fl & G_BADIDX) st = RBFFD_BAD_INDEX;
     else if (fl & G_NONFIN) st = RBFFD_NONFINITE;
@@ -243,25 +278,27 @@ __attribute__((amdgpu_waves_per_eu(KP == 32 ? 5 : 3))) void weights3_kernel(
     else if (luflag == G_LU_NONFIN) st = RBFFD_NONFINITE;
     else if (luflag == G_LU_SING) st = RBFFD_SINGULAR;
     else if (fl & G_ZBAD) st = RBFFD_NONFINITE;
+    if (!live) return;
     const bool good = st == RBFFD_OK;
     double *wi = w + i * (int64_t)k_stride;
     const double s2 = OP == 0 ? sc * sc : sc;  // the operator's power of the scale
     if (pos < n) wi[pos] = good ? zf / s2 : __builtin_nan("");
-    for (int q = n + lane; q < k_stride; q += kWave) wi[q] = 0.0;
-    if (lane == 0 && status) status[i] = st;
+    for (int q = n + r; q < k_stride; q += SEG) wi[q] = 0.0;
+    if (r == 0 && status) status[i] = st;
 }
 
 template <int OP>
 int launch3(const double *x, const double *y, const double *z, int64_t n_nodes,
             const int32_t *nbr, int32_t k_stride, int32_t n, double *w, int32_t *status,
             hipStream_t s) {
-    const unsigned nb = (unsigned)ceil_div(n_nodes, kWaves3);
-    if (n + kMono3 <= 32)
-        hipLaunchKernelGGL((weights3_kernel<32, OP>), dim3(nb), dim3(kWave * kWaves3), 0, s, x,
-                           y, z, n_nodes, nbr, k_stride, (int)n, n_nodes, w, status);
+    if (n + kMono3 <= 32)  // two stencils per wavefront
+        hipLaunchKernelGGL((weights3_kernel<32, 32, OP>),
+                           dim3((unsigned)ceil_div(n_nodes, 2 * kWaves3)), dim3(kWave * kWaves3),
+                           0, s, x, y, z, n_nodes, nbr, k_stride, (int)n, n_nodes, w, status);
     else
-        hipLaunchKernelGGL((weights3_kernel<64, OP>), dim3(nb), dim3(kWave * kWaves3), 0, s, x,
-                           y, z, n_nodes, nbr, k_stride, (int)n, n_nodes, w, status);
+        hipLaunchKernelGGL((weights3_kernel<64, kWave, OP>),
+                           dim3((unsigned)ceil_div(n_nodes, kWaves3)), dim3(kWave * kWaves3), 0,
+                           s, x, y, z, n_nodes, nbr, k_stride, (int)n, n_nodes, w, status);
     return last_launch_rc();
 }
 
