@@ -154,8 +154,8 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, "
-              f"WORLD_SIZE={world}); stencils are independent, the multi-GPU "
-              f"sharding is described in DESIGN.md but not built", file=sys.stderr)
+              f"WORLD_SIZE={world}); stencils are independent and would shard by "
+              f"rows, but only the one-GPU path is built", file=sys.stderr)
         sys.exit(2)
 
     import torch
