@@ -66,24 +66,49 @@ __global__ __launch_bounds__(kThreads) void csr_fill(int64_t n_nodes, const int3
     val[at + rank] = w[i * (int64_t)k_stride + k];
 }
 
-__global__ __launch_bounds__(kThreads) void spmv_rows(int64_t n_rows,
-                                                      const int64_t *__restrict__ row_ptr,
-                                                      const int32_t *__restrict__ col,
-                                                      const double *__restrict__ val,
-                                                      const double *__restrict__ u,
-                                                      const double *__restrict__ f,
-                                                      double *__restrict__ y) {
-    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (i >= n_rows) return;
+// One thread per row, one wavefront per block of 64 rows.  The block's
+// nonzeros are a contiguous range of col / val: they are staged through LDS
+// in chunks, with consecutive lanes loading consecutive entries, and each
+// thread then sums its own row from LDS in CSR order (the rows' entries are
+// read in the same order as a plain sequential loop, so the sums are the
+// same doubles).
+constexpr int kSpRows = 64;
+constexpr int kSpChunk = 1024;  // entries per staging pass (12 KB of LDS)
+
+__global__ __launch_bounds__(kSpRows) void spmv_rows(int64_t n_rows,
+                                                     const int64_t *__restrict__ row_ptr,
+                                                     const int32_t *__restrict__ col,
+                                                     const double *__restrict__ val,
+                                                     const double *__restrict__ u,
+                                                     const double *__restrict__ f,
+                                                     double *__restrict__ y) {
+    __shared__ double s_val[kSpChunk];
+    __shared__ int32_t s_col[kSpChunk];
+    const int t = threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * kSpRows;
+    const int64_t i = r0 + t;
+    const int64_t rl = r0 + kSpRows < n_rows ? r0 + kSpRows : n_rows;  // past the last row
+    const int64_t b0 = row_ptr[r0], b1 = row_ptr[rl];
+    int64_t e = i < n_rows ? row_ptr[i] : b1;
+    const int64_t e1 = i < n_rows ? row_ptr[i + 1] : b1;
     double acc = 0.0;
-    const int64_t e1 = row_ptr[i + 1];
-    for (int64_t e = row_ptr[i]; e < e1; ++e) {
-        const int32_t c = col[e];
-        // the operator is square: a column outside [0, n_rows) poisons the row
-        acc = ((int64_t)c >= 0 && (int64_t)c < n_rows) ? fma(val[e], u[c], acc)
-                                                        : __builtin_nan("");
+    for (int64_t c0 = b0; c0 < b1; c0 += kSpChunk) {
+        const int64_t c1 = c0 + kSpChunk < b1 ? c0 + kSpChunk : b1;
+        for (int64_t q = c0 + t; q < c1; q += kSpRows) {
+            s_val[q - c0] = val[q];
+            s_col[q - c0] = col[q];
+        }
+        __syncthreads();
+        // this row's entries in the chunk (e >= c0 here: rows are ascending)
+        for (; e < e1 && e < c1; ++e) {
+            const int32_t c = s_col[e - c0];
+            // the operator is square: a column outside [0, n_rows) poisons the row
+            acc = ((int64_t)c >= 0 && (int64_t)c < n_rows) ? fma(s_val[e - c0], u[c], acc)
+                                                            : __builtin_nan("");
+        }
+        __syncthreads();
     }
-    y[i] = f ? acc - f[i] : acc;
+    if (i < n_rows) y[i] = f ? acc - f[i] : acc;
 }
 
 }  // namespace
@@ -139,7 +164,7 @@ extern "C" int rbffd_spmv(int64_t n_rows, const int64_t *row_ptr, const int32_t 
     if (n_rows < 0 || !row_ptr || !col || !val || !u || !y) return RBFFD_ERR_ARG;
     if (n_rows == 0) return RBFFD_SUCCESS;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipLaunchKernelGGL(spmv_rows, dim3((unsigned)ceil_div(n_rows, kThreads)), dim3(kThreads), 0,
+    hipLaunchKernelGGL(spmv_rows, dim3((unsigned)ceil_div(n_rows, kSpRows)), dim3(kSpRows), 0,
                        s, n_rows, row_ptr, col, val, u, f, y);
     return last_launch_rc();
 }
