@@ -66,6 +66,52 @@ __global__ __launch_bounds__(kThreads) void csr_fill(int64_t n_nodes, const int3
     val[at + rank] = w[i * (int64_t)k_stride + k];
 }
 
+// csr_fill with the block's rows (their first kmax support entries) staged
+// in LDS first: the rank loop then reads LDS, where the threads of one row
+// read one address at a time.  For kmax <= kFillMaxK.
+constexpr int kFillMaxK = 128;
+
+__global__ __launch_bounds__(kThreads) void csr_fill_staged(
+    int64_t n_nodes, const int32_t *nbr, int32_t k_stride, int32_t kmax, const int8_t *order,
+    int n_uniform, OrderTable tab, const double *w, const uint8_t *is_boundary,
+    const int64_t *row_ptr, int32_t *col, double *val) {
+    // rows overlapping one block: at most kThreads / kmax + 2
+    __shared__ int32_t s_nbr[kThreads + 2 * kFillMaxK];
+    const int64_t e0 = (int64_t)blockIdx.x * kThreads;
+    const int64_t i_first = e0 / kmax;
+    const int64_t i_end = (e0 + kThreads - 1) / kmax;
+    const int64_t i_last = i_end < n_nodes - 1 ? i_end : n_nodes - 1;
+    const int staged = (int)(i_last - i_first + 1) * kmax;
+    for (int q = threadIdx.x; q < staged; q += kThreads) {
+        const int rr = q / kmax;
+        s_nbr[q] = nbr[(i_first + rr) * (int64_t)k_stride + (q - rr * kmax)];
+    }
+    __syncthreads();
+    const int64_t e = e0 + threadIdx.x;
+    const int64_t i = e / kmax;
+    const int k = (int)(e - i * kmax);
+    if (i >= n_nodes) return;
+    const int64_t at = row_ptr[i];
+    if (is_boundary && is_boundary[i]) {
+        if (k == 0) {
+            col[at] = (int32_t)i;
+            val[at] = 1.0;
+        }
+        return;
+    }
+    const int n = row_support(order, n_uniform, tab, i);
+    if (k >= n) return;
+    const int32_t *c = s_nbr + (i - i_first) * kmax;
+    const int32_t ck = c[k];
+    int rank = 0;
+    for (int l = 0; l < n; ++l) {
+        const int32_t cl = c[l];
+        rank += (cl < ck || (cl == ck && l < k)) ? 1 : 0;
+    }
+    col[at + rank] = ck;
+    val[at + rank] = w[i * (int64_t)k_stride + k];
+}
+
 // One thread per row, one wavefront per block of 64 rows.  The block's
 // nonzeros are a contiguous range of col / val: they are staged through LDS
 // in chunks, with consecutive lanes loading consecutive entries, and each
@@ -152,9 +198,14 @@ extern "C" int rbffd_assemble_csr(int64_t n_nodes, const int32_t *nbr, int32_t k
     int rc = exclusive_scan_i64(row_ptr, row_ptr, n_nodes + 1, workspace, s);
     if (rc) return rc;
     const int64_t slots = n_nodes * (int64_t)kmax;
-    hipLaunchKernelGGL(csr_fill, dim3((unsigned)ceil_div(slots, kThreads)), dim3(kThreads), 0, s,
-                       n_nodes, nbr, k_stride, (int32_t)kmax, order, n, tab, w, is_boundary,
-                       (const int64_t *)row_ptr, col, val);
+    if (kmax <= kFillMaxK)
+        hipLaunchKernelGGL(csr_fill_staged, dim3((unsigned)ceil_div(slots, kThreads)),
+                           dim3(kThreads), 0, s, n_nodes, nbr, k_stride, (int32_t)kmax, order, n,
+                           tab, w, is_boundary, (const int64_t *)row_ptr, col, val);
+    else
+        hipLaunchKernelGGL(csr_fill, dim3((unsigned)ceil_div(slots, kThreads)), dim3(kThreads),
+                           0, s, n_nodes, nbr, k_stride, (int32_t)kmax, order, n, tab, w,
+                           is_boundary, (const int64_t *)row_ptr, col, val);
     return last_launch_rc();
 }
 
