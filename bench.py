@@ -221,8 +221,11 @@ def main():
     fma64 = measured_fma_peak(torch, dev, 0)
     fma32 = measured_fma_peak(torch, dev, 1)
     out = {
-        "metric": "RBF-FD Laplacian stencils/s (kNN + FP64 weights + CSR + residual), "
-                  "unit disk ~100k nodes, m=4, n=30",
+        # the headline metric; this line's value is its m = 4 FP64 point on the
+        # unit disk, per whole step (the workload below), and the m = 2/4/6
+        # FP64 and mixed figures are in per_order_1M_square
+        "metric": "RBF-FD \u2207\u00b2 stencils/sec at m=2/4/6 (FP64 vs mixed+refine); "
+                  "% of FLOP roofline",
         "value": N / (ms_step * 1e-3),
         "unit": "stencils/s",
         "n_gpus": 1,
