@@ -114,12 +114,14 @@ __global__ __launch_bounds__(kThreads) void csr_fill_staged(
 
 // One thread per row, one wavefront per block of 64 rows.  The block's
 // nonzeros are a contiguous range of col / val: they are staged through LDS
-// in chunks, with consecutive lanes loading consecutive entries, and each
-// thread then sums its own row from LDS in CSR order (the rows' entries are
-// read in the same order as a plain sequential loop, so the sums are the
-// same doubles).
+// in chunks, with consecutive lanes loading consecutive entries and the
+// gathered u of each entry (all lanes' gathers in flight at once), and each
+// thread then sums its own row from LDS in CSR order (the same operands in
+// the same order as a plain sequential loop, so the sums are the same
+// doubles; an entry whose column lies outside [0, n_rows) stages NaN, which
+// poisons its row as before).
 constexpr int kSpRows = 64;
-constexpr int kSpChunk = 1024;  // entries per staging pass (12 KB of LDS)
+constexpr int kSpChunk = 1024;  // entries per staging pass (16 KB of LDS)
 
 __global__ __launch_bounds__(kSpRows) void spmv_rows(int64_t n_rows,
                                                      const int64_t *__restrict__ row_ptr,
@@ -129,7 +131,7 @@ __global__ __launch_bounds__(kSpRows) void spmv_rows(int64_t n_rows,
                                                      const double *__restrict__ f,
                                                      double *__restrict__ y) {
     __shared__ double s_val[kSpChunk];
-    __shared__ int32_t s_col[kSpChunk];
+    __shared__ double s_u[kSpChunk];
     const int t = threadIdx.x;
     const int64_t r0 = (int64_t)blockIdx.x * kSpRows;
     const int64_t i = r0 + t;
@@ -141,17 +143,14 @@ __global__ __launch_bounds__(kSpRows) void spmv_rows(int64_t n_rows,
     for (int64_t c0 = b0; c0 < b1; c0 += kSpChunk) {
         const int64_t c1 = c0 + kSpChunk < b1 ? c0 + kSpChunk : b1;
         for (int64_t q = c0 + t; q < c1; q += kSpRows) {
+            const int32_t c = col[q];
             s_val[q - c0] = val[q];
-            s_col[q - c0] = col[q];
+            // the operator is square: a column outside [0, n_rows) poisons the row
+            s_u[q - c0] = ((int64_t)c >= 0 && (int64_t)c < n_rows) ? u[c] : __builtin_nan("");
         }
         __syncthreads();
         // this row's entries in the chunk (e >= c0 here: rows are ascending)
-        for (; e < e1 && e < c1; ++e) {
-            const int32_t c = s_col[e - c0];
-            // the operator is square: a column outside [0, n_rows) poisons the row
-            acc = ((int64_t)c >= 0 && (int64_t)c < n_rows) ? fma(s_val[e - c0], u[c], acc)
-                                                            : __builtin_nan("");
-        }
+        for (; e < e1 && e < c1; ++e) acc = fma(s_val[e - c0], s_u[e - c0], acc);
         __syncthreads();
     }
     if (i < n_rows) y[i] = f ? acc - f[i] : acc;
