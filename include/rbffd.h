@@ -120,7 +120,8 @@ int rbffd_knn(const double *x, const double *y, int64_t n_nodes, int32_t k,
  *   then RBFFD_FELL_BACK_FP64 (weights valid).
  * w: [n_nodes][k_stride] FP64 out.  status: [n_nodes] int32 out (may be NULL).
  * refine_steps: [n_nodes] int32 out (may be NULL; mixed only): corrections
- * applied, 0 for stencils that fell back or failed.
+ * applied; for a stencil that fell back, the corrections tried before it
+ * did (0 when the FP32 factorisation or the assembly failed).
  * save (may be NULL): factors for rbffd_weights_backward; see
  * rbffd_weights_save_size.  Only with RBFFD_FP64.
  * ======================================================================== */

@@ -63,6 +63,7 @@ def _load():
             lib.oracle_assemble.argtypes = [I64, P, P, I64, P, ctypes.c_int,
                                             ctypes.c_int, P, P, P]
             lib.oracle_lu.argtypes = [ctypes.c_int, P, P, P]
+            lib.oracle_lu32.argtypes = [ctypes.c_int, P, P, P]
             lib.oracle_lu_solve.argtypes = [ctypes.c_int, P, P, P, P]
             lib.oracle_lu_solve.restype = None
             lib.oracle_weights.argtypes = [I64, P, P, P, I32, P, I32, I32, P,
@@ -73,6 +74,8 @@ def _load():
                                                  P, I64, P, P, P]
             lib.oracle_adjoint.argtypes = [I64, P, P, P, I32, P, I32, I32, P,
                                            P, P, P]
+            lib.oracle_adjoint_rows.argtypes = [I64, P, P, P, I32, P, I32, I32, P,
+                                                P, P, I64, P, P]
             lib.oracle_csr.argtypes = [I64, P, I32, P, I32, P, P, P, P, P, P]
             lib.oracle_spmv.argtypes = [I64, P, P, P, P, P, P]
             lib.oracle_knn3.argtypes = [I64, P, P, P, I32, P, I64, P]
@@ -225,6 +228,18 @@ def lu(M):
     return st, A, perm, dinv
 
 
+def lu32(M):
+    """The FP32 factorisation of the mixed form (in a float32 copy of M).
+    Returns (status, LU, perm, dinv) as ``lu``, in float32."""
+    lib = _load()
+    A = np.ascontiguousarray(M, dtype=np.float32).copy()
+    K = A.shape[0]
+    perm = np.zeros(K, dtype=np.int32)
+    dinv = np.zeros(K, dtype=np.float32)
+    st = lib.oracle_lu32(K, _p(A), _p(perm), _p(dinv))
+    return st, A, perm, dinv
+
+
 def lu_solve(LU, perm, dinv, b):
     lib = _load()
     LU = _f64(LU)
@@ -281,7 +296,8 @@ def weights_op(x, y, nbr, m: int, n: int, op: int, rows=None):
 def weights_mixed(x, y, nbr, m: int | None = None, n: int | None = None, order=None,
                   n_for_m=(12, 30, 56), rows=None, k_stride: int | None = None):
     """Mixed-precision weights: FP32 LU of the FP64-assembled system + FP64
-    refinement, FP64 fallback.  Returns (w, status, corrections)."""
+    refinement, FP64 fallback.  Returns (w, status, corrections); for a
+    stencil that fell back, the corrections tried before it did."""
     lib = _load()
     x, y, nbr = _f64(x), _f64(y), _i32(nbr)
     _check_supports(x, y, nbr, k_stride)
@@ -302,8 +318,9 @@ def weights_mixed(x, y, nbr, m: int | None = None, n: int | None = None, order=N
 
 
 def adjoint(x, y, nbr, G, m: int | None = None, n: int | None = None, order=None,
-            n_for_m=(12, 30, 56)):
-    """dL/dx, dL/dy of all nodes given G = dL/dw (reverse mode of weights)."""
+            n_for_m=(12, 30, 56), rows=None):
+    """dL/dx, dL/dy of all nodes given G = dL/dw (reverse mode of weights).
+    With rows, only the listed nodes' stencils contribute (in list order)."""
     lib = _load()
     x, y, nbr, G = _f64(x), _f64(y), _i32(nbr), _f64(G)
     _check_supports(x, y, nbr)
@@ -313,9 +330,11 @@ def adjoint(x, y, nbr, G, m: int | None = None, n: int | None = None, order=None
     gx = np.empty(N)
     gy = np.empty(N)
     o = None if order is None else np.ascontiguousarray(order, dtype=np.int8)
-    rc = lib.oracle_adjoint(N, _p(x), _p(y), _p(nbr), nbr.shape[1], _p(o),
-                            -1 if m is None else m, -1 if n is None else n,
-                            _p(_i32(n_for_m)), _p(G), _p(gx), _p(gy))
+    r = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    rc = lib.oracle_adjoint_rows(N, _p(x), _p(y), _p(nbr), nbr.shape[1], _p(o),
+                                 -1 if m is None else m, -1 if n is None else n,
+                                 _p(_i32(n_for_m)), _p(G), _p(r), N if r is None else r.shape[0],
+                                 _p(gx), _p(gy))
     if rc < 0:
         raise ValueError(f"oracle_adjoint: error {rc}")
     return gx, gy, rc

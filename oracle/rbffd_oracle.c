@@ -28,6 +28,7 @@
  *   oracle_weights    w of eq. (1): w_k = z_k / s^2 for the n support nodes.
  *   oracle_adjoint    dL/dx, dL/dy for all nodes from dL/dw (reverse mode of the
  *                     map above, with the scale s held fixed).
+ *   oracle_lu32       oracle_lu in FP32 (fabsf, 1.0f / pivot, fmaf updates).
  *   oracle_weights_mixed  the same weights from an FP32 factorisation of the
  *                     FP64-assembled system, refined in FP64: residual
  *                     rhs - M z in FP64 (fused, columns ascending), FP32
@@ -36,7 +37,9 @@
  *                     pivot, a correction above half the previous one (the
  *                     first is compared with the initial solve), a non-finite
  *                     value or 10 corrections without convergence send the
- *                     stencil to the FP64 path (status OR_FELL_BACK).
+ *                     stencil to the FP64 path (status OR_FELL_BACK).  The
+ *                     corrections applied, or tried before a fallback, are
+ *                     reported per stencil.
  *   oracle_csr        the discrete operator of eq. (1) as a CSR matrix, with the
  *                     Dirichlet rows of section IV replaced by identity rows.
  *   oracle_spmv       y = W u - f, a sequential row sum in CSR order.
@@ -491,7 +494,7 @@ static int weights_any(int64_t n_nodes, const double *x, const double *y,
 /* ---------------------------------------------------------------------- */
 
 /* oracle_lu in single precision (fabsf, 1.0f / pivot, fmaf updates). */
-static int lu32(int K, float *M, int32_t *perm, float *dinv)
+int oracle_lu32(int K, float *M, int32_t *perm, float *dinv)
 {
     for (int c = 0; c < K; ++c) {
         int p = c;
@@ -549,7 +552,8 @@ static void lu32_solve(int K, const float *LU, const int32_t *perm, const float 
 #define MIXED_TOL 1e-12
 
 /* One stencil, mixed precision.  Returns the status; *iters = number of
- * corrections applied (0 when the stencil fell back or failed early). */
+ * corrections applied, or tried before the stencil fell back (0 when the
+ * assembly or the FP32 factorisation failed). */
 static int stencil_solve_mixed(int64_t n_nodes, const double *x, const double *y,
                                int64_t i, const int32_t *idx, int n, int m,
                                double *M, double *z, float *M32, float *d32,
@@ -563,7 +567,7 @@ static int stencil_solve_mixed(int64_t n_nodes, const double *x, const double *y
         return st;
     for (int e = 0; e < K * K; ++e)
         M32[e] = (float)M[e];
-    int ok = lu32(K, M32, perm, dinv32) == OR_OK;
+    int ok = oracle_lu32(K, M32, perm, dinv32) == OR_OK;
     if (ok) {
         for (int q = 0; q < K; ++q)
             d32[q] = (float)rhs[q];
@@ -611,8 +615,7 @@ static int stencil_solve_mixed(int64_t n_nodes, const double *x, const double *y
     }
     if (ok)
         return OR_OK;
-    *iters = 0;
-    /* FP64 path from scratch */
+    /* FP64 path from scratch; *iters keeps the corrections tried */
     st = stencil_solve(n_nodes, x, y, i, idx, n, m, 0, M, z, perm, dinv, s);
     return st == OR_OK ? OR_FELL_BACK : st;
 }
@@ -704,11 +707,31 @@ int oracle_weights_mixed(int64_t n_nodes, const double *x, const double *y,
  * grad_x, grad_y are overwritten.  Returns the number of failed stencils
  * (their terms are skipped), or a negative argument error.
  */
+int oracle_adjoint_rows(int64_t n_nodes, const double *x, const double *y,
+                        const int32_t *nbr, int32_t k_stride,
+                        const int8_t *order, int32_t m_uniform, int32_t n_uniform,
+                        const int32_t *n_for_m, const double *G,
+                        const int64_t *rows, int64_t n_rows,
+                        double *grad_x, double *grad_y);
+
 int oracle_adjoint(int64_t n_nodes, const double *x, const double *y,
                    const int32_t *nbr, int32_t k_stride,
                    const int8_t *order, int32_t m_uniform, int32_t n_uniform,
                    const int32_t *n_for_m, const double *G,
                    double *grad_x, double *grad_y)
+{
+    return oracle_adjoint_rows(n_nodes, x, y, nbr, k_stride, order, m_uniform, n_uniform,
+                               n_for_m, G, NULL, n_nodes, grad_x, grad_y);
+}
+
+/* As oracle_adjoint, with only the stencils of the listed nodes (in list
+ * order; rows == NULL: every node) contributing to the gradients. */
+int oracle_adjoint_rows(int64_t n_nodes, const double *x, const double *y,
+                        const int32_t *nbr, int32_t k_stride,
+                        const int8_t *order, int32_t m_uniform, int32_t n_uniform,
+                        const int32_t *n_for_m, const double *G,
+                        const int64_t *rows, int64_t n_rows,
+                        double *grad_x, double *grad_y)
 {
     int kmax = 0;
     if (order) {
@@ -734,9 +757,11 @@ int oracle_adjoint(int64_t n_nodes, const double *x, const double *y,
     memset(grad_x, 0, sizeof(double) * (size_t)n_nodes);
     memset(grad_y, 0, sizeof(double) * (size_t)n_nodes);
     int failed = 0;
-    for (int64_t i = 0; i < n_nodes; ++i) {
+    for (int64_t t = 0; t < n_rows; ++t) {
+        const int64_t i = rows ? rows[t] : t;
         int m, n;
-        if (support_of(order, m_uniform, n_uniform, n_for_m, i, &m, &n) != 0) {
+        if (i < 0 || i >= n_nodes ||
+            support_of(order, m_uniform, n_uniform, n_for_m, i, &m, &n) != 0) {
             failed = OR_EARG;
             break;
         }

@@ -136,6 +136,39 @@ def _dev(t: torch.Tensor, dtype, name: str) -> torch.Tensor:
     return t.contiguous()
 
 
+def _vec(t: torch.Tensor, n: int, dtype, name: str) -> torch.Tensor:
+    """An input of exactly n entries (the kernels index it by node or row)."""
+    t = _dev(t, dtype, name)
+    if t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} entries, expected {n}")
+    return t
+
+
+def _supports(nbr: torch.Tensor) -> torch.Tensor:
+    nbr = _dev(nbr, torch.int32, "nbr")
+    if nbr.dim() != 2 or nbr.shape[1] < 1:
+        raise ValueError(f"nbr must be [N, k], got shape {tuple(nbr.shape)}")
+    return nbr
+
+
+def _out(t, shape, dtype, name: str, device) -> torch.Tensor:
+    """A caller-provided output: written in place, so it is never copied;
+    anything but a contiguous device tensor of the exact shape is refused."""
+    if t is None:
+        return torch.empty(shape, dtype=dtype, device=device)
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise RbffdError(f"{name} must be a GPU tensor (the library has no CPU path)")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous (it is written in place)")
+    return t
+
+
 def _p(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
@@ -168,8 +201,8 @@ def rbffd_knn(x: torch.Tensor, y: torch.Tensor, k: int) -> torch.Tensor:
     """k nearest nodes of every node, ascending by (d^2, index): int32 [N, k]."""
     lib = _load()
     x = _dev(x, torch.float64, "x")
-    y = _dev(y, torch.float64, "y")
     N = x.numel()
+    y = _vec(y, N, torch.float64, "y")
     ws = _workspace(_size(lib.rbffd_knn_workspace_size, N, k), x.device)
     nbr = torch.empty((N, k), dtype=torch.int32, device=x.device)
     _check(lib.rbffd_knn(_p(x), _p(y), N, k, _p(nbr), _p(ws), ws.numel(), _stream(x.device)),
@@ -177,13 +210,20 @@ def rbffd_knn(x: torch.Tensor, y: torch.Tensor, k: int) -> torch.Tensor:
     return nbr
 
 
-def _order_args(order, m, n, n_for_order):
+def _order_args(order, m, n, n_for_order, N):
     if order is None:
         if m is None or n is None:
             raise ValueError("give (m, n) or a per-node order")
         return None, int(m), int(n), None, n + n_monomials(m)
     kmax = max(nv + n_monomials(mv) for mv, nv in zip((2, 4, 6), n_for_order))
-    return _dev(order, torch.int8, "order"), -1, -1, _n_for_order(n_for_order), kmax
+    return _vec(order, N, torch.int8, "order"), -1, -1, _n_for_order(n_for_order), kmax
+
+
+def _nodes2(x, y, nbr):
+    """Coordinates and supports: x, y [N] FP64, nbr [N, k] int32."""
+    nbr = _supports(nbr)
+    N = nbr.shape[0]
+    return _vec(x, N, torch.float64, "x"), _vec(y, N, torch.float64, "y"), nbr, N, nbr.shape[1]
 
 
 def rbffd_weights(x, y, nbr, m=None, n=None, order=None, n_for_order=DEFAULT_N_FOR_ORDER,
@@ -196,19 +236,17 @@ def rbffd_weights(x, y, nbr, m=None, n=None, order=None, n_for_order=DEFAULT_N_F
     int32 [N] tensor, optional) receives the corrections per stencil.
     """
     lib = _load()
-    x = _dev(x, torch.float64, "x")
-    y = _dev(y, torch.float64, "y")
-    nbr = _dev(nbr, torch.int32, "nbr")
-    N, ks = nbr.shape
-    o, m_, n_, nfo, kmax = _order_args(order, m, n, n_for_order)
-    w = out if out is not None else torch.empty((N, ks), dtype=torch.float64, device=x.device)
-    st = status if status is not None else torch.empty(N, dtype=torch.int32, device=x.device)
+    x, y, nbr, N, ks = _nodes2(x, y, nbr)
+    o, m_, n_, nfo, kmax = _order_args(order, m, n, n_for_order, N)
+    w = _out(out, (N, ks), torch.float64, "out", x.device)
+    st = _out(status, (N,), torch.int32, "status", x.device)
     sv = None
     if save:
         sv = _workspace(_size(lib.rbffd_weights_save_size, N, kmax), x.device)
     ws = _workspace(_size(lib.rbffd_weights_workspace_size, N, int(o is not None), precision),
                     x.device)
-    rs = None if refine_steps is None else _dev(refine_steps, torch.int32, "refine_steps")
+    rs = None if refine_steps is None else \
+        _out(refine_steps, (N,), torch.int32, "refine_steps", x.device)
     _check(lib.rbffd_weights(_p(x), _p(y), N, _p(nbr), ks, _p(o), m_, n_, nfo, precision,
                              _p(w), _p(st), _p(rs), _p(sv), 0 if sv is None else sv.numel(),
                              _p(ws), ws.numel(), _stream(x.device)), "rbffd_weights")
@@ -219,12 +257,9 @@ def rbffd_weights_op(x, y, nbr, m: int, n: int, op: int, out=None, status=None):
     """Weights of eq. (1) for the operator op (OP_LAPLACIAN, OP_DX, OP_DY),
     FP64, uniform (m, n).  Returns (w [N, k_stride], status [N])."""
     lib = _load()
-    x = _dev(x, torch.float64, "x")
-    y = _dev(y, torch.float64, "y")
-    nbr = _dev(nbr, torch.int32, "nbr")
-    N, ks = nbr.shape
-    w = out if out is not None else torch.empty((N, ks), dtype=torch.float64, device=x.device)
-    st = status if status is not None else torch.empty(N, dtype=torch.int32, device=x.device)
+    x, y, nbr, N, ks = _nodes2(x, y, nbr)
+    w = _out(out, (N, ks), torch.float64, "out", x.device)
+    st = _out(status, (N,), torch.int32, "status", x.device)
     _check(lib.rbffd_weights_op(_p(x), _p(y), N, _p(nbr), ks, int(m), int(n), int(op), _p(w),
                                 _p(st), _stream(x.device)), "rbffd_weights_op")
     return w, st
@@ -237,11 +272,11 @@ def rbffd_knn3(x, y, z, k: int, out=None):
     x = _dev(x, torch.float64, "x")
     y = _dev(y, torch.float64, "y")
     z = _dev(z, torch.float64, "z")
-    N = x.shape[0]
-    if y.shape[0] != N or z.shape[0] != N:
-        raise RbffdError("x, y and z must have the same length")
+    N = x.numel()
+    y = _vec(y, N, torch.float64, "y")
+    z = _vec(z, N, torch.float64, "z")
     ws = _workspace(_size(lib.rbffd_knn3_workspace_size, N, int(k)), x.device)
-    nbr = out if out is not None else torch.empty((N, k), dtype=torch.int32, device=x.device)
+    nbr = _out(out, (N, int(k)), torch.int32, "out", x.device)
     _check(lib.rbffd_knn3(_p(x), _p(y), _p(z), N, int(k), _p(nbr), _p(ws), ws.numel(),
                           _stream(x.device)), "rbffd_knn3")
     return nbr
@@ -252,15 +287,10 @@ def rbffd_weights3(x, y, z, nbr, m: int = 2, n: int = 20, out=None, status=None,
     FP64: the Laplacian, or with op one of OP_DX, OP_DY, OP3_DZ a first
     derivative.  Returns (w [N, k_stride], status [N])."""
     lib = _load()
-    x = _dev(x, torch.float64, "x")
-    y = _dev(y, torch.float64, "y")
-    z = _dev(z, torch.float64, "z")
-    nbr = _dev(nbr, torch.int32, "nbr")
-    N, ks = nbr.shape
-    if x.shape[0] != N or y.shape[0] != N or z.shape[0] != N:
-        raise RbffdError("x, y, z must be [N] and nbr [N, k_stride]")
-    w = out if out is not None else torch.empty((N, ks), dtype=torch.float64, device=x.device)
-    st = status if status is not None else torch.empty(N, dtype=torch.int32, device=x.device)
+    x, y, nbr, N, ks = _nodes2(x, y, nbr)
+    z = _vec(z, N, torch.float64, "z")
+    w = _out(out, (N, ks), torch.float64, "out", x.device)
+    st = _out(status, (N,), torch.int32, "status", x.device)
     if op is None:
         _check(lib.rbffd_weights3(_p(x), _p(y), _p(z), N, _p(nbr), ks, int(m), int(n), _p(w),
                                   _p(st), _stream(x.device)), "rbffd_weights3")
@@ -275,16 +305,19 @@ def rbffd_weights_backward(x, y, nbr, grad_w, save, status=None, m=None, n=None,
                            n_for_order=DEFAULT_N_FOR_ORDER):
     """dL/dx, dL/dy [N] from dL/dw, reusing the factors saved by rbffd_weights."""
     lib = _load()
-    x = _dev(x, torch.float64, "x")
-    y = _dev(y, torch.float64, "y")
-    nbr = _dev(nbr, torch.int32, "nbr")
+    x, y, nbr, N, ks = _nodes2(x, y, nbr)
     grad_w = _dev(grad_w, torch.float64, "grad_w")
-    N, ks = nbr.shape
-    o, m_, n_, nfo, _ = _order_args(order, m, n, n_for_order)
+    if tuple(grad_w.shape) != (N, ks):
+        raise ValueError(f"grad_w must have the shape of nbr {(N, ks)}, got {tuple(grad_w.shape)}")
+    o, m_, n_, nfo, kmax = _order_args(order, m, n, n_for_order, N)
+    save = _dev(save, torch.uint8, "save")
+    need = _size(lib.rbffd_weights_save_size, N, kmax)
+    if save.numel() < need:
+        raise ValueError(f"save has {save.numel()} bytes, the factors need {need}")
     gx = torch.empty(N, dtype=torch.float64, device=x.device)
     gy = torch.empty(N, dtype=torch.float64, device=x.device)
     ws = _workspace(_size(lib.rbffd_weights_backward_workspace_size, N, ks), x.device)
-    st = None if status is None else _dev(status, torch.int32, "status")
+    st = None if status is None else _vec(status, N, torch.int32, "status")
     _check(lib.rbffd_weights_backward(_p(x), _p(y), N, _p(nbr), ks, _p(o), m_, n_, nfo,
                                       _p(grad_w), _p(save), save.numel(), _p(st), _p(gx), _p(gy),
                                       _p(ws), ws.numel(), _stream(x.device)),
@@ -299,14 +332,19 @@ def rbffd_assemble_csr(nbr, w, n=None, order=None, n_for_order=DEFAULT_N_FOR_ORD
     col/val have capacity N * max n; the first row_ptr[N] entries are valid.
     """
     lib = _load()
-    nbr = _dev(nbr, torch.int32, "nbr")
-    w = _dev(w, torch.float64, "w")
+    nbr = _supports(nbr)
     N, ks = nbr.shape
+    w = _dev(w, torch.float64, "w")
+    if tuple(w.shape) != (N, ks):
+        raise ValueError(f"w must have the shape of nbr {(N, ks)}, got {tuple(w.shape)}")
     if order is None:
+        if n is None:
+            raise ValueError("give n or a per-node order")
         o, nfo, nmax = None, None, int(n)
     else:
-        o, nfo, nmax = _dev(order, torch.int8, "order"), _n_for_order(n_for_order), max(n_for_order)
-    b = None if is_boundary is None else _dev(is_boundary, torch.uint8, "is_boundary")
+        o, nfo, nmax = _vec(order, N, torch.int8, "order"), _n_for_order(n_for_order), \
+            max(n_for_order)
+    b = None if is_boundary is None else _vec(is_boundary, N, torch.uint8, "is_boundary")
     cap = N * nmax
     row_ptr = torch.empty(N + 1, dtype=torch.int64, device=nbr.device)
     col = torch.empty(cap, dtype=torch.int32, device=nbr.device)
@@ -324,10 +362,15 @@ def rbffd_spmv(row_ptr, col, val, u, f=None, out=None):
     row_ptr = _dev(row_ptr, torch.int64, "row_ptr")
     col = _dev(col, torch.int32, "col")
     val = _dev(val, torch.float64, "val")
-    u = _dev(u, torch.float64, "u")
-    fz = None if f is None else _dev(f, torch.float64, "f")
     n = row_ptr.numel() - 1
-    y = out if out is not None else torch.empty(n, dtype=torch.float64, device=u.device)
+    if n < 1:
+        raise ValueError("row_ptr must have at least two entries")
+    if col.numel() != val.numel():
+        raise ValueError(f"col ({col.numel()}) and val ({val.numel()}) differ in length")
+    # the operator is square (one column per node): u has one entry per row
+    u = _vec(u, n, torch.float64, "u")
+    fz = None if f is None else _vec(f, n, torch.float64, "f")
+    y = _out(out, (n,), torch.float64, "out", u.device)
     _check(lib.rbffd_spmv(n, _p(row_ptr), _p(col), _p(val), _p(u), _p(fz), _p(y),
                           _stream(u.device)), "rbffd_spmv")
     return y
@@ -341,11 +384,11 @@ def rbffd_solve(row_ptr, col, val, b, x0=None, rtol: float = 1e-10, max_iter: in
     row_ptr = _dev(row_ptr, torch.int64, "row_ptr")
     col = _dev(col, torch.int32, "col")
     val = _dev(val, torch.float64, "val")
-    b = _dev(b, torch.float64, "b")
     n = row_ptr.numel() - 1
-    if b.numel() != n:
-        raise ValueError(f"b has {b.numel()} entries for {n} rows")
-    x = torch.zeros_like(b) if x0 is None else _dev(x0, torch.float64, "x0").clone()
+    if col.numel() != val.numel():
+        raise ValueError(f"col ({col.numel()}) and val ({val.numel()}) differ in length")
+    b = _vec(b, n, torch.float64, "b")
+    x = torch.zeros_like(b) if x0 is None else _vec(x0, n, torch.float64, "x0").clone()
     ws = _workspace(_size(lib.rbffd_solve_workspace_size, n), b.device)
     it, rr, info = ctypes.c_int32(0), ctypes.c_double(0.0), ctypes.c_int32(0)
     _check(lib.rbffd_solve(n, _p(row_ptr), _p(col), _p(val), _p(b), _p(x), float(rtol),
@@ -359,17 +402,17 @@ def rbffd_time_steps(nbr, w, n: int, f, u, dt: float, n_steps: int, is_boundary=
     """n_steps of the explicit pseudo-time loop of eq. (3), in place on u:
     u <- u + dt (f + sum_k w u[nbr]) at interior nodes.  Returns u."""
     lib = _load()
-    nbr = _dev(nbr, torch.int32, "nbr")
-    w = _dev(w, torch.float64, "w")
-    f = _dev(f, torch.float64, "f")
-    if not isinstance(u, torch.Tensor) or not u.is_cuda or u.dtype != torch.float64 \
-            or not u.is_contiguous():
-        raise TypeError("u must be a contiguous FP64 GPU tensor (updated in place)")
+    nbr = _supports(nbr)
     N, ks = nbr.shape
-    b = None if is_boundary is None else _dev(is_boundary, torch.uint8, "is_boundary")
-    work = u_work if u_work is not None else torch.empty_like(u)
-    ws = workspace if workspace is not None else \
-        _workspace(_size(lib.rbffd_time_steps_workspace_size, N, max(int(n), 1)), u.device)
+    w = _dev(w, torch.float64, "w")
+    if tuple(w.shape) != (N, ks):
+        raise ValueError(f"w must have the shape of nbr {(N, ks)}, got {tuple(w.shape)}")
+    f = _vec(f, N, torch.float64, "f")
+    u = _out(u, (N,), torch.float64, "u", f.device)
+    b = None if is_boundary is None else _vec(is_boundary, N, torch.uint8, "is_boundary")
+    work = _out(u_work, (N,), torch.float64, "u_work", f.device)
+    ws = _workspace(_size(lib.rbffd_time_steps_workspace_size, N, max(int(n), 1)), u.device) \
+        if workspace is None else _dev(workspace, torch.uint8, "workspace")
     _check(lib.rbffd_time_steps(N, _p(nbr), ks, int(n), _p(w), _p(b), _p(f), float(dt),
                                 int(n_steps), _p(u), _p(work), _p(ws), ws.numel(),
                                 _stream(u.device)), "rbffd_time_steps")

@@ -13,7 +13,8 @@
 //      previous one (the first is compared with max|z| of the initial
 //      solve), a non-finite value, an FP32 zero or non-finite pivot, or no
 //      convergence after 10 corrections sends the stencil to the FP64 kernel
-//      (appended to a list; that launch reports RBFFD_FELL_BACK_FP64).
+//      (appended to a list; that launch reports RBFFD_FELL_BACK_FP64); the
+//      corrections tried before the fallback are reported.
 // Layout: as the FP64 multi-slot kernel (SEG lanes per stencil, SL rows per
 // lane) with FP32 rows, i.e. half the registers per row, so more stencils fit
 // in a wavefront.  The FP64 matrix rows needed by the residual go to a
@@ -384,7 +385,7 @@ __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1))) void weights_mx_kernel(
                 }
             } else if (l0 == 0) {
                 fb_list[atomicAdd(fb_count, 1)] = (int32_t)i;
-                if (iters) iters[i] = 0;
+                if (iters) iters[i] = nit;  // the corrections tried
             }
         }
         __syncthreads();  // LDS reuse by the next stencil group

@@ -189,3 +189,16 @@ def test_backward_full_size_annulus():
     err = np.abs(np.array(adj) - np.array(fd)).max() / np.abs(np.array(fd)).max()
     say(f"  FD rel err {err:.3e}")
     assert err <= 1e-6
+    # the oracle's adjoint on 150 sampled nodes: every stencil that names a
+    # sampled node (its own and those whose supports hold it) contributes
+    sample = rng.choice(ns.n_nodes, size=150, replace=False)
+    touch = np.nonzero(np.isin(nbr, sample).any(axis=1))[0]
+    rows = np.unique(np.concatenate([sample, touch]))
+    say(f"  oracle adjoint over {rows.size} stencils")
+    gxo, gyo, failed = oracle.adjoint(ns.x, ns.y, nbr, host(G), m=m, n=n, rows=rows)
+    assert failed == 0
+    scale = max(np.abs(gxo[sample]).max(), np.abs(gyo[sample]).max())
+    err = max(np.abs(gx[sample] - gxo[sample]).max(),
+              np.abs(gy[sample] - gyo[sample]).max()) / scale
+    say(f"  vs oracle adjoint {err:.3e}")
+    assert err <= 1e-11

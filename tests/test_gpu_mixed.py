@@ -122,3 +122,49 @@ def test_mixed_order_batch():
     for m in (2, 4, 6):
         sel = ns.order == m
         assert rel_err(w[sel], w_mx[sel], NFM[m]).max() <= 1e-12
+
+
+@pytest.mark.parametrize("m", [2, 4, 6])
+def test_mixed_1m_square_sampled(m):
+    """The 1M-node square (h = 1e-3) in mixed precision at m = 2, 4, 6: the
+    launches run several grid-stride passes at this size.  Sampled rows
+    against the mixed oracle (statuses and corrections exactly) and the FP64
+    oracle (1e-9)."""
+    ns = nodes.workload("square_1m_m6")
+    n = NFM[m]
+    say("mixed 1M square m =", m, ns.n_nodes)
+    X, Y = dev(ns.x), dev(ns.y)
+    NB = rb.rbffd_knn(X, Y, n)
+    it = torch.zeros(ns.n_nodes, dtype=torch.int32, device="cuda")
+    w, st, _ = rb.rbffd_weights(X, Y, NB, m=m, n=n, precision=rb.MIXED, refine_steps=it)
+    w, st, it, nbr = host(w), host(st), host(it), host(NB)
+    assert np.all((st == 0) | (st == rb.FELL_BACK_FP64))
+    rng = np.random.default_rng(7 + m)
+    rows = np.unique(np.concatenate([rng.choice(ns.n_nodes, size=300, replace=False),
+                                     [0, 999, ns.n_nodes - 1], np.arange(ns.n_nodes - 40, ns.n_nodes)]))
+    full = np.zeros_like(nbr)
+    full[rows] = nbr[rows]
+    w_mx, st_mx, it_mx = oracle.weights_mixed(ns.x, ns.y, full, m=m, n=n, rows=rows)
+    assert np.array_equal(st[rows], st_mx) and np.array_equal(it[rows], it_mx)
+    assert rel_err(w[rows], w_mx, n).max() <= 1e-12
+    w64, _ = oracle.weights(ns.x, ns.y, full, m=m, n=n, rows=rows)
+    assert rel_err(w[rows], w64, n).max() <= 1e-9
+    say("  statuses", np.bincount(st), "mean corrections", it[st == 0].mean())
+
+
+@pytest.mark.parametrize("i,k,tries", [(40, 16, 1), (90, 7, 1), (40, 8, 10), (90, 1, 10)])
+def test_mixed_fallback_rule_and_cap(i, k, tries):
+    """The crafted stencils of the oracle's fallback pins (corrections that
+    shrink by more or less than one half, or too slowly for the cap): the
+    GPU falls back at the same correction."""
+    ns = nodes.unit_square(12, seed=3)
+    nbr = oracle.knn(ns.x, ns.y, 12)
+    d = 10.0 ** (-4.0 - k / 20.0)
+    x, y = ns.x.copy(), ns.y.copy()
+    x[nbr[i, 4]] = x[nbr[i, 3]] + d
+    y[nbr[i, 4]] = y[nbr[i, 3]] + 0.3 * d
+    w_mx, st_mx, it_mx = oracle.weights_mixed(x, y, nbr, m=2, n=12)
+    w, st, it = gpu_mixed(x, y, nbr, m=2, n=12)
+    assert st_mx[i] == oracle.FELL_BACK and it_mx[i] == tries
+    assert np.array_equal(st, st_mx) and np.array_equal(it, it_mx)
+    assert rel_err(w, w_mx, 12).max() <= 1e-12

@@ -61,3 +61,21 @@ def test_adjoint_self_node_and_translation_invariance():
     assert failed == 0
     assert abs(gx.sum()) <= 1e-9 * np.abs(gx).sum()
     assert abs(gy.sum()) <= 1e-9 * np.abs(gy).sum()
+
+
+def test_adjoint_restricted_to_the_stencils_of_sampled_nodes():
+    # the gradient at a node only gathers the stencils that name it, so the
+    # adjoint over those stencils alone gives the same bits there
+    ns = nodes.unit_square(14, seed=12)
+    nbr = oracle.knn(ns.x, ns.y, 30)
+    G = nodes.gaussian_cotangent(ns.n_nodes, 30, seed=3)
+    gx, gy, failed = oracle.adjoint(ns.x, ns.y, nbr, G, m=4, n=30)
+    assert failed == 0
+    sample = np.array([3, 50, 111, 170])
+    rows = np.unique(np.concatenate([sample, np.nonzero(np.isin(nbr, sample).any(axis=1))[0]]))
+    assert rows.size < ns.n_nodes
+    gxr, gyr, failed = oracle.adjoint(ns.x, ns.y, nbr, G, m=4, n=30, rows=rows)
+    assert failed == 0
+    assert np.array_equal(gxr[sample], gx[sample]) and np.array_equal(gyr[sample], gy[sample])
+    others = np.setdiff1d(np.arange(ns.n_nodes), rows)
+    assert np.any(gxr[others] != gx[others])

@@ -59,7 +59,7 @@ def test_mixed_falls_back_to_fp64_on_ill_conditioned_stencil():
     w64, st64 = oracle.weights(x, y, nbr, m=2, n=12, rows=[i])
     wm, stm, it = oracle.weights_mixed(x, y, nbr, m=2, n=12, rows=[i])
     assert st64[0] == oracle.OK
-    assert stm[0] == oracle.FELL_BACK and it[0] == 0
+    assert stm[0] == oracle.FELL_BACK and 1 <= it[0] <= 10
     assert np.array_equal(wm, w64)
     # a milder pair (1e-3 apart) is refined instead, to the same weights
     x[nbr[i, 4]] = x[nbr[i, 3]] + 1e-3
@@ -77,3 +77,85 @@ def test_mixed_reports_assembly_failures_without_fallback():
     wm, stm, _ = oracle.weights_mixed(ns.x, ns.y, nb, m=2, n=12, rows=[10, 11])
     assert stm[0] == oracle.DUPLICATE and np.all(np.isnan(wm[0]))
     assert stm[1] == oracle.OK
+
+
+def test_lu32_is_a_partial_pivoting_factorisation():
+    # P M32 = L U to FP32 rounding, unit L, and every pivot the first largest
+    # |entry| of its column among the rows not yet pivoted
+    ns = nodes.unit_square(12, seed=3)
+    nbr = oracle.knn(ns.x, ns.y, 30)
+    st, M, rhs, s = oracle.assemble(ns.x, ns.y, 77, nbr[77], 4)
+    st, LU, perm, dinv = oracle.lu32(M)
+    assert st == oracle.OK
+    K = M.shape[0]
+    A = M.astype(np.float32).astype(np.float64)
+    L = np.tril(LU.astype(np.float64), -1) + np.eye(K)
+    U = np.triu(LU.astype(np.float64))
+    PA = A.copy()
+    for c in range(K):
+        p = perm[c]
+        PA[[c, p]] = PA[[p, c]]
+    assert np.abs(PA - L @ U).max() <= 64 * np.finfo(np.float32).eps * np.abs(A).max()
+    assert np.abs(L).max() <= 1.0
+    assert np.allclose(dinv.astype(np.float64), 1.0 / np.diag(U), rtol=1e-7)
+
+
+# The refinement's fallback rule (a correction larger than half the previous
+# one, the first compared with max|z0|) and its cap of 10 corrections are
+# pinned by stencils whose FP32 factors contract the error at a known rate.
+# The rate comes from the oracle's FP32 factors F = P^T L U, iterated here in
+# FP64 arithmetic: z0 = F^-1 b, then z += F^-1 (b - M z).  Two support nodes
+# are pulled together by delta to set cond(M), hence the rate.
+
+def _perturbed(i, k):
+    ns = nodes.unit_square(12, seed=3)
+    nbr = oracle.knn(ns.x, ns.y, 12)
+    d = 10.0 ** (-4.0 - k / 20.0)
+    x, y = ns.x.copy(), ns.y.copy()
+    x[nbr[i, 4]] = x[nbr[i, 3]] + d
+    y[nbr[i, 4]] = y[nbr[i, 3]] + 0.3 * d
+    return x, y, nbr
+
+
+def _model_ratios(M, b, steps=10):
+    st, LU, perm, _ = oracle.lu32(M)
+    assert st == oracle.OK
+    K = M.shape[0]
+    L = np.tril(LU.astype(np.float64), -1) + np.eye(K)
+    U = np.triu(LU.astype(np.float64))
+    P = np.eye(K)
+    for c in range(K):
+        p = perm[c]
+        P[[c, p]] = P[[p, c]]
+    F = P.T @ L @ U
+    z = np.linalg.solve(F, b)
+    prev = np.abs(z).max()
+    out = []
+    for _ in range(steps):
+        d = np.linalg.solve(F, b - M @ z)
+        z = z + d
+        dn = np.abs(d).max()
+        out.append(dn / prev)
+        prev = dn
+    return np.array(out)
+
+
+@pytest.mark.parametrize("i,k,lo,hi,tries", [
+    (40, 16, 0.70, 0.80, 1),   # corrections shrink by ~0.75: the first one already
+    (90, 12, 0.78, 0.82, 1),   # exceeds half of max|z0|
+    (90, 7, 0.50, 0.52, 1),    # just above one half
+    (40, 8, 0.47, 0.50, 10),   # just below one half: refined until the cap
+    (90, 1, 0.20, 0.22, 10),   # ~0.2 per step: too slow for 1e-12 in 10
+    (77, 9, 0.32, 0.34, 10),
+])
+def test_mixed_fallback_rule_and_cap(i, k, lo, hi, tries):
+    x, y, nbr = _perturbed(i, k)
+    st, M, rhs, s = oracle.assemble(x, y, i, nbr[i], 2)
+    rat = _model_ratios(M, rhs)
+    assert np.all((rat >= lo) & (rat <= hi)), rat
+    wm, stm, it = oracle.weights_mixed(x, y, nbr, m=2, n=12, rows=[i])
+    w64, st64 = oracle.weights(x, y, nbr, m=2, n=12, rows=[i])
+    assert st64[0] == oracle.OK
+    assert stm[0] == oracle.FELL_BACK
+    assert it[0] == tries
+    assert np.array_equal(wm, w64)
