@@ -22,7 +22,8 @@
  *     RBFFD_OK ... RBFFD_DUPLICATE below) and the failed stencil's weights
  *     are NaN, so it cannot be used silently.
  *   - Calls on different streams are independent; the only process-wide
- *     state is the batch tuning table (rbffd_batch_tuning_set).
+ *     state is the batch tuning table (rbffd_batch_tuning_set) and the fixed
+ *     scratch array of rbffd_knn_noalloc.
  */
 #ifndef RBFFD_H
 #define RBFFD_H
@@ -39,6 +40,7 @@ extern "C" {
 #define RBFFD_ERR_ARG (-1)          /* invalid argument (null, size, range) */
 #define RBFFD_ERR_WORKSPACE (-2)    /* workspace missing or too small */
 #define RBFFD_ERR_UNSUPPORTED (-3)  /* valid but not built (e.g. K > 96) */
+#define RBFFD_ERR_TOO_LARGE (-4)    /* input too large for a no-allocation call */
 #define RBFFD_ERR_HIP (-100)        /* RBFFD_ERR_HIP - hipError_t */
 
 /* ---- per-stencil status codes ------------------------------------------ */
@@ -85,6 +87,33 @@ int rbffd_version(void);
 int rbffd_knn_workspace_size(int64_t n_nodes, int32_t k, size_t *bytes /* host */);
 int rbffd_knn(const double *x, const double *y, int64_t n_nodes, int32_t k,
               int32_t *nbr, void *workspace, size_t workspace_bytes, void *stream);
+
+/* --------------------------------------------------------------------------
+ * rbffd_knn without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments (minus the workspace), same kernels and
+ * the same nbr, bit for bit.  Its scratch is a fixed array of
+ * RBFFD_KNN_NOALLOC_SCRATCH_BYTES in device memory that the library holds on
+ * every GPU it runs on, until the process ends; the call itself allocates
+ * nothing and frees nothing.
+ *
+ * Size limit: the call is accepted when rbffd_knn_workspace_size(n_nodes, k)
+ * is at most RBFFD_KNN_NOALLOC_SCRATCH_BYTES: every k <= 64 up to at least
+ * 1,397,396 nodes, and the standard supports k = 12, 30, 56 up to 2,236,160,
+ * 2,329,376 and 2,515,808 nodes.  Larger inputs return RBFFD_ERR_TOO_LARGE
+ * before anything is enqueued.
+ * Device: the scratch used is the current device's (hipGetDevice); the
+ * stream must belong to that device.  The first call on a device looks the
+ * array up (hipGetSymbolAddress) and keeps its address.
+ * Concurrency: every call on one GPU shares that GPU's array, so calls that
+ * overlap in time on one GPU (other streams, other host threads) race and
+ * corrupt each other's results; serialise them (one stream, or events).
+ * Each call clears what it needs cleared (a fill kernel, no memset) and
+ * overwrites the rest, so the previous call's contents do no harm.
+ * ------------------------------------------------------------------------ */
+#define RBFFD_KNN_NOALLOC_SCRATCH_BYTES (64u << 20)
+int rbffd_knn_noalloc(const double *x, const double *y, int64_t n_nodes, int32_t k,
+                      int32_t *nbr, void *stream);
 
 /* ==========================================================================
  * Stencil weights: w of eq. (1) for L = Laplacian with phi(r) = r^3 and all

@@ -46,6 +46,7 @@ def _load():
             "rbffd_version": ([], ctypes.c_int),
             "rbffd_knn_workspace_size": ([I64, I32, PSZ], ctypes.c_int),
             "rbffd_knn": ([P, P, I64, I32, P, P, SZ, P], ctypes.c_int),
+            "rbffd_knn_noalloc": ([P, P, I64, I32, P, P], ctypes.c_int),
             "rbffd_weights_workspace_size": ([I64, I32, I32, PSZ], ctypes.c_int),
             "rbffd_weights_save_size": ([I64, I32, PSZ], ctypes.c_int),
             "rbffd_weights": ([P, P, I64, P, I32, P, I32, I32, P, I32, P, P, P, P, SZ, P, SZ,
@@ -207,6 +208,20 @@ def rbffd_knn(x: torch.Tensor, y: torch.Tensor, k: int) -> torch.Tensor:
     nbr = torch.empty((N, k), dtype=torch.int32, device=x.device)
     _check(lib.rbffd_knn(_p(x), _p(y), N, k, _p(nbr), _p(ws), ws.numel(), _stream(x.device)),
            "rbffd_knn")
+    return nbr
+
+
+def rbffd_knn_noalloc(x: torch.Tensor, y: torch.Tensor, k: int, out=None) -> torch.Tensor:
+    """rbffd_knn with the library's fixed scratch instead of a workspace (the
+    C call allocates nothing).  out: an optional int32 [N, k] output, written
+    in place; without it one is allocated here, by torch."""
+    lib = _load()
+    x = _dev(x, torch.float64, "x")
+    N = x.numel()
+    y = _vec(y, N, torch.float64, "y")
+    nbr = _out(out, (N, k), torch.int32, "out", x.device)
+    _check(lib.rbffd_knn_noalloc(_p(x), _p(y), N, k, _p(nbr), _stream(x.device)),
+           "rbffd_knn_noalloc")
     return nbr
 
 

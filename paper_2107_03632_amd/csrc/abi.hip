@@ -147,6 +147,7 @@ extern "C" const char *rbffd_error_string(int code) {
     case RBFFD_ERR_ARG: return "invalid argument";
     case RBFFD_ERR_WORKSPACE: return "workspace missing or too small";
     case RBFFD_ERR_UNSUPPORTED: return "unsupported configuration";
+    case RBFFD_ERR_TOO_LARGE: return "input exceeds the fixed scratch of a no-allocation call";
     case RBFFD_SINGULAR: return "stencil: zero pivot (singular system)";
     case RBFFD_FELL_BACK_FP64: return "stencil: mixed precision fell back to FP64";
     case RBFFD_NONFINITE: return "stencil: non-finite coordinate, pivot or solution";

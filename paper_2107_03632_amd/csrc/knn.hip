@@ -18,6 +18,8 @@
 
 #include <float.h>
 
+#include <mutex>
+
 #include "common.h"
 #include "knn_topk.h"
 
@@ -310,15 +312,14 @@ extern "C" int rbffd_knn_workspace_size(int64_t n_nodes, int32_t k, size_t *byte
     return RBFFD_SUCCESS;
 }
 
-extern "C" int rbffd_knn(const double *x, const double *y, int64_t n_nodes, int32_t k,
-                         int32_t *nbr, void *workspace, size_t workspace_bytes, void *stream) {
-    if (!x || !y || !nbr || n_nodes < 1 || n_nodes >= INT32_MAX || k < 1 || k > n_nodes)
-        return RBFFD_ERR_ARG;
-    if (k > 64) return RBFFD_ERR_UNSUPPORTED;
-    KnnWs w = carve(nullptr, n_nodes, k);
-    if (!workspace || workspace_bytes < w.bytes) return RBFFD_ERR_WORKSPACE;
-    w = carve(workspace, n_nodes, k);
-    hipStream_t s = static_cast<hipStream_t>(stream);
+namespace rbffd {
+namespace {
+
+// The whole search on stream s with the workspace carved as w.  Everything
+// that must start at zero (the two cell histograms) is cleared here by a
+// fill kernel; the rest of the workspace is written before it is read.
+int knn_launch(const double *x, const double *y, int64_t n_nodes, int32_t k, int32_t *nbr,
+               const KnnWs &w, hipStream_t s) {
     const int64_t cells = max_cells(n_nodes, k);
     const unsigned nb = (unsigned)ceil_div(n_nodes, kThreads);
     const int parts = (int)(ceil_div(n_nodes, kThreads) < kBBoxBlocks ? ceil_div(n_nodes, kThreads)
@@ -366,4 +367,62 @@ extern "C" int rbffd_knn(const double *x, const double *y, int64_t n_nodes, int3
                                xs, ys, n_nodes, k, nbr);
     }
     return last_launch_rc();
+}
+
+// Scratch of rbffd_knn_noalloc, used in place of a caller workspace.  Each
+// GPU the library runs on holds its own copy of this array until the process
+// ends.  Host code never passes the array's name to a kernel (on the host it
+// is a stand-in, not a device address): it uses the per-device address from
+// hipGetSymbolAddress below.
+static __device__ __align__(256) char scratch[RBFFD_KNN_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's copy of `scratch`, looked up once per device (with
+// that device current) and kept.
+int scratch_for_current_device(void **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_rc(e);
+    if (dev < 0 || dev >= kMaxDevices) return RBFFD_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_rc(e);
+        if (!p) return RBFFD_ERR_HIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return RBFFD_SUCCESS;
+}
+
+}  // namespace
+}  // namespace rbffd
+
+extern "C" int rbffd_knn(const double *x, const double *y, int64_t n_nodes, int32_t k,
+                         int32_t *nbr, void *workspace, size_t workspace_bytes, void *stream) {
+    if (!x || !y || !nbr || n_nodes < 1 || n_nodes >= INT32_MAX || k < 1 || k > n_nodes)
+        return RBFFD_ERR_ARG;
+    if (k > 64) return RBFFD_ERR_UNSUPPORTED;
+    KnnWs w = carve(nullptr, n_nodes, k);
+    if (!workspace || workspace_bytes < w.bytes) return RBFFD_ERR_WORKSPACE;
+    w = carve(workspace, n_nodes, k);
+    return knn_launch(x, y, n_nodes, k, nbr, w, static_cast<hipStream_t>(stream));
+}
+
+extern "C" int rbffd_knn_noalloc(const double *x, const double *y, int64_t n_nodes, int32_t k,
+                                 int32_t *nbr, void *stream) {
+    if (!x || !y || !nbr || n_nodes < 1 || n_nodes >= INT32_MAX || k < 1 || k > n_nodes)
+        return RBFFD_ERR_ARG;
+    if (k > 64) return RBFFD_ERR_UNSUPPORTED;
+    KnnWs w = carve(nullptr, n_nodes, k);
+    if (w.bytes > (size_t)RBFFD_KNN_NOALLOC_SCRATCH_BYTES) return RBFFD_ERR_TOO_LARGE;
+    void *base = nullptr;
+    const int rc = scratch_for_current_device(&base);
+    if (rc) return rc;
+    w = carve(base, n_nodes, k);
+    return knn_launch(x, y, n_nodes, k, nbr, w, static_cast<hipStream_t>(stream));
 }

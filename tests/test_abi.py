@@ -101,6 +101,20 @@ def test_argument_errors_before_any_launch(lib):
     assert lib.rbffd_solve_workspace_size(0, ctypes.byref(sz)) == -1
 
 
+def test_noalloc_knn_refuses_on_the_host(lib):
+    # argument errors and inputs past the fixed scratch are refused before
+    # the device is touched (the pointers are never dereferenced)
+    P = ctypes.c_void_p
+    lib.rbffd_knn_noalloc.argtypes = [P, P, ctypes.c_int64, ctypes.c_int32, P, P]
+    assert lib.rbffd_knn_noalloc(None, None, 10, 3, None, None) == -1
+    fake = P(256)
+    assert lib.rbffd_knn_noalloc(fake, fake, 100, 65, fake, None) == -3
+    assert lib.rbffd_knn_noalloc(fake, fake, 3_000_000, 12, fake, None) == -4
+    assert lib.rbffd_knn_noalloc(fake, fake, 1_400_000, 1, fake, None) == -4
+    lib.rbffd_error_string.restype = ctypes.c_char_p
+    assert b"no-allocation" in lib.rbffd_error_string(-4)
+
+
 def test_product_path_never_imports_the_oracle():
     pkg = os.path.join(ROOT, "paper_2107_03632_amd")
     for dirpath, _, files in os.walk(pkg):
