@@ -115,27 +115,103 @@ def measured_fma_peak(torch, dev, dtype: int, blocks: int = 8192, iters: int = 4
     return blocks * 256 * iters * 8 * 2 / (ms * 1e-3) / 1e12
 
 
+def host_cpu():
+    """The host's CPU model, its logical CPU count and the threads this
+    process may use (its affinity set, capped by OMP_NUM_THREADS if set)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    threads = min(avail, int(env)) if env.isdigit() and int(env) > 0 else avail
+    return model, os.cpu_count(), max(1, threads)
+
+
+def _oracle_rows_parallel(fn, rows, threads):
+    """fn(chunk) over `rows` split into contiguous chunks, one host thread
+    each.  The oracle's C calls release the GIL, so the chunks run on
+    separate cores; each stencil is computed exactly as in a serial call."""
+    import concurrent.futures as cf
+    chunks = [c for c in np.array_split(rows, threads * 4) if c.size]
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        return list(ex.map(fn, chunks))
+
+
 def cpu_baseline(ns, m, n, stride):
-    """The oracle, single-threaded, on every stride-th node: brute-force kNN,
-    weights, CSR rows and SpMV rows for those stencils."""
+    """The oracle (plain C, one stencil at a time, unchanged) on the host.
+    All cores: the whole bench step over every stencil of the workload
+    (brute-force kNN, weights, CSR rows, SpMV rows), rows split over host
+    threads, with kNN and weights also reported alone.  One core: every
+    stride-th stencil, as the paper times its CPU (one core).  Per order:
+    weights alone at m = 2, 4, 6 on the 10k-node square."""
     import oracle
-    from paper_2107_03632_amd.nodes import manufactured
-    rows = np.arange(0, ns.n_nodes, stride)
+    from paper_2107_03632_amd import nodes
+    model, nproc, threads = host_cpu()
+    N = ns.n_nodes
+    u, f = nodes.manufactured(ns.x, ns.y)
+
+    # all cores, every stencil
+    rows = np.arange(N)
     t0 = time.perf_counter()
-    nb = oracle.knn(ns.x, ns.y, n, queries=rows)
+    parts = _oracle_rows_parallel(lambda c: oracle.knn(ns.x, ns.y, n, queries=c), rows, threads)
+    nb = np.concatenate(parts)
     t1 = time.perf_counter()
-    full = np.zeros((ns.n_nodes, n), dtype=np.int32)
-    full[rows] = nb
-    w, st = oracle.weights(ns.x, ns.y, full, m=m, n=n, rows=rows)
+    parts = _oracle_rows_parallel(lambda c: oracle.weights(ns.x, ns.y, nb, m=m, n=n, rows=c),
+                                  rows, threads)
+    w = np.concatenate([p[0] for p in parts])
     t2 = time.perf_counter()
-    rp, col, val = oracle.csr(nb, w, n=n, is_boundary=ns.is_boundary[rows])
-    u, f = manufactured(ns.x, ns.y)
-    oracle.spmv(rp, col, val, u, f[rows])
+    rp, col, val = oracle.csr(nb, w, n=n, is_boundary=ns.is_boundary)
+    oracle.spmv(rp, col, val, u, f)
     t3 = time.perf_counter()
-    return {"value": len(rows) / (t3 - t0), "unit": "stencils/s", "cores": 1, "kind": "oracle",
-            "sample": f"{len(rows)} of {ns.n_nodes} stencils (every {stride}th node): "
-                      f"brute-force kNN {t1 - t0:.2f} s, weights {t2 - t1:.2f} s, "
-                      f"CSR+SpMV {t3 - t2:.2f} s, one thread"}
+
+    # one core, every stride-th stencil
+    srows = np.arange(0, N, stride)
+    s0 = time.perf_counter()
+    snb = oracle.knn(ns.x, ns.y, n, queries=srows)
+    s1 = time.perf_counter()
+    full = np.zeros((N, n), dtype=np.int32)
+    full[srows] = snb
+    sw, _ = oracle.weights(ns.x, ns.y, full, m=m, n=n, rows=srows)
+    s2 = time.perf_counter()
+    srp, scol, sval = oracle.csr(snb, sw, n=n, is_boundary=ns.is_boundary[srows])
+    oracle.spmv(srp, scol, sval, u, f[srows])
+    s3 = time.perf_counter()
+
+    # weights alone per order, all cores, on the 10k-node square (h = 1e-2)
+    sq = nodes.workload("square_10k_m6")
+    sqrows = np.arange(sq.n_nodes)
+    per_order = {}
+    for mo, no in ((2, 12), (4, 30), (6, 56)):
+        nbo = np.concatenate(_oracle_rows_parallel(
+            lambda c: oracle.knn(sq.x, sq.y, no, queries=c), sqrows, threads))
+        q0 = time.perf_counter()
+        _oracle_rows_parallel(lambda c: oracle.weights(sq.x, sq.y, nbo, m=mo, n=no, rows=c),
+                              sqrows, threads)
+        q1 = time.perf_counter()
+        per_order[f"m{mo}_n{no}"] = {"weights_stencils_per_s": sq.n_nodes / (q1 - q0),
+                                     "s": q1 - q0}
+
+    return {"value": N / (t3 - t0), "unit": "stencils/s", "cores": threads, "kind": "oracle",
+            "sample": f"all {N} stencils of the workload on {threads} host threads (rows "
+                      f"split into chunks): brute-force kNN {t1 - t0:.2f} s, weights "
+                      f"{t2 - t1:.2f} s, CSR+SpMV {t3 - t2:.2f} s (one thread)",
+            "host_cpu": model, "nproc": nproc,
+            "knn_only_stencils_per_s": N / (t1 - t0),
+            "weights_only_stencils_per_s": N / (t2 - t1),
+            "single_core": {
+                "value": len(srows) / (s3 - s0), "cores": 1,
+                "knn_only_stencils_per_s": len(srows) / (s1 - s0),
+                "weights_only_stencils_per_s": len(srows) / (s2 - s1),
+                "sample": f"{len(srows)} of {N} stencils (every {stride}th node): kNN "
+                          f"{s1 - s0:.2f} s, weights {s2 - s1:.2f} s, CSR+SpMV "
+                          f"{s3 - s2:.2f} s"},
+            "per_order_weights_square_10k": per_order}
 
 
 def main():
