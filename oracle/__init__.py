@@ -72,6 +72,9 @@ def _load():
                                               P, I64, I32, P, P]
             lib.oracle_weights_mixed.argtypes = [I64, P, P, P, I32, P, I32, I32, P,
                                                  P, I64, P, P, P]
+            lib.oracle_weights_mixed_form.argtypes = [I64, P, P, P, I32, P, I32, I32, P,
+                                                      P, I64, P, P, P, I32]
+            lib.oracle_gj32.argtypes = [ctypes.c_int, P, P]
             lib.oracle_adjoint.argtypes = [I64, P, P, P, I32, P, I32, I32, P,
                                            P, P, P]
             lib.oracle_adjoint_rows.argtypes = [I64, P, P, P, I32, P, I32, I32, P,
@@ -240,6 +243,18 @@ def lu32(M):
     return st, A, perm, dinv
 
 
+def gj32(M):
+    """The FP32 Gauss-Jordan inversion of the mixed form's second reading (in
+    a float32 copy of M).  Returns (status, S, perm): S = (P M)^-1 in
+    float32, P the row swaps perm[c] <-> c taken in column order."""
+    lib = _load()
+    A = np.ascontiguousarray(M, dtype=np.float32).copy()
+    K = A.shape[0]
+    perm = np.zeros(K, dtype=np.int32)
+    st = lib.oracle_gj32(K, _p(A), _p(perm))
+    return st, A, perm
+
+
 def lu_solve(LU, perm, dinv, b):
     lib = _load()
     LU = _f64(LU)
@@ -293,11 +308,17 @@ def weights_op(x, y, nbr, m: int, n: int, op: int, rows=None):
     return w, st
 
 
+MIXED_LU, MIXED_GJ = 0, 1
+
+
 def weights_mixed(x, y, nbr, m: int | None = None, n: int | None = None, order=None,
-                  n_for_m=(12, 30, 56), rows=None, k_stride: int | None = None):
-    """Mixed-precision weights: FP32 LU of the FP64-assembled system + FP64
-    refinement, FP64 fallback.  Returns (w, status, corrections); for a
-    stencil that fell back, the corrections tried before it did."""
+                  n_for_m=(12, 30, 56), rows=None, k_stride: int | None = None,
+                  form: int = MIXED_LU):
+    """Mixed-precision weights: FP32 factorisation of the FP64-assembled
+    system + FP64 refinement, FP64 fallback.  form MIXED_LU: LU factors and
+    triangular solves; MIXED_GJ: the Gauss-Jordan inverse applied as a
+    product.  Returns (w, status, corrections); for a stencil that fell back,
+    the corrections tried before it did."""
     lib = _load()
     x, y, nbr = _f64(x), _f64(y), _i32(nbr)
     _check_supports(x, y, nbr, k_stride)
@@ -309,9 +330,10 @@ def weights_mixed(x, y, nbr, m: int | None = None, n: int | None = None, order=N
     w = np.empty((nr, ks))
     st = np.empty(nr, dtype=np.int32)
     it = np.empty(nr, dtype=np.int32)
-    rc = lib.oracle_weights_mixed(N, _p(x), _p(y), _p(nbr), ks, _p(o),
-                                  -1 if m is None else m, -1 if n is None else n,
-                                  _p(_i32(n_for_m)), _p(r), nr, _p(w), _p(st), _p(it))
+    rc = lib.oracle_weights_mixed_form(N, _p(x), _p(y), _p(nbr), ks, _p(o),
+                                       -1 if m is None else m, -1 if n is None else n,
+                                       _p(_i32(n_for_m)), _p(r), nr, _p(w), _p(st), _p(it),
+                                       int(form))
     if rc != 0:
         raise ValueError(f"oracle_weights_mixed: error {rc}")
     return w, st, it

@@ -40,6 +40,13 @@
  *                     stencil to the FP64 path (status OR_FELL_BACK).  The
  *                     corrections applied, or tried before a fallback, are
  *                     reported per stencil.
+ *   oracle_gj32       in-place Gauss-Jordan inversion in FP32 with the same
+ *                     pivot rule (the pivot row scaled by 1.0f / pivot, fmaf
+ *                     eliminations of every other row).
+ *   oracle_weights_mixed_form  the mixed form with the FP32 factorisation
+ *                     given as LU factors (form 0, as oracle_weights_mixed) or
+ *                     as that Gauss-Jordan inverse, applied to each
+ *                     right-hand side as a product (form 1).
  *   oracle_csr        the discrete operator of eq. (1) as a CSR matrix, with the
  *                     Dirichlet rows of section IV replaced by identity rows.
  *   oracle_spmv       y = W u - f, a sequential row sum in CSR order.
@@ -548,6 +555,75 @@ static void lu32_solve(int K, const float *LU, const int32_t *perm, const float 
     }
 }
 
+/* In-place Gauss-Jordan inversion in single precision: for each column c,
+ * the first largest |entry| among rows c..K-1 (rows swapped physically, as
+ * oracle_lu32 does) is the pivot; the pivot row is scaled by the pivot's
+ * reciprocal (1.0f / pivot) and its multiple f = M[r][c] is removed from
+ * every other row r (fmaf(-f, pivot row, row)); column c of row r then holds
+ * -f / pivot (as -f * reciprocal) and the pivot's place its reciprocal.  On
+ * success M holds the inverse of the row-swapped matrix, (P M)^-1, and
+ * perm[c] is the row swapped with row c at column c. */
+int oracle_gj32(int K, float *M, int32_t *perm)
+{
+    for (int c = 0; c < K; ++c) {
+        int p = c;
+        float best = fabsf(M[c * K + c]);
+        for (int r = c + 1; r < K; ++r) {
+            float v = fabsf(M[r * K + c]);
+            if (v > best) {
+                best = v;
+                p = r;
+            }
+        }
+        if (!isfinite(best))
+            return OR_NONFINITE;
+        if (best == 0.0f)
+            return OR_SINGULAR;
+        perm[c] = p;
+        if (p != c)
+            for (int q = 0; q < K; ++q) {
+                float t = M[c * K + q];
+                M[c * K + q] = M[p * K + q];
+                M[p * K + q] = t;
+            }
+        float inv = 1.0f / M[c * K + c];
+        for (int q = 0; q < K; ++q)
+            if (q != c)
+                M[c * K + q] = M[c * K + q] * inv;
+        M[c * K + c] = inv;
+        for (int r = 0; r < K; ++r) {
+            if (r == c)
+                continue;
+            float f = M[r * K + c];
+            for (int q = 0; q < K; ++q)
+                if (q != c)
+                    M[r * K + q] = fmaf(-f, M[c * K + q], M[r * K + q]);
+            M[r * K + c] = -f * inv;
+        }
+    }
+    return OR_OK;
+}
+
+/* b <- (P M)^-1 P b: the row swaps applied to b, then the stored inverse
+ * times it (each row a fused sum over the columns in order). */
+static void gj32_apply(int K, const float *S, const int32_t *perm, float *b, float *tmp)
+{
+    for (int c = 0; c < K; ++c) {
+        int p = perm[c];
+        float t = b[c];
+        b[c] = b[p];
+        b[p] = t;
+    }
+    for (int r = 0; r < K; ++r) {
+        float acc = 0.0f;
+        for (int q = 0; q < K; ++q)
+            acc = fmaf(S[r * K + q], b[q], acc);
+        tmp[r] = acc;
+    }
+    for (int r = 0; r < K; ++r)
+        b[r] = tmp[r];
+}
+
 #define MIXED_MAX_CORRECTIONS 10
 #define MIXED_TOL 1e-12
 
@@ -558,7 +634,7 @@ static int stencil_solve_mixed(int64_t n_nodes, const double *x, const double *y
                                int64_t i, const int32_t *idx, int n, int m,
                                double *M, double *z, float *M32, float *d32,
                                int32_t *perm, float *dinv32, double *dinv, double *rhs,
-                               double *s, int *iters)
+                               double *s, int *iters, int form)
 {
     const int K = n + n_monomials(m);
     *iters = 0;
@@ -567,11 +643,16 @@ static int stencil_solve_mixed(int64_t n_nodes, const double *x, const double *y
         return st;
     for (int e = 0; e < K * K; ++e)
         M32[e] = (float)M[e];
-    int ok = oracle_lu32(K, M32, perm, dinv32) == OR_OK;
+    /* form 0: LU factors and triangular solves; form 1: the Gauss-Jordan
+     * inverse applied to each right-hand side (dinv32 is its scratch row) */
+    int ok = (form == 0 ? oracle_lu32(K, M32, perm, dinv32) : oracle_gj32(K, M32, perm)) == OR_OK;
     if (ok) {
         for (int q = 0; q < K; ++q)
             d32[q] = (float)rhs[q];
-        lu32_solve(K, M32, perm, dinv32, d32);
+        if (form == 0)
+            lu32_solve(K, M32, perm, dinv32, d32);
+        else
+            gj32_apply(K, M32, perm, d32, dinv32);
         double prev = 0.0;
         for (int q = 0; q < K; ++q) {
             z[q] = (double)d32[q];
@@ -586,7 +667,10 @@ static int stencil_solve_mixed(int64_t n_nodes, const double *x, const double *y
                     acc = fma(-M[r * K + c], z[c], acc);
                 d32[r] = (float)acc;
             }
-            lu32_solve(K, M32, perm, dinv32, d32);
+            if (form == 0)
+                lu32_solve(K, M32, perm, dinv32, d32);
+            else
+                gj32_apply(K, M32, perm, d32, dinv32);
             double dn = 0.0, zn = 0.0;
             int bad = 0;
             for (int q = 0; q < K; ++q) {
@@ -621,13 +705,16 @@ static int stencil_solve_mixed(int64_t n_nodes, const double *x, const double *y
 }
 
 /* As oracle_weights, mixed precision.  iters (may be NULL) receives the
- * number of FP64 refinement corrections per listed node. */
-int oracle_weights_mixed(int64_t n_nodes, const double *x, const double *y,
-                         const int32_t *nbr, int32_t k_stride,
-                         const int8_t *order, int32_t m_uniform, int32_t n_uniform,
-                         const int32_t *n_for_m, const int64_t *rows, int64_t n_rows,
-                         double *w, int32_t *status, int32_t *iters)
+ * number of FP64 refinement corrections per listed node.  form: 0 solves
+ * with FP32 LU factors, 1 applies the FP32 Gauss-Jordan inverse. */
+int oracle_weights_mixed_form(int64_t n_nodes, const double *x, const double *y,
+                              const int32_t *nbr, int32_t k_stride,
+                              const int8_t *order, int32_t m_uniform, int32_t n_uniform,
+                              const int32_t *n_for_m, const int64_t *rows, int64_t n_rows,
+                              double *w, int32_t *status, int32_t *iters, int32_t form)
 {
+    if (form != 0 && form != 1)
+        return OR_EARG;
     int kmax = 0;
     if (order) {
         for (int q = 0; q < 3; ++q) {
@@ -666,7 +753,7 @@ int oracle_weights_mixed(int64_t n_nodes, const double *x, const double *y,
         }
         double s = 0.0;
         int st = stencil_solve_mixed(n_nodes, x, y, i, nbr + i * (int64_t)k_stride, n, m,
-                                     M, z, M32, d32, perm, dinv32, dinv, rhs, &s, &it);
+                                     M, z, M32, d32, perm, dinv32, dinv, rhs, &s, &it, form);
         double *wr = w + t * (int64_t)k_stride;
         if (st == OR_OK || st == OR_FELL_BACK) {
             double s2 = s * s;
@@ -685,6 +772,16 @@ int oracle_weights_mixed(int64_t n_nodes, const double *x, const double *y,
     }
     free(M); free(M32); free(z); free(d32); free(perm);
     return rc;
+}
+
+int oracle_weights_mixed(int64_t n_nodes, const double *x, const double *y,
+                         const int32_t *nbr, int32_t k_stride,
+                         const int8_t *order, int32_t m_uniform, int32_t n_uniform,
+                         const int32_t *n_for_m, const int64_t *rows, int64_t n_rows,
+                         double *w, int32_t *status, int32_t *iters)
+{
+    return oracle_weights_mixed_form(n_nodes, x, y, nbr, k_stride, order, m_uniform, n_uniform,
+                                     n_for_m, rows, n_rows, w, status, iters, 0);
 }
 
 /* ---------------------------------------------------------------------- */

@@ -159,3 +159,110 @@ def test_mixed_fallback_rule_and_cap(i, k, lo, hi, tries):
     assert stm[0] == oracle.FELL_BACK
     assert it[0] == tries
     assert np.array_equal(wm, w64)
+
+
+# ---- the second reading: the FP32 factorisation as a Gauss-Jordan inverse ----
+
+def test_gj32_inverts_the_fp32_matrix():
+    # S = (P M32)^-1 to FP32 accuracy, S (P M32) = I, with M32 = (float) M
+    ns = nodes.unit_square(12, seed=3)
+    nbr = oracle.knn(ns.x, ns.y, 30)
+    st, M, rhs, s = oracle.assemble(ns.x, ns.y, 77, nbr[77], 4)
+    st, S, perm = oracle.gj32(M)
+    assert st == oracle.OK
+    K = M.shape[0]
+    A = M.astype(np.float32).astype(np.float64)
+    PA = A.copy()
+    for c in range(K):
+        p = perm[c]
+        PA[[c, p]] = PA[[p, c]]
+    S = S.astype(np.float64)
+    cond = np.linalg.cond(PA, np.inf)
+    eps = np.finfo(np.float32).eps
+    assert np.abs(S @ PA - np.eye(K)).max() <= K * cond * eps
+    inv = np.linalg.inv(PA)
+    assert np.abs(S - inv).max() <= K * cond * eps * np.abs(inv).max()
+    # the pivots are those of partial pivoting: the same rows as the LU
+    # factorisation picks on this well-conditioned system
+    st2, LU, perm_lu, _ = oracle.lu32(M)
+    assert np.array_equal(perm, perm_lu)
+
+
+def test_gj32_small_cases_by_hand():
+    # [[1, 2, 0], [2, 1, 1], [0, 1, 2]]: column 0 pivots on row 1 (|2| > |1|),
+    # then the inverse of the swapped matrix is (P M)^-1 = M^-1 P^T, det M = -7
+    M = np.array([[1.0, 2.0, 0.0], [2.0, 1.0, 1.0], [0.0, 1.0, 2.0]])
+    st, S, perm = oracle.gj32(M)
+    assert st == oracle.OK and perm[0] == 1
+    P = np.eye(3)
+    P[[0, 1]] = P[[1, 0]]
+    exact = np.array([[1.0, -4.0, 2.0], [-4.0, 2.0, -1.0], [2.0, -1.0, -3.0]]) / -7.0
+    assert np.allclose(S.astype(np.float64), exact @ P.T, rtol=0, atol=1e-6)
+    # a tie in |entry|: the first of the equal rows is the pivot (no swap)
+    st, S, perm = oracle.gj32(np.array([[1.0, 1.0], [-1.0, 1.0]]))
+    assert st == oracle.OK and perm[0] == 0
+    assert np.allclose(S, np.array([[0.5, -0.5], [0.5, 0.5]]), rtol=0, atol=0)
+    # a zero column: singular
+    st, S, perm = oracle.gj32(np.array([[0.0, 1.0], [0.0, 2.0]]))
+    assert st == oracle.SINGULAR
+
+
+@pytest.mark.parametrize("m", [2, 4, 6])
+def test_mixed_gj_matches_fp64_and_exact_solution(m):
+    ns = nodes.unit_disk(2000, 160, seed=31)
+    n = NFM[m]
+    nbr = oracle.knn(ns.x, ns.y, n)
+    w64, st64 = oracle.weights(ns.x, ns.y, nbr, m=m, n=n)
+    wm, stm, it = oracle.weights_mixed(ns.x, ns.y, nbr, m=m, n=n, form=oracle.MIXED_GJ)
+    assert np.all((stm == 0) | (stm == oracle.FELL_BACK))
+    e = np.abs(wm - w64).max(axis=1) / np.abs(w64).max(axis=1)
+    assert e.max() <= 1e-9
+    assert np.all(it[stm == 0] >= 1) and np.all(it <= 10)
+    for i in [0, 411, ns.n_nodes - 3]:
+        st, M, rhs, s = oracle.assemble(ns.x, ns.y, i, nbr[i], m)
+        with mpmath.workdps(50):
+            zm = mpmath.lu_solve(mpmath.matrix(M.tolist()), mpmath.matrix(rhs.tolist()))
+            w_ex = np.array([float(zm[k] / (mpmath.mpf(s) ** 2)) for k in range(n)])
+        assert np.abs(wm[i, :n] - w_ex).max() / np.abs(w_ex).max() <= 1e-9
+
+
+def _model_ratios_gj(M, b, steps=10):
+    # the oracle's FP32 inverse S = (P M32)^-1, iterated in FP64:
+    # z0 = S P b, z += S P (b - M z)
+    st, S, perm = oracle.gj32(M)
+    assert st == oracle.OK
+    K = M.shape[0]
+    P = np.eye(K)
+    for c in range(K):
+        p = perm[c]
+        P[[c, p]] = P[[p, c]]
+    F = S.astype(np.float64) @ P
+    z = F @ b
+    prev = np.abs(z).max()
+    out = []
+    for _ in range(steps):
+        d = F @ (b - M @ z)
+        z = z + d
+        dn = np.abs(d).max()
+        out.append(dn / prev)
+        prev = dn
+    return np.array(out)
+
+
+@pytest.mark.parametrize("i,k,lo,hi,tries", [
+    (90, 4, 0.53, 0.58, 1),    # corrections shrink by ~0.57: above one half at once
+    (90, 7, 2.2, 2.5, 1),      # they grow
+    (90, 12, 0.42, 0.46, 10),  # below one half: refined until the cap
+    (90, 1, 0.22, 0.24, 10),   # ~0.23 per step: too slow for 1e-12 in 10
+])
+def test_mixed_gj_fallback_rule_and_cap(i, k, lo, hi, tries):
+    x, y, nbr = _perturbed(i, k)
+    st, M, rhs, s = oracle.assemble(x, y, i, nbr[i], 2)
+    rat = _model_ratios_gj(M, rhs)
+    assert np.all((rat >= lo) & (rat <= hi)), rat
+    wm, stm, it = oracle.weights_mixed(x, y, nbr, m=2, n=12, rows=[i], form=oracle.MIXED_GJ)
+    w64, st64 = oracle.weights(x, y, nbr, m=2, n=12, rows=[i])
+    assert st64[0] == oracle.OK
+    assert stm[0] == oracle.FELL_BACK
+    assert it[0] == tries
+    assert np.array_equal(wm, w64)
