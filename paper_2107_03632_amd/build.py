@@ -28,6 +28,15 @@ FLAGS = [
 ]
 
 
+# per-source additions: the mixed-precision kernels keep their FP32 matrix-core
+# accumulators in ordinary VGPRs (with accumulation registers the compiler
+# copies the tiles back and forth and needs twice the registers)
+EXTRA_FLAGS = {
+    "weights_mx_k45.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+    "weights_mx_k84.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+}
+
+
 def sources() -> list[str]:
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
@@ -43,7 +52,8 @@ def _compile(src: str, force: bool) -> str:
             os.path.getmtime(obj) >= max(os.path.getmtime(d) for d in _deps(src)):
         return obj
     tmp = obj + ".tmp"
-    subprocess.run([HIPCC, *FLAGS, "-c", src, "-o", tmp], check=True)
+    extra = EXTRA_FLAGS.get(os.path.basename(src), [])
+    subprocess.run([HIPCC, *FLAGS, *extra, "-c", src, "-o", tmp], check=True)
     os.replace(tmp, obj)
     return obj
 

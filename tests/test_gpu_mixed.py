@@ -1,11 +1,21 @@
 """GPU mixed-precision weights (FP32 factorisation + FP64 refinement,
 FP64 fallback) against the oracle's mixed form and the FP64 oracle.
 
-The GPU performs the same operations in the same precisions as the oracle's
-mixed form (FP32 factorisation and solves with fused updates, FP64 fused
-residuals), so weights, statuses (including fall-backs) and correction counts
-are compared exactly; against the FP64 oracle the bar is 1e-9 relative per
-stencil.
+m = 2 (K = 18): the GPU performs the same operations in the same precisions
+as the oracle's mixed form (FP32 LU and triangular solves with fused
+updates, FP64 fused residuals), so weights, statuses (including fall-backs)
+and correction counts are compared exactly.
+
+m = 4, 6 (K = 45, 84): the GPU inverts the FP32 system by blocked
+Gauss-Jordan on the matrix cores and applies the inverse to each residual;
+it is compared with the oracle's Gauss-Jordan form (oracle.MIXED_GJ), whose
+FP32 inverse it reproduces bit for bit (the rank-4 matrix-core updates round
+as the sequential fused eliminations).  The products with the inverse and
+the FP64 residuals sum in another order on the GPU, so a correction's size
+can differ in its last bits: statuses must agree, the correction counts of
+converged stencils agree for most stencils (all at m = 4, about 85% at
+m = 6) and never differ by more than one, and the weights agree to 1e-11
+relative (1e-9 against the FP64 oracle, the target).
 """
 
 import sys
@@ -20,6 +30,8 @@ from paper_2107_03632_amd import nodes
 
 pytestmark = pytest.mark.gpu
 NFM = {2: 12, 4: 30, 6: 56}
+# the oracle's mixed form that each system size's GPU kernel follows
+FORM = {2: oracle.MIXED_LU, 4: oracle.MIXED_GJ, 6: oracle.MIXED_GJ}
 
 
 def say(*a):
@@ -38,6 +50,36 @@ def host(t):
 
 def rel_err(a, b, n):
     return np.abs(a[:, :n] - b[:, :n]).max(axis=1) / np.abs(b[:, :n]).max(axis=1)
+
+
+def check_mixed(w, st, it, w_mx, st_mx, it_mx, w64, n, exact, what=""):
+    """Mixed results against the mixed oracle (exactly when the GPU follows
+    the same operations, else to the refinement's accuracy) and the FP64
+    oracle (1e-9)."""
+    assert np.array_equal(st, st_mx), f"{what}: statuses differ"
+    ok = ~np.isnan(w_mx[:, :n]).any(axis=1)
+    if exact:
+        assert np.array_equal(it, it_mx), f"{what}: correction counts differ"
+        assert rel_err(w[ok], w_mx[ok], n).max() <= 1e-12
+    else:
+        # converged stencils: the same number of corrections, or one more or
+        # one fewer where the last correction's size lies at the stopping
+        # threshold (the products' summation order moves it by a few ulps);
+        # a stencil that falls back reports the corrections it tried before
+        # diverging, which such differences can move further
+        conv = st_mx == 0
+        d = np.abs(it.astype(np.int64) - it_mx)[conv]
+        if d.size:
+            say(f"  {what}: corrections equal {np.mean(d == 0):.4f}, max diff {d.max()}")
+            assert d.max() <= 1 and np.mean(d == 0) >= 0.75, f"{what}: correction counts"
+        e_mx = rel_err(w[ok], w_mx[ok], n)
+        say(f"  {what}: vs mixed oracle {e_mx.max():.3e}")
+        assert e_mx.max() <= 1e-11
+    assert np.array_equal(np.isnan(w[:, :n]), np.isnan(w_mx[:, :n]))
+    ok64 = ~np.isnan(w64[:, :n]).any(axis=1)
+    e64 = rel_err(w[ok64], w64[ok64], n)
+    say(f"  {what}: vs FP64 oracle {e64.max():.3e}")
+    assert e64.max() <= 1e-9
 
 
 def gpu_mixed(x, y, nbr, **kw):
@@ -59,18 +101,12 @@ def test_mixed_matches_mixed_oracle_and_fp64(m):
     ns = nodes.unit_disk(3000, 200, seed=21)
     n = NFM[m]
     nbr = oracle.knn(ns.x, ns.y, n)
-    w_mx, st_mx, it_mx = oracle.weights_mixed(ns.x, ns.y, nbr, m=m, n=n)
+    w_mx, st_mx, it_mx = oracle.weights_mixed(ns.x, ns.y, nbr, m=m, n=n, form=FORM[m])
     w64, st64 = oracle.weights(ns.x, ns.y, nbr, m=m, n=n)
     w, st, it = gpu_mixed(ns.x, ns.y, nbr, m=m, n=n)
-    say("mixed", m, "statuses", np.bincount(st), "mean corrections", it[st == 0].mean())
-    assert np.array_equal(st, st_mx)
-    assert np.array_equal(it, it_mx)
-    e_mx = rel_err(w, w_mx, n)
-    say(f"  vs mixed oracle {e_mx.max():.3e}, bit-exact {np.mean(e_mx == 0):.4f}")
-    assert e_mx.max() <= 1e-12
-    e64 = rel_err(w, w64, n)
-    say(f"  vs FP64 oracle {e64.max():.3e}")
-    assert e64.max() <= 1e-9
+    say("mixed", m, "statuses", np.bincount(st), "mean corrections", it[st == 0].mean(),
+        "oracle", it_mx[st_mx == 0].mean())
+    check_mixed(w, st, it, w_mx, st_mx, it_mx, w64, n, exact=m == 2, what=f"m={m}")
 
 
 def test_mixed_fallback_and_failures():
@@ -105,23 +141,29 @@ def test_mixed_full_size_square_sampled():
     assert np.array_equal(nbr[rows], oracle.knn(ns.x, ns.y, 56, queries=rows))
     full = np.zeros_like(nbr)
     full[rows] = nbr[rows]
-    w_mx, st_mx, it_mx = oracle.weights_mixed(ns.x, ns.y, full, m=6, n=56, rows=rows)
-    assert np.array_equal(st[rows], st_mx) and np.array_equal(it[rows], it_mx)
-    assert rel_err(w[rows], w_mx, 56).max() <= 1e-12
+    w_mx, st_mx, it_mx = oracle.weights_mixed(ns.x, ns.y, full, m=6, n=56, rows=rows,
+                                              form=oracle.MIXED_GJ)
     w64, _ = oracle.weights(ns.x, ns.y, full, m=6, n=56, rows=rows)
-    assert rel_err(w[rows], w64, 56).max() <= 1e-9
+    check_mixed(w[rows], st[rows], it[rows], w_mx, st_mx, it_mx, w64, 56, exact=False,
+                what="10k m=6")
     say("  statuses", np.bincount(st), "mean corrections", it[st == 0].mean())
 
 
 def test_mixed_order_batch():
     ns = nodes.cell_centred_square(40, seed=3, order_seed=33)
     nbr = oracle.knn(ns.x, ns.y, 56)
-    w_mx, st_mx, it_mx = oracle.weights_mixed(ns.x, ns.y, nbr, order=ns.order)
     w, st, it = gpu_mixed(ns.x, ns.y, nbr, order=dev(ns.order))
-    assert np.array_equal(st, st_mx) and np.array_equal(it, it_mx)
+    # per order, the oracle's form that the GPU kernel of that system size runs
+    w_mx, st_mx, it_mx = oracle.weights_mixed(ns.x, ns.y, nbr, order=ns.order)
+    w_gj, st_gj, it_gj = oracle.weights_mixed(ns.x, ns.y, nbr, order=ns.order,
+                                              form=oracle.MIXED_GJ)
+    gj = ns.order != 2
+    w_mx[gj], st_mx[gj], it_mx[gj] = w_gj[gj], st_gj[gj], it_gj[gj]
+    w64, _ = oracle.weights(ns.x, ns.y, nbr, order=ns.order)
     for m in (2, 4, 6):
         sel = ns.order == m
-        assert rel_err(w[sel], w_mx[sel], NFM[m]).max() <= 1e-12
+        check_mixed(w[sel], st[sel], it[sel], w_mx[sel], st_mx[sel], it_mx[sel], w64[sel],
+                    NFM[m], exact=m == 2, what=f"batch m={m}")
 
 
 @pytest.mark.parametrize("m", [2, 4, 6])
@@ -144,11 +186,11 @@ def test_mixed_1m_square_sampled(m):
                                      [0, 999, ns.n_nodes - 1], np.arange(ns.n_nodes - 40, ns.n_nodes)]))
     full = np.zeros_like(nbr)
     full[rows] = nbr[rows]
-    w_mx, st_mx, it_mx = oracle.weights_mixed(ns.x, ns.y, full, m=m, n=n, rows=rows)
-    assert np.array_equal(st[rows], st_mx) and np.array_equal(it[rows], it_mx)
-    assert rel_err(w[rows], w_mx, n).max() <= 1e-12
+    w_mx, st_mx, it_mx = oracle.weights_mixed(ns.x, ns.y, full, m=m, n=n, rows=rows,
+                                              form=FORM[m])
     w64, _ = oracle.weights(ns.x, ns.y, full, m=m, n=n, rows=rows)
-    assert rel_err(w[rows], w64, n).max() <= 1e-9
+    check_mixed(w[rows], st[rows], it[rows], w_mx, st_mx, it_mx, w64, n, exact=m == 2,
+                what=f"1M m={m}")
     say("  statuses", np.bincount(st), "mean corrections", it[st == 0].mean())
 
 
@@ -168,3 +210,29 @@ def test_mixed_fallback_rule_and_cap(i, k, tries):
     assert st_mx[i] == oracle.FELL_BACK and it_mx[i] == tries
     assert np.array_equal(st, st_mx) and np.array_equal(it, it_mx)
     assert rel_err(w, w_mx, 12).max() <= 1e-12
+
+
+@pytest.mark.parametrize("m", [4, 6])
+def test_mixed_blocked_fallback_and_failures(m):
+    """The matrix-core mixed kernels: an ill-conditioned stencil (two support
+    nodes 1e-6 h apart) falls back to FP64 on both sides and gets the FP64
+    weights; a duplicate node and a bad index fail without fallback; the
+    rest refine."""
+    n = NFM[m]
+    ns = nodes.unit_square(14, seed=5)
+    nbr = oracle.knn(ns.x, ns.y, n)
+    x, y = ns.x.copy(), ns.y.copy()
+    i = 100
+    x[nbr[i, 6]] = x[nbr[i, 5]] + 1e-6 / 14
+    y[nbr[i, 6]] = y[nbr[i, 5]]
+    nb = nbr.copy()
+    nb[20, 5] = nb[20, 4]
+    nb[21, 2] = 10 ** 6
+    w_mx, st_mx, it_mx = oracle.weights_mixed(x, y, nb, m=m, n=n, form=oracle.MIXED_GJ)
+    w64, _ = oracle.weights(x, y, nb, m=m, n=n)
+    w, st, it = gpu_mixed(x, y, nb, m=m, n=n)
+    say(f"m={m}: oracle statuses {np.bincount(st_mx)}, gpu {np.bincount(st)}")
+    assert st_mx[20] == oracle.DUPLICATE and st_mx[21] == oracle.BAD_INDEX
+    assert st_mx[i] == oracle.FELL_BACK
+    check_mixed(w, st, it, w_mx, st_mx, it_mx, w64, n, exact=False, what=f"fallback m={m}")
+    assert np.array_equal(w[i, :n], w64[i, :n])  # the FP64 kernel's weights, bit for bit
