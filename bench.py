@@ -225,6 +225,9 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain device copy of known size first (for --pmc scaling)")
     ap.add_argument("--cpu-stride", type=int, default=7)
+    ap.add_argument("--profile-case", default=None,
+                    help="only run one weights launch pattern under a profiler: "
+                         "{fp64,mixed}_m{2,4,6} on the 1M-node square (prints its timing)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -240,6 +243,10 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+
+    if args.profile_case:
+        profile_case(torch, rb, nodes, dev, args.profile_case, args.warmup, args.steps)
+        return
 
     if args.copy_calibration:
         nbytes = 1 << 30
@@ -335,6 +342,7 @@ def main():
         out["per_order_1M_square"] = extras_per_order(torch, rb, nodes, dev, stream)
         out["adjoint_annulus_200k_m4"] = extras_adjoint(torch, rb, nodes, dev, stream)
         out["time_loop_unit_disk"] = extras_time_loop(torch, rb, nodes, dev, stream)
+        out["time_loop_cache_sweep"] = extras_time_loop_sweep(torch, rb, nodes, dev, stream)
         out["derivative_weights_unit_disk"] = extras_ops(torch, rb, stream, X, Y, ns, m, n)
         out["laplacian_3d_cube_1m"] = extras_3d(torch, rb, nodes, dev, stream)
 
@@ -356,6 +364,41 @@ def timed(torch, stream, fn, reps=3):
         e1.synchronize()
         ts.append(e0.elapsed_time(e1))
     return float(np.median(ts))
+
+
+def profile_case(torch, rb, nodes, dev, case, warmup, steps):
+    """One weights launch pattern on the 1M-node square, for kernel traces
+    and counters: `warmup` untimed calls, then `steps` timed ones."""
+    prec, mpart = case.split("_")
+    m = int(mpart[1:])
+    n = {2: 12, 4: 30, 6: 56}[m]
+    if prec not in ("fp64", "mixed") or m not in (2, 4, 6):
+        raise SystemExit(f"unknown profile case {case}")
+    ns = nodes.workload("square_1m_m6")
+    X = torch.as_tensor(ns.x, device=dev)
+    Y = torch.as_tensor(ns.y, device=dev)
+    nb = rb.rbffd_knn(X, Y, n)
+    out = torch.empty((ns.n_nodes, n), dtype=torch.float64, device=dev)
+    st = torch.empty(ns.n_nodes, dtype=torch.int32, device=dev)
+    pr = rb.MIXED if prec == "mixed" else rb.FP64
+    stream = torch.cuda.current_stream(dev)
+
+    def run():
+        rb.rbffd_weights(X, Y, nb, m=m, n=n, precision=pr, out=out, status=st)
+    for _ in range(max(warmup, 0)):
+        run()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(steps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        run()
+        e1.record(stream)
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    print(json.dumps({"profile_case": case, "n_nodes": ns.n_nodes, "ms": ts,
+                      "statuses": np.bincount(st.cpu().numpy()).tolist()}), flush=True)
 
 
 def extras_per_order(torch, rb, nodes, dev, stream):
@@ -387,6 +430,7 @@ def extras_per_order(torch, rb, nodes, dev, stream):
                      "failed": int((st64 != 0).sum().item())},
             "mixed": {"stencils_per_s": N / (ms_mx * 1e-3), "ms": ms_mx,
                       "speedup_vs_fp64": ms / ms_mx,
+                      "target_met": bool(ms / ms_mx > 1.0 and err <= 1e-9),
                       "mean_corrections": it[ok].double().mean().item() if ok.any() else None,
                       "fell_back": int((stmx == rb.FELL_BACK_FP64).sum().item()),
                       "failed": int(((stmx != 0) & (stmx != rb.FELL_BACK_FP64)).sum().item()),
@@ -448,11 +492,35 @@ def extras_solve(torch, rb, nodes, dev, X, Y, B, U, F, ns, m, n, rtol=1e-10):
     ms = 1e3 * (time.perf_counter() - t0)
     N, nnz = ns.n_nodes, int(col.numel())
     per_it = 2 * (20 * nnz + 16 * N) + 14 * 8 * N
-    return {"method": "BiCGSTAB, no preconditioner", "rtol": rtol, "iterations": it,
-            "info": info, "relres_true": rr, "ms": ms, "ms_per_iteration": ms / max(it, 1),
-            "model_bytes_per_iteration": per_it,
-            "model_gb_per_s": per_it * it / (ms * 1e-3) / 1e9,
-            "max_err_vs_exact": (x - U).abs().max().item(), "nnz": nnz}
+    res = {"method": "BiCGSTAB, no preconditioner", "rtol": rtol, "iterations": it,
+           "info": info, "relres_true": rr, "ms": ms, "ms_per_iteration": ms / max(it, 1),
+           "model_bytes_per_iteration": per_it,
+           "model_gb_per_s": per_it * it / (ms * 1e-3) / 1e9,
+           "max_err_vs_exact": (x - U).abs().max().item(), "nnz": nnz}
+    # the host-synchronisation-free form: eager, then as one captured graph
+    # (max_iter iterations enqueued; those after convergence return at once),
+    # and with the Jacobi preconditioner
+    max_iter = it + 16
+    xa = torch.zeros_like(b)
+    ws = None
+    res_t = torch.empty(16, dtype=torch.int8, device=dev)
+    for name, pre in (("none", rb.PRECOND_NONE), ("jacobi", rb.PRECOND_JACOBI)):
+        mi = max_iter if pre == rb.PRECOND_NONE else 2 * max_iter
+
+        def run():
+            xa.zero_()
+            rb.rbffd_solve_async(rp, col, val, b, xa, rtol=rtol, max_iter=mi, precond=pre,
+                                 result=res_t, workspace=ws)
+        _, _, ws = rb.rbffd_solve_async(rp, col, val, b, xa, rtol=rtol, max_iter=mi,
+                                        precond=pre, result=res_t, workspace=ws)
+        ms_eager = timed(torch, torch.cuda.current_stream(dev), run, reps=2)
+        ms_graph = graph_timed(torch, run, reps=2)
+        ia, ra, fa = rb.solve_result(res_t)
+        res[f"async_{name}"] = {"iterations": ia, "info": fa, "relres_true": ra,
+                                "max_iter_enqueued": mi, "ms_eager": ms_eager,
+                                "ms_graph_replay": ms_graph,
+                                "max_err_vs_exact": (xa - U).abs().max().item()}
+    return res
 
 
 def extras_ops(torch, rb, stream, X, Y, ns, m, n):
@@ -562,6 +630,44 @@ def extras_time_loop(torch, rb, nodes, dev, stream, steps=200, dt=1e-6):
                                                                  workspace=ws))
             row["graph_100_steps_ms_per_step"] = gms / 100
         res.append(row)
+    return res
+
+
+def extras_time_loop_sweep(torch, rb, nodes, dev, stream, dt=1e-6):
+    """The cache-regime study of the paper's Table 1, redone for the MI355X:
+    microseconds per explicit step and GB/s on the paper's per-node data
+    model 8 (4 + n) + 4 (1 + n) bytes, for unit disks of ~1e3 ... 4e6 nodes
+    at n = 12, 15, 20, 30, 45, 60 (weights of order m = 2 on each support).
+    The MI355X has 4 MB of L2 per XCD and 256 MB of Infinity Cache; the
+    model puts those capacities at N = 4e6 / (8 (4 + n) + 4 (1 + n)) and
+    256e6 / (...) nodes."""
+    ns_list = (1000, 3000, 10_000, 30_000, 100_000, 300_000, 1_000_000, 4_000_000)
+    res = []
+    for n_target in ns_list:
+        ns = nodes.unit_disk(n_target, max(100, int(3 * math.sqrt(n_target))), seed=2)
+        X = torch.as_tensor(ns.x, device=dev)
+        Y = torch.as_tensor(ns.y, device=dev)
+        u_exact, F = nodes.manufactured(ns.x, ns.y)
+        f = torch.as_tensor(-F, device=dev)
+        B = torch.as_tensor(ns.is_boundary, device=dev)
+        u = torch.as_tensor(np.where(ns.is_boundary != 0, u_exact, 0.0), device=dev)
+        work = torch.empty_like(u)
+        nbr60 = rb.rbffd_knn(X, Y, 60)
+        steps = 200 if ns.n_nodes <= 100_000 else 50
+        for n in (12, 15, 20, 30, 45, 60):
+            nbr = nbr60[:, :n].contiguous()
+            w, st, _ = rb.rbffd_weights(X, Y, nbr, m=2, n=n)
+            ws = torch.empty(ns.n_nodes * n * 12 + 1024, dtype=torch.uint8, device=dev)
+            ms = timed(torch, stream, lambda: rb.rbffd_time_steps(
+                nbr, w, n, f, u, dt, steps, is_boundary=B, u_work=work, workspace=ws))
+            per = ms / steps
+            nbytes = ns.n_nodes * (8 * (4 + n) + 4 * (1 + n))
+            res.append({"n_nodes": ns.n_nodes, "n": n, "steps": steps,
+                        "us_per_step": per * 1e3, "model_bytes": nbytes,
+                        "gb_per_s": nbytes / (per * 1e-3) / 1e9,
+                        "node_updates_per_s": ns.n_nodes / (per * 1e-3)})
+            del w, ws
+        del nbr60
     return res
 
 

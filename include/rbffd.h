@@ -345,7 +345,7 @@ int rbffd_spmv(int64_t n_rows, const int64_t *row_ptr, const int32_t *col,
  * info = RBFFD_SOLVE_*.  Unlike the other calls this one synchronizes the
  * stream (it reads the convergence flag every 8 iterations), so it cannot
  * be captured into a graph.  workspace: rbffd_solve_workspace_size bytes
- * (six vectors and the reduction partials).
+ * (six vectors, the Jacobi scaling and the reduction partials).
  * Errors: RBFFD_ERR_ARG for null pointers, n_rows < 1, rtol < 0 or NaN,
  * max_iter < 0; RBFFD_ERR_WORKSPACE for a short workspace.  A column
  * outside [0, n_rows) makes its row NaN and the solve ends with
@@ -356,6 +356,34 @@ int rbffd_solve(int64_t n_rows, const int64_t *row_ptr, const int32_t *col, cons
                 const double *b, double *x, double rtol, int32_t max_iter,
                 int32_t *iters /* host */, double *relres /* host */, int32_t *info /* host */,
                 void *workspace, size_t workspace_bytes, void *stream);
+
+/* --------------------------------------------------------------------------
+ * The same solve with an optional preconditioner and no host
+ * synchronisation, so that it can be captured into a graph.
+ * precond: RBFFD_PRECOND_NONE (the iteration of rbffd_solve, the same bits)
+ * or RBFFD_PRECOND_JACOBI: right preconditioning by the diagonal of W
+ * (W D^-1 y = b, x = D^-1 y; the residual and the stopping test stay those
+ * of W x = b).  The interior rows of the assembled operator scale as 1/h^2
+ * and its Dirichlet rows as 1; the scaling puts every row on the unit
+ * diagonal.  A row without a non-zero finite diagonal entry is left
+ * unscaled.
+ * All max_iter iterations are enqueued (five launches each); once the solve
+ * has ended every later launch returns at once.  result (device) receives
+ * {iters, info, relres} as rbffd_solve returns them, after the last launch;
+ * read it after synchronising the stream.  Same workspace and errors as
+ * rbffd_solve, and RBFFD_ERR_ARG for an unknown precond.
+ * ------------------------------------------------------------------------ */
+#define RBFFD_PRECOND_NONE 0
+#define RBFFD_PRECOND_JACOBI 1
+typedef struct {
+    int32_t iters;
+    int32_t info;
+    double relres;
+} rbffd_solve_result;
+int rbffd_solve_async(int64_t n_rows, const int64_t *row_ptr, const int32_t *col,
+                      const double *val, const double *b, double *x, double rtol,
+                      int32_t max_iter, int32_t precond, rbffd_solve_result *result,
+                      void *workspace, size_t workspace_bytes, void *stream);
 
 #ifdef __cplusplus
 }

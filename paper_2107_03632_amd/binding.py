@@ -70,6 +70,8 @@ def _load():
             "rbffd_solve": ([I64, P, P, P, P, P, ctypes.c_double, I32,
                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
                              ctypes.POINTER(ctypes.c_int32), P, SZ, P], ctypes.c_int),
+            "rbffd_solve_async": ([I64, P, P, P, P, P, ctypes.c_double, I32, I32, P, P, SZ, P],
+                                  ctypes.c_int),
             "rbffd_batch_tuning_set": ([P], ctypes.c_int),
             "rbffd_batch_tuning_get": ([P], ctypes.c_int),
         }
@@ -410,6 +412,51 @@ def rbffd_solve(row_ptr, col, val, b, x0=None, rtol: float = 1e-10, max_iter: in
                            int(max_iter), ctypes.byref(it), ctypes.byref(rr), ctypes.byref(info),
                            _p(ws), ws.numel(), _stream(b.device)), "rbffd_solve")
     return x, it.value, rr.value, info.value
+
+
+PRECOND_NONE, PRECOND_JACOBI = 0, 1
+
+
+class SolveResult(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("info", ctypes.c_int32), ("relres", ctypes.c_double)]
+
+
+def rbffd_solve_async(row_ptr, col, val, b, x, rtol: float = 1e-10, max_iter: int = 2000,
+                      precond: int = PRECOND_JACOBI, result=None, workspace=None):
+    """Enqueue the solve of W x = b in place on x (the initial guess), without
+    host synchronisation (capturable in a graph).  result: an int8 device
+    tensor of 16 bytes receiving {iters, info, relres} (see
+    solve_result()); workspace: optional, rbffd_solve_workspace_size bytes.
+    Returns (x, result, workspace)."""
+    lib = _load()
+    row_ptr = _dev(row_ptr, torch.int64, "row_ptr")
+    col = _dev(col, torch.int32, "col")
+    val = _dev(val, torch.float64, "val")
+    n = row_ptr.numel() - 1
+    if col.numel() != val.numel():
+        raise ValueError(f"col ({col.numel()}) and val ({val.numel()}) differ in length")
+    b = _vec(b, n, torch.float64, "b")
+    x = _out(x, (n,), torch.float64, "x", b.device)
+    need = _size(lib.rbffd_solve_workspace_size, n)
+    if workspace is None:
+        workspace = _workspace(need, b.device)
+    elif not isinstance(workspace, torch.Tensor) or not workspace.is_cuda or \
+            workspace.dtype != torch.uint8 or workspace.numel() < need or \
+            not workspace.is_contiguous():
+        raise ValueError(f"workspace must be a contiguous uint8 GPU tensor of >= {need} bytes")
+    result = _out(result, (ctypes.sizeof(SolveResult),), torch.int8, "result", b.device)
+    _check(lib.rbffd_solve_async(n, _p(row_ptr), _p(col), _p(val), _p(b), _p(x), float(rtol),
+                                 int(max_iter), int(precond), _p(result), _p(workspace),
+                                 workspace.numel(), _stream(b.device)), "rbffd_solve_async")
+    return x, result, workspace
+
+
+def solve_result(result) -> tuple:
+    """(iterations, relative true residual, info) from a result tensor
+    (synchronises with the device)."""
+    raw = bytes(result.cpu().numpy().tobytes())
+    r = SolveResult.from_buffer_copy(raw)
+    return r.iters, r.relres, r.info
 
 
 def rbffd_time_steps(nbr, w, n: int, f, u, dt: float, n_steps: int, is_boundary=None,

@@ -66,11 +66,13 @@ __device__ __forceinline__ double sum_partials(const double *part, int n, int st
     return block_sum(a, sh);
 }
 
-// Row r of W times u, in lane 0 of the row's 16 lanes.
+// Row r of W times u (times D^-1 u when dinv is given), in lane 0 of the
+// row's 16 lanes.
 __device__ __forceinline__ double row_dot(int64_t r, int64_t n, const int64_t *__restrict__ row_ptr,
                                           const int32_t *__restrict__ col,
                                           const double *__restrict__ val,
-                                          const double *__restrict__ u, int l16) {
+                                          const double *__restrict__ u,
+                                          const double *__restrict__ dinv, int l16) {
     double acc = 0.0;
     bool bad = false;
     const int64_t e1 = row_ptr[r + 1];
@@ -78,7 +80,8 @@ __device__ __forceinline__ double row_dot(int64_t r, int64_t n, const int64_t *_
         const int32_t c = col[e];
         const bool ok = (int64_t)c >= 0 && (int64_t)c < n;
         bad = bad || !ok;
-        acc = fma(val[e], u[ok ? c : 0], acc);
+        const int64_t cc = ok ? c : 0;
+        acc = fma(val[e], dinv ? u[cc] * dinv[cc] : u[cc], acc);
     }
 #pragma unroll
     for (int o = kRowLanes / 2; o > 0; o >>= 1) {
@@ -100,7 +103,8 @@ __global__ __launch_bounds__(kT) void k_spmv_dot(int64_t n, const int64_t *__res
                                                 double *__restrict__ out,
                                                 const double *__restrict__ w0, bool two,
                                                 double *__restrict__ partial, int np,
-                                                const SolveState *__restrict__ st) {
+                                                const SolveState *__restrict__ st,
+                                                const double *__restrict__ dinv) {
     __shared__ double sh[kT / kWave];
     if (st && st->flag != kRunning) return;
     const int l16 = threadIdx.x & (kRowLanes - 1);
@@ -108,7 +112,7 @@ __global__ __launch_bounds__(kT) void k_spmv_dot(int64_t n, const int64_t *__res
     const int64_t stride = (int64_t)gridDim.x * (kT / kRowLanes);
     for (int64_t r = (int64_t)blockIdx.x * (kT / kRowLanes) + threadIdx.x / kRowLanes; r < n;
          r += stride) {
-        const double y0 = row_dot(r, n, row_ptr, col, val, in, l16);
+        const double y0 = row_dot(r, n, row_ptr, col, val, in, dinv, l16);
         const double y = sub ? sub[r] - y0 : y0;
         if (l16 == 0) {
             out[r] = y;
@@ -183,7 +187,8 @@ __global__ __launch_bounds__(kT) void k_s(int64_t n, const double *__restrict__ 
     if (blockIdx.x == 0 && threadIdx.x == 0) st->alpha = alpha;
 }
 
-// K4: omega, x += alpha p + omega s, r = s - omega t, partials (r0, r), (r, r).
+// K4: omega, x += alpha p + omega s (with dinv: x += D^-1 (alpha p + omega s),
+// the right-preconditioned update), r = s - omega t, partials (r0, r), (r, r).
 __global__ __launch_bounds__(kT) void k_xr(int64_t n, double *__restrict__ x,
                                           const double *__restrict__ p,
                                           const double *__restrict__ s,
@@ -191,7 +196,8 @@ __global__ __launch_bounds__(kT) void k_xr(int64_t n, double *__restrict__ x,
                                           const double *__restrict__ r0,
                                           const double *__restrict__ part_ts, int nb,
                                           double *__restrict__ part_out,
-                                          SolveState *__restrict__ st) {
+                                          SolveState *__restrict__ st,
+                                          const double *__restrict__ dinv) {
     __shared__ double sh[kT / kWave];
     if (st->flag != kRunning) return;
     const double ts = sum_partials(part_ts, nb, 2, sh);
@@ -201,7 +207,10 @@ __global__ __launch_bounds__(kT) void k_xr(int64_t n, double *__restrict__ x,
     const double alpha = st->alpha;
     double d0 = 0.0, d1 = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
-        x[i] = fma(omega, s[i], fma(alpha, p[i], x[i]));
+        if (dinv)
+            x[i] = fma(omega, s[i] * dinv[i], fma(alpha, p[i] * dinv[i], x[i]));
+        else
+            x[i] = fma(omega, s[i], fma(alpha, p[i], x[i]));
         const double ri = fma(-omega, t[i], s[i]);
         r[i] = ri;
         d0 = fma(r0[i], ri, d0);
@@ -245,6 +254,36 @@ __global__ __launch_bounds__(kT) void k_p(int64_t n, double *__restrict__ p,
     }
 }
 
+// Jacobi scaling: dinv[i] = 1 / W_ii (1 where the row has no non-zero
+// diagonal entry; the first diagonal entry of a row counts).
+__global__ __launch_bounds__(kT) void k_diag(int64_t n, const int64_t *__restrict__ row_ptr,
+                                            const int32_t *__restrict__ col,
+                                            const double *__restrict__ val,
+                                            double *__restrict__ dinv) {
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
+        double d = 0.0;
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e)
+            if ((int64_t)col[e] == i) {
+                d = val[e];
+                break;
+            }
+        dinv[i] = (d != 0.0 && isfinite(d)) ? 1.0 / d : 1.0;
+    }
+}
+
+// the outcome into a device record (iterations, info, relative residual)
+__global__ void k_report(const SolveState *__restrict__ st, const double *__restrict__ fin,
+                         rbffd_solve_result *__restrict__ out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int32_t flag = st->flag;
+    out->iters = st->iters;
+    out->info = flag == kRunning ? RBFFD_SOLVE_MAX_ITER
+              : flag == kConverged ? RBFFD_SOLVE_CONVERGED
+              : flag == kBreakdown ? RBFFD_SOLVE_BREAKDOWN
+                                   : RBFFD_SOLVE_NONFINITE;
+    out->relres = st->bb > 0.0 ? sqrt(*fin / st->bb) : sqrt(*fin);
+}
+
 // the final residual norm (b - W x, b - W x) from block partials
 __global__ __launch_bounds__(kT) void k_final(const double *__restrict__ part, int nb,
                                              double *__restrict__ out) {
@@ -254,7 +293,7 @@ __global__ __launch_bounds__(kT) void k_final(const double *__restrict__ part, i
 }
 
 struct Ws {
-    double *r, *r0, *p, *v, *s, *t, *p1, *p3, *p4, *pf, *fin;
+    double *r, *r0, *p, *v, *s, *t, *p1, *p3, *p4, *pf, *fin, *dinv;
     SolveState *st;
     size_t bytes;
 };
@@ -274,6 +313,7 @@ Ws carve_ws(void *base, int64_t n) {
     w.pf = c.take<double>(2 * kMaxBlocks);
     w.fin = c.take<double>(1);
     w.st = c.take<SolveState>(1);
+    w.dinv = c.take<double>(n);
     w.bytes = c.bytes();
     return w;
 }
@@ -289,6 +329,82 @@ extern "C" int rbffd_solve_workspace_size(int64_t n_rows, size_t *bytes) {
     return RBFFD_SUCCESS;
 }
 
+namespace rbffd {
+namespace {
+
+// The whole solve on stream s.  check_every > 0: the host reads the state
+// every check_every iterations and stops enqueueing once it is final, then
+// fills *host_out.  check_every == 0: all max_iter iterations are enqueued
+// (each launch returns at once when the solve has ended) and the outcome
+// goes to the device record dev_out; nothing waits on the host.
+int solve_impl(int64_t n_rows, const int64_t *row_ptr, const int32_t *col, const double *val,
+               const double *b, double *x, double rtol, int32_t max_iter, bool jacobi,
+               int check_every, rbffd_solve_result *host_out, rbffd_solve_result *dev_out,
+               const Ws &w, hipStream_t s) {
+    const int nb = (int)std::min<int64_t>(kMaxBlocks, ceil_div(n_rows, kT / kRowLanes));
+    const int nv = (int)std::min<int64_t>(kMaxBlocks, ceil_div(n_rows, kT));
+    const double *dv = jacobi ? w.dinv : nullptr;
+    int rc;
+#define LAUNCH(...)                                  \
+    do {                                             \
+        hipLaunchKernelGGL(__VA_ARGS__);             \
+        if ((rc = last_launch_rc()) != 0) return rc; \
+    } while (0)
+    if (jacobi) LAUNCH(k_diag, dim3(nv), dim3(kT), 0, s, n_rows, row_ptr, col, val, w.dinv);
+    // (b, b); r = b - W x with (r, r); start
+    LAUNCH(k_norm_b, dim3(nv), dim3(kT), 0, s, n_rows, b, w.p1);
+    LAUNCH(k_set_bb, dim3(1), dim3(kT), 0, s, w.p1, nv, w.st);
+    LAUNCH(k_spmv_dot, dim3(nb), dim3(kT), 0, s, n_rows, row_ptr, col, val, x, b, w.r,
+           (const double *)nullptr, false, w.p3, 1, (const SolveState *)nullptr,
+           (const double *)nullptr);
+    LAUNCH(k_start, dim3(nv), dim3(kT), 0, s, n_rows, w.r, w.r0, w.p, w.p3, nb, rtol * rtol,
+           w.st);
+    SolveState h{};
+    for (int it = 0; it < max_iter; ++it) {
+        const int par = it & 1;
+        LAUNCH(k_spmv_dot, dim3(nb), dim3(kT), 0, s, n_rows, row_ptr, col, val, w.p,
+               (const double *)nullptr, w.v, w.r0, false, w.p1, 1, w.st, dv);
+        LAUNCH(k_s, dim3(nv), dim3(kT), 0, s, n_rows, w.r, w.v, w.s, w.p1, nb, par, w.st);
+        LAUNCH(k_spmv_dot, dim3(nb), dim3(kT), 0, s, n_rows, row_ptr, col, val, w.s,
+               (const double *)nullptr, w.t, w.s, true, w.p3, 2, w.st, dv);
+        LAUNCH(k_xr, dim3(nv), dim3(kT), 0, s, n_rows, x, w.p, w.s, w.t, w.r, w.r0, w.p3, nb,
+               w.p4, w.st, dv);
+        LAUNCH(k_p, dim3(nv), dim3(kT), 0, s, n_rows, w.p, w.r, w.v, w.p4, nv, par, w.st);
+        if (check_every > 0 && ((it + 1) % check_every == 0 || it + 1 == max_iter)) {
+            if ((rc = hip_rc(hipMemcpyAsync(&h, w.st, sizeof(h), hipMemcpyDeviceToHost, s))))
+                return rc;
+            if ((rc = hip_rc(hipStreamSynchronize(s)))) return rc;
+            if (h.flag != kRunning) break;
+        }
+    }
+    // the true residual b - W x of the returned x
+    LAUNCH(k_spmv_dot, dim3(nb), dim3(kT), 0, s, n_rows, row_ptr, col, val, x, b, w.t,
+           (const double *)nullptr, false, w.pf, 1, (const SolveState *)nullptr,
+           (const double *)nullptr);
+    LAUNCH(k_final, dim3(1), dim3(kT), 0, s, w.pf, nb, w.fin);
+    if (dev_out) {
+        LAUNCH(k_report, dim3(1), dim3(kWave), 0, s, (const SolveState *)w.st,
+               (const double *)w.fin, dev_out);
+        return RBFFD_SUCCESS;
+    }
+#undef LAUNCH
+    double fin = 0.0;
+    if ((rc = hip_rc(hipMemcpyAsync(&h, w.st, sizeof(h), hipMemcpyDeviceToHost, s)))) return rc;
+    if ((rc = hip_rc(hipMemcpyAsync(&fin, w.fin, sizeof(fin), hipMemcpyDeviceToHost, s))))
+        return rc;
+    if ((rc = hip_rc(hipStreamSynchronize(s)))) return rc;
+    host_out->iters = h.iters;
+    host_out->relres = h.bb > 0.0 ? sqrt(fin / h.bb) : sqrt(fin);
+    host_out->info = h.flag == kRunning ? RBFFD_SOLVE_MAX_ITER
+                   : h.flag == kConverged ? RBFFD_SOLVE_CONVERGED
+                   : h.flag == kBreakdown ? RBFFD_SOLVE_BREAKDOWN
+                                          : RBFFD_SOLVE_NONFINITE;
+    return RBFFD_SUCCESS;
+}
+
+}  // namespace
+}  // namespace rbffd
+
 extern "C" int rbffd_solve(int64_t n_rows, const int64_t *row_ptr, const int32_t *col,
                            const double *val, const double *b, double *x, double rtol,
                            int32_t max_iter, int32_t *iters, double *relres, int32_t *info,
@@ -298,55 +414,26 @@ extern "C" int rbffd_solve(int64_t n_rows, const int64_t *row_ptr, const int32_t
     if (!(rtol >= 0.0) || max_iter < 0) return RBFFD_ERR_ARG;
     const Ws w = carve_ws(workspace, n_rows);
     if (!workspace || workspace_bytes < w.bytes) return RBFFD_ERR_WORKSPACE;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const int nb = (int)std::min<int64_t>(kMaxBlocks, ceil_div(n_rows, kT / kRowLanes));
-    const int nv = (int)std::min<int64_t>(kMaxBlocks, ceil_div(n_rows, kT));
-    int rc;
-#define LAUNCH(...)                                  \
-    do {                                             \
-        hipLaunchKernelGGL(__VA_ARGS__);             \
-        if ((rc = last_launch_rc()) != 0) return rc; \
-    } while (0)
-    // (b, b); r = b - W x with (r, r); start
-    LAUNCH(k_norm_b, dim3(nv), dim3(kT), 0, s, n_rows, b, w.p1);
-    LAUNCH(k_set_bb, dim3(1), dim3(kT), 0, s, w.p1, nv, w.st);
-    LAUNCH(k_spmv_dot, dim3(nb), dim3(kT), 0, s, n_rows, row_ptr, col, val, x, b, w.r,
-           (const double *)nullptr, false, w.p3, 1, (const SolveState *)nullptr);
-    LAUNCH(k_start, dim3(nv), dim3(kT), 0, s, n_rows, w.r, w.r0, w.p, w.p3, nb, rtol * rtol,
-           w.st);
-    SolveState h{};
-    for (int it = 0; it < max_iter; ++it) {
-        const int par = it & 1;
-        LAUNCH(k_spmv_dot, dim3(nb), dim3(kT), 0, s, n_rows, row_ptr, col, val, w.p,
-               (const double *)nullptr, w.v, w.r0, false, w.p1, 1, w.st);
-        LAUNCH(k_s, dim3(nv), dim3(kT), 0, s, n_rows, w.r, w.v, w.s, w.p1, nb, par, w.st);
-        LAUNCH(k_spmv_dot, dim3(nb), dim3(kT), 0, s, n_rows, row_ptr, col, val, w.s,
-               (const double *)nullptr, w.t, w.s, true, w.p3, 2, w.st);
-        LAUNCH(k_xr, dim3(nv), dim3(kT), 0, s, n_rows, x, w.p, w.s, w.t, w.r, w.r0, w.p3, nb,
-               w.p4, w.st);
-        LAUNCH(k_p, dim3(nv), dim3(kT), 0, s, n_rows, w.p, w.r, w.v, w.p4, nv, par, w.st);
-        if ((it + 1) % kCheckEvery == 0 || it + 1 == max_iter) {
-            if ((rc = hip_rc(hipMemcpyAsync(&h, w.st, sizeof(h), hipMemcpyDeviceToHost, s))))
-                return rc;
-            if ((rc = hip_rc(hipStreamSynchronize(s)))) return rc;
-            if (h.flag != kRunning) break;
-        }
-    }
-    // the true residual b - W x of the returned x
-    LAUNCH(k_spmv_dot, dim3(nb), dim3(kT), 0, s, n_rows, row_ptr, col, val, x, b, w.t,
-           (const double *)nullptr, false, w.pf, 1, (const SolveState *)nullptr);
-    LAUNCH(k_final, dim3(1), dim3(kT), 0, s, w.pf, nb, w.fin);
-#undef LAUNCH
-    double fin = 0.0;
-    if ((rc = hip_rc(hipMemcpyAsync(&h, w.st, sizeof(h), hipMemcpyDeviceToHost, s)))) return rc;
-    if ((rc = hip_rc(hipMemcpyAsync(&fin, w.fin, sizeof(fin), hipMemcpyDeviceToHost, s))))
-        return rc;
-    if ((rc = hip_rc(hipStreamSynchronize(s)))) return rc;
-    *iters = h.iters;
-    *relres = h.bb > 0.0 ? sqrt(fin / h.bb) : sqrt(fin);
-    *info = h.flag == kRunning ? RBFFD_SOLVE_MAX_ITER
-          : h.flag == kConverged ? RBFFD_SOLVE_CONVERGED
-          : h.flag == kBreakdown ? RBFFD_SOLVE_BREAKDOWN
-                                 : RBFFD_SOLVE_NONFINITE;
+    rbffd_solve_result res{};
+    const int rc = solve_impl(n_rows, row_ptr, col, val, b, x, rtol, max_iter, false, kCheckEvery,
+                              &res, nullptr, w, static_cast<hipStream_t>(stream));
+    if (rc) return rc;
+    *iters = res.iters;
+    *relres = res.relres;
+    *info = res.info;
     return RBFFD_SUCCESS;
+}
+
+extern "C" int rbffd_solve_async(int64_t n_rows, const int64_t *row_ptr, const int32_t *col,
+                                 const double *val, const double *b, double *x, double rtol,
+                                 int32_t max_iter, int32_t precond, rbffd_solve_result *result,
+                                 void *workspace, size_t workspace_bytes, void *stream) {
+    if (n_rows < 1 || !row_ptr || !col || !val || !b || !x || !result) return RBFFD_ERR_ARG;
+    if (!(rtol >= 0.0) || max_iter < 0) return RBFFD_ERR_ARG;
+    if (precond != RBFFD_PRECOND_NONE && precond != RBFFD_PRECOND_JACOBI) return RBFFD_ERR_ARG;
+    const Ws w = carve_ws(workspace, n_rows);
+    if (!workspace || workspace_bytes < w.bytes) return RBFFD_ERR_WORKSPACE;
+    return solve_impl(n_rows, row_ptr, col, val, b, x, rtol, max_iter,
+                      precond == RBFFD_PRECOND_JACOBI, 0, nullptr, result, w,
+                      static_cast<hipStream_t>(stream));
 }

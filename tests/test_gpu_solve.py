@@ -125,3 +125,94 @@ def test_solve_limits_and_errors():
     assert info == rb.SOLVE_NONFINITE
     with pytest.raises(rb.RbffdError):
         rb.rbffd_solve(rp, col, val, dev(b), rtol=-1.0)
+
+
+def test_async_unpreconditioned_same_bits_as_solve():
+    ns = nodes.unit_square(30, seed=27)
+    rp, col, val, b, ue = gpu_system(ns, 2)
+    B = dev(b)
+    x1, it1, rr1, info1 = rb.rbffd_solve(rp, col, val, B, rtol=1e-11, max_iter=3000)
+    x2 = torch.zeros_like(B)
+    x2, res, _ = rb.rbffd_solve_async(rp, col, val, B, x2, rtol=1e-11, max_iter=it1 + 20,
+                                      precond=rb.PRECOND_NONE)
+    it2, rr2, info2 = rb.solve_result(res)
+    say("sync", it1, rr1, "async", it2, rr2)
+    assert (it2, info2) == (it1, info1) and rr2 == rr1
+    assert torch.equal(x1, x2)
+
+
+@pytest.mark.parametrize("m", [2, 4])
+def test_jacobi_solve_matches_direct_solve(m):
+    """The right-preconditioned (Jacobi) iteration reaches the direct
+    solution; its iteration count is reported, not asserted (the diagonal
+    scaling leaves the operator's spectrum as it is: D^-1 W and W D^-1 are
+    similar to the row-scaled operator, whose conditioning grows as 1/h^2)."""
+    ns = nodes.unit_square(40, seed=28)
+    rp, col, val, b, ue = gpu_system(ns, m)
+    x_ref = oracle.solve(host(rp), host(col), host(val), b)
+    B = dev(b)
+    _, it0, _, _ = rb.rbffd_solve(rp, col, val, B, rtol=1e-12, max_iter=20000)
+    x, res, _ = rb.rbffd_solve_async(rp, col, val, B, torch.zeros_like(B), rtol=1e-12,
+                                     max_iter=4000, precond=rb.PRECOND_JACOBI)
+    it, rr, info = rb.solve_result(res)
+    xg = host(x)
+    err = np.abs(xg - x_ref).max() / np.abs(x_ref).max()
+    say(f"m={m}: jacobi {it} iterations (none: {it0}), relres {rr:.2e}, vs direct {err:.2e}")
+    # the true residual departs from the recurrence's (rtol = 1e-12) by the
+    # rounding of W x, a few multiples of cond * eps
+    assert info == rb.SOLVE_CONVERGED and rr <= 1e-10
+    r = oracle.spmv(host(rp), host(col), host(val), xg, b)
+    assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(b)
+    assert err <= 1e-7
+
+
+@pytest.mark.parametrize("precond", [0, 1])
+def test_solve_graph_replay(precond):
+    """The host-synchronisation-free solve captured in a graph and replayed
+    three times, with eager work between the replays: every replay gives the
+    eager call's bits and outcome."""
+    ns = nodes.unit_square(40, seed=29)
+    rp, col, val, b, ue = gpu_system(ns, 4)
+    B = dev(b)
+    x, res, ws = rb.rbffd_solve_async(rp, col, val, B, torch.zeros_like(B), rtol=1e-11,
+                                      max_iter=800, precond=precond)
+    it, rr, info = rb.solve_result(res)
+    say(f"precond {precond}: {it} iterations, relres {rr:.2e}")
+    assert info == rb.SOLVE_CONVERGED and rr <= 1e-10
+    x_eager = x.clone()
+    xg2 = torch.empty_like(B)
+    res2 = torch.empty(16, dtype=torch.int8, device="cuda")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        xg2.zero_()
+        rb.rbffd_solve_async(rp, col, val, B, xg2, rtol=1e-11, max_iter=800, precond=precond,
+                             result=res2, workspace=ws)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        xg2.zero_()
+        rb.rbffd_solve_async(rp, col, val, B, xg2, rtol=1e-11, max_iter=800, precond=precond,
+                             result=res2, workspace=ws)
+    for rep in range(3):
+        xg2.fill_(7.0)
+        res2.fill_(0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(xg2, x_eager), f"replay {rep}"
+        assert rb.solve_result(res2) == (it, rr, info)
+
+
+def test_jacobi_solve_full_disk():
+    ns = nodes.workload("disk_100k_m4")
+    rp, col, val, b, ue = gpu_system(ns, 4)
+    B = dev(b)
+    x, res, ws = rb.rbffd_solve_async(rp, col, val, B, torch.zeros_like(B), rtol=1e-10,
+                                      max_iter=4000, precond=rb.PRECOND_JACOBI)
+    it, rr, info = rb.solve_result(res)
+    xg = host(x)
+    err = np.abs(xg - ue).max()
+    say(f"disk 100k m=4 jacobi: {it} iterations, relres {rr:.2e}, max error vs exact {err:.2e}")
+    assert info == rb.SOLVE_CONVERGED and rr <= 1e-9 and err < 1e-4

@@ -95,3 +95,18 @@ def test_time_loop_bad_index_and_errors():
         rb.rbffd_time_steps(dev(nbr), dev(w), 13, dev(f), dev(u0), 1e-4, 1)
     with pytest.raises(rb.RbffdError):
         rb.rbffd_time_steps(dev(nbr), dev(w), 12, dev(f), dev(u0), 1e-4, -1)
+
+
+@pytest.mark.parametrize("n_target", [30000, 40000])
+def test_time_loop_bit_exact_around_the_single_workgroup_limit(n_target):
+    """Node sets just below and above the size up to which every step runs in
+    one workgroup launch: the same bits as the oracle's loop either way."""
+    ns = nodes.unit_disk(n_target, 600, seed=13)
+    nbr, w, f, u0 = _problem(ns, 2, 12)
+    for steps in (8, 9):
+        ref = oracle.time_steps(nbr, w, 12, f, u0, 1e-6, steps, is_boundary=ns.is_boundary)
+        u = dev(u0)
+        rb.rbffd_time_steps(dev(nbr), dev(w), 12, dev(f), u, 1e-6, steps,
+                            is_boundary=dev(ns.is_boundary))
+        torch.cuda.synchronize()
+        assert np.array_equal(u.cpu().numpy(), ref), f"N={ns.n_nodes} steps={steps}"
