@@ -7,10 +7,6 @@
 // thread per node summing its row with fma in k order; the neighbours'
 // values are gathered (the spatial order of the nodes keeps them in cache).
 // The two value buffers swap roles each step.
-// Small node sets (at most kFusedMaxNodes) run every step in one launch of a
-// single workgroup, with a workgroup barrier between steps: there the time
-// of a step is the latency of a launch, not its work.  The per-node
-// arithmetic is the same, so both forms give the same bits.
 
 #include "common.h"
 
@@ -18,11 +14,6 @@ namespace rbffd {
 namespace {
 
 constexpr int kTL = 256;
-constexpr int kFB = 1024;  // threads of the single-workgroup form
-#ifndef RBFFD_TL_FUSED_MAX_NODES
-#define RBFFD_TL_FUSED_MAX_NODES 32768
-#endif
-constexpr int64_t kFusedMaxNodes = RBFFD_TL_FUSED_MAX_NODES;
 
 // k-major copies: nbrT[k * n + i] = nbr[i][k], wT likewise, k < nk
 __global__ __launch_bounds__(kTL) void ell_to_kmajor(int64_t n, const int32_t *__restrict__ nbr,
@@ -69,21 +60,6 @@ __global__ __launch_bounds__(kTL) void explicit_step(int64_t n, const int32_t *_
     const int64_t i = (int64_t)blockIdx.x * kTL + threadIdx.x;
     if (i >= n) return;
     step_node(i, n, nbrT, nk, wT, is_boundary, f, dt, src, dst);
-}
-
-// every step in one workgroup: step t reads one buffer and writes the other,
-// then the workgroup barrier makes its writes visible to the next step
-__global__ __launch_bounds__(kFB) void explicit_steps_block(
-    int64_t n, const int32_t *__restrict__ nbrT, int32_t nk, const double *__restrict__ wT,
-    const uint8_t *__restrict__ is_boundary, const double *__restrict__ f, double dt,
-    int64_t n_steps, double *a, double *b) {
-    for (int64_t t = 0; t < n_steps; ++t) {
-        const double *src = (t & 1) ? b : a;
-        double *dst = (t & 1) ? a : b;
-        for (int64_t i = threadIdx.x; i < n; i += kFB)
-            step_node(i, n, nbrT, nk, wT, is_boundary, f, dt, src, dst);
-        __syncthreads();
-    }
 }
 
 __global__ __launch_bounds__(kTL) void copy_f64(int64_t n, const double *__restrict__ src,
@@ -136,23 +112,13 @@ extern "C" int rbffd_time_steps(int64_t n_nodes, const int32_t *nbr, int32_t k_s
     hipLaunchKernelGGL(ell_to_kmajor, dim3((unsigned)tblocks), dim3(kTL), 0, s, n_nodes, nbr,
                        k_stride, n, w, ws.nbrT, ws.wT);
     double *a = u, *b = u_work;
-    if (n_nodes <= kFusedMaxNodes) {
-        hipLaunchKernelGGL(explicit_steps_block, dim3(1), dim3(kFB), 0, s, n_nodes,
-                           (const int32_t *)ws.nbrT, n, (const double *)ws.wT, is_boundary, f, dt,
-                           n_steps, a, b);
-        if (n_steps & 1) {
-            a = u_work;
-            b = u;
-        }
-    } else {
-        for (int64_t t = 0; t < n_steps; ++t) {
-            hipLaunchKernelGGL(explicit_step, dim3((unsigned)blocks), dim3(kTL), 0, s, n_nodes,
-                               (const int32_t *)ws.nbrT, n, (const double *)ws.wT, is_boundary,
-                               f, dt, (const double *)a, b);
-            double *c = a;
-            a = b;
-            b = c;
-        }
+    for (int64_t t = 0; t < n_steps; ++t) {
+        hipLaunchKernelGGL(explicit_step, dim3((unsigned)blocks), dim3(kTL), 0, s, n_nodes,
+                           (const int32_t *)ws.nbrT, n, (const double *)ws.wT, is_boundary, f,
+                           dt, (const double *)a, b);
+        double *c = a;
+        a = b;
+        b = c;
     }
     if (a != u)
         hipLaunchKernelGGL(copy_f64, dim3((unsigned)blocks), dim3(kTL), 0, s, n_nodes,

@@ -116,7 +116,7 @@ struct GjLds {
 // One wavefront computes stencil i.  AREG: keep the FP64 entries of the
 // tiles that hold A entries in registers for the residual (else they are
 // recomputed from the FP64 offsets at every correction).
-template <int KP, int NFIX, int MFIX, bool AREG, int UNR>
+template <int KP, int NFIX, int MFIX, bool AREG, int UNR, int RCP>
 __device__ __forceinline__ void weights_gj_wave(
     const double *__restrict__ x, const double *__restrict__ y, int64_t n_nodes,
     const int32_t *__restrict__ nbr, int32_t k_stride, int64_t i, double *__restrict__ w,
@@ -172,6 +172,7 @@ __device__ __forceinline__ void weights_gj_wave(
         }
     }
     const double sc = sqrt(seg_all_max_d<kWave>(d2m, lane));
+    if (!isfinite(sc)) flags |= F_NONFIN;  // an offset's square overflowed
     if (sc == 0.0) flags |= F_DUP;
     // the monomials of row r, into the table
     auto monomials = [&](int s) {
@@ -331,7 +332,10 @@ __device__ __forceinline__ void weights_gj_wave(
             const float piv = __builtin_bit_cast(
                 float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, bv), win));
             if (!(piv != 0.0f) || !isfinite(piv)) lufail = true;
-            const float inv = 1.0f / piv;
+            // the reciprocal: IEEE (RCP = 0) or the hardware's within an ulp
+            // (RCP = 1); the refinement, not the factors, sets the accuracy,
+            // but a less exact inverse can take more corrections
+            const float inv = RCP ? __builtin_amdgcn_rcpf(piv) : 1.0f / piv;
             const bool b1 = bs != 0;
             // the pivot row's other panel entries, scaled
             float wv[4];
@@ -684,7 +688,7 @@ __device__ __forceinline__ void weights_gj_wave(
     }
 }
 
-template <int KP, int NFIX, int MFIX, bool AREG, int OCC, int UNR>
+template <int KP, int NFIX, int MFIX, bool AREG, int OCC, int UNR, int RCP>
 __global__ __launch_bounds__(kWave)
 __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1))) void weights_gj_kernel(
     const double *__restrict__ x, const double *__restrict__ y, int64_t n_nodes,
@@ -697,13 +701,13 @@ __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1))) void weights_gj_kernel(
     const int64_t t = blockIdx.x;
     if (t >= n_rows) return;
     const int64_t i = rows ? (int64_t)rows[t] : t;
-    weights_gj_wave<KP, NFIX, MFIX, AREG, UNR>(x, y, n_nodes, nbr, k_stride, i, w, status,
+    weights_gj_wave<KP, NFIX, MFIX, AREG, UNR, RCP>(x, y, n_nodes, nbr, k_stride, i, w, status,
                                                iters, fb_count, fb_list, lds);
 }
 
 // One block (one wavefront) per listed stencil; no scratch memory.
 // UNR: 4 unrolls the panel loop fully, 1 keeps it rolled within a tile column.
-template <int KP, int NFIX, int MFIX, bool AREG, int OCC = 0, int UNR = 1>
+template <int KP, int NFIX, int MFIX, bool AREG, int OCC = 0, int UNR = 1, int RCP = 0>
 struct GjLaunch {
     static size_t scratch_bytes(int64_t) { return 0; }
     static int run(const double *x, const double *y, int64_t n_nodes, const int32_t *nbr,
@@ -712,7 +716,8 @@ struct GjLaunch {
                    int32_t *fb_count, int32_t *fb_list, hipStream_t stream) {
         if (n_rows <= 0) return RBFFD_SUCCESS;
         if (n_rows > 0x7fffffff) return RBFFD_ERR_UNSUPPORTED;
-        hipLaunchKernelGGL((weights_gj_kernel<KP, NFIX, MFIX, AREG, OCC, UNR>), dim3((unsigned)n_rows),
+        hipLaunchKernelGGL((weights_gj_kernel<KP, NFIX, MFIX, AREG, OCC, UNR, RCP>),
+                           dim3((unsigned)n_rows),
                            dim3(kWave), 0, stream, x, y, n_nodes, nbr, k_stride, rows, n_rows_dev,
                            n_rows, w, status, iters, fb_count, fb_list);
         return last_launch_rc();

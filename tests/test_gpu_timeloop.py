@@ -98,9 +98,9 @@ def test_time_loop_bad_index_and_errors():
 
 
 @pytest.mark.parametrize("n_target", [30000, 40000])
-def test_time_loop_bit_exact_around_the_single_workgroup_limit(n_target):
-    """Node sets just below and above the size up to which every step runs in
-    one workgroup launch: the same bits as the oracle's loop either way."""
+def test_time_loop_bit_exact_mid_size(n_target):
+    """Mid-size node sets (30k, 40k), an even and an odd number of steps (the
+    result ends in either buffer): the same bits as the oracle's loop."""
     ns = nodes.unit_disk(n_target, 600, seed=13)
     nbr, w, f, u0 = _problem(ns, 2, 12)
     for steps in (8, 9):
