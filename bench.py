@@ -47,15 +47,17 @@ def weights_flops(m: int, n: int) -> int:
     return lu + solves + assembly
 
 
-def weights3_flops(n: int) -> int:
-    """The same count for the 3-D stencil (m = 2, M = 10, K = n + 10): LU and
-    solves as above; assembly 5 n (n - 1) (half the pairs, 3 differences,
-    3 squares, 2 sums, a square root and a product each), 18 (n - 1) for the
-    offsets, scale and right-hand side, n (M - 1) monomial products, n."""
-    K = n + 10
+def weights3_flops(n: int, m: int = 2) -> int:
+    """The same count for the 3-D stencil (M = (m+1)(m+2)(m+3)/6 monomials,
+    K = n + M): LU and solves as above; assembly 5 n (n - 1) (half the pairs,
+    3 differences, 3 squares, 2 sums, a square root and a product each),
+    18 (n - 1) for the offsets, scale and right-hand side, n (M - 1)
+    monomial products, n."""
+    M = (m + 1) * (m + 2) * (m + 3) // 6
+    K = n + M
     lu = (K - 1) * K // 2 + (K - 1) * K * (2 * K - 1) // 3
     solves = 2 * K * (K - 1) + K
-    assembly = 5 * n * (n - 1) + 18 * (n - 1) + n * 9 + n
+    assembly = 5 * n * (n - 1) + 18 * (n - 1) + n * (M - 1) + n
     return lu + solves + assembly
 
 
@@ -227,7 +229,8 @@ def main():
     ap.add_argument("--cpu-stride", type=int, default=7)
     ap.add_argument("--profile-case", default=None,
                     help="only run one weights launch pattern under a profiler: "
-                         "{fp64,mixed}_m{2,4,6} on the 1M-node square (prints its timing)")
+                         "{fp64,mixed}_m{2,4,6} on the 1M-node square, cube_m{2,4} / "
+                         "cube40_m4 on the 3-D lattice (prints its timing)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -367,24 +370,41 @@ def timed(torch, stream, fn, reps=3):
 
 
 def profile_case(torch, rb, nodes, dev, case, warmup, steps):
-    """One weights launch pattern on the 1M-node square, for kernel traces
-    and counters: `warmup` untimed calls, then `steps` timed ones."""
+    """One weights launch pattern, for kernel traces and counters: `warmup`
+    untimed calls, then `steps` timed ones.  fp64_m{2,4,6}, mixed_m{2,4,6}:
+    the 1M-node square; cube_m{2,4}: the 3-D Laplacian on the jittered 100^3
+    lattice (n = 20, 70); cube40_m4: the same on the 40^3 lattice."""
     prec, mpart = case.split("_")
     m = int(mpart[1:])
-    n = {2: 12, 4: 30, 6: 56}[m]
-    if prec not in ("fp64", "mixed") or m not in (2, 4, 6):
-        raise SystemExit(f"unknown profile case {case}")
-    ns = nodes.workload("square_1m_m6")
-    X = torch.as_tensor(ns.x, device=dev)
-    Y = torch.as_tensor(ns.y, device=dev)
-    nb = rb.rbffd_knn(X, Y, n)
-    out = torch.empty((ns.n_nodes, n), dtype=torch.float64, device=dev)
-    st = torch.empty(ns.n_nodes, dtype=torch.int32, device=dev)
-    pr = rb.MIXED if prec == "mixed" else rb.FP64
     stream = torch.cuda.current_stream(dev)
+    if prec in ("cube", "cube40"):
+        if m not in (2, 4):
+            raise SystemExit(f"unknown profile case {case}")
+        n = {2: 20, 4: 70}[m]
+        x, y, z = nodes.jittered_cube(100 if prec == "cube" else 40, seed=6)
+        X, Y, Z = (torch.as_tensor(a, device=dev) for a in (x, y, z))
+        nb = rb.rbffd_knn3(X, Y, Z, n)
+        N = x.shape[0]
+        out = torch.empty((N, n), dtype=torch.float64, device=dev)
+        st = torch.empty(N, dtype=torch.int32, device=dev)
 
-    def run():
-        rb.rbffd_weights(X, Y, nb, m=m, n=n, precision=pr, out=out, status=st)
+        def run():
+            rb.rbffd_weights3(X, Y, Z, nb, m, n, out=out, status=st)
+    else:
+        n = {2: 12, 4: 30, 6: 56}.get(m)
+        if prec not in ("fp64", "mixed") or n is None:
+            raise SystemExit(f"unknown profile case {case}")
+        ns = nodes.workload("square_1m_m6")
+        X = torch.as_tensor(ns.x, device=dev)
+        Y = torch.as_tensor(ns.y, device=dev)
+        nb = rb.rbffd_knn(X, Y, n)
+        N = ns.n_nodes
+        out = torch.empty((N, n), dtype=torch.float64, device=dev)
+        st = torch.empty(N, dtype=torch.int32, device=dev)
+        pr = rb.MIXED if prec == "mixed" else rb.FP64
+
+        def run():
+            rb.rbffd_weights(X, Y, nb, m=m, n=n, precision=pr, out=out, status=st)
     for _ in range(max(warmup, 0)):
         run()
     torch.cuda.synchronize()
@@ -397,7 +417,7 @@ def profile_case(torch, rb, nodes, dev, case, warmup, steps):
         e1.record(stream)
         e1.synchronize()
         ts.append(e0.elapsed_time(e1))
-    print(json.dumps({"profile_case": case, "n_nodes": ns.n_nodes, "ms": ts,
+    print(json.dumps({"profile_case": case, "n_nodes": N, "ms": ts,
                       "statuses": np.bincount(st.cpu().numpy()).tolist()}), flush=True)
 
 
@@ -546,35 +566,40 @@ def extras_ops(torch, rb, stream, X, Y, ns, m, n):
     return res
 
 
-def extras_3d(torch, rb, nodes, dev, stream, n=20):
-    """Three-dimensional nodes: the jittered 100^3 lattice of [0,1]^3, m = 2,
-    n = 20 (K = 30).  kNN and weights per launch, the weights' fraction of
-    the FP64 peak, and the largest error of the weights applied to
-    u = sin(pi x) sin(pi y) sin(pi z) (lap u = -3 pi^2 u) over nodes at least
-    3 h inside the cube; the same for the d/dz weights."""
+def extras_3d(torch, rb, nodes, dev, stream):
+    """Three-dimensional nodes: the jittered 100^3 lattice of [0,1]^3 at
+    m = 2, n = 20 (K = 30) and m = 4, n = 70 (K = 105).  Per order: kNN and
+    weights per launch, the weights' fraction of the FP64 peak, and the
+    largest error of the weights applied to u = sin(pi x) sin(pi y)
+    sin(pi z) (lap u = -3 pi^2 u) over nodes at least 3 h inside the cube;
+    the same for the d/dz weights."""
     x, y, z = nodes.jittered_cube(100, seed=6)
     X, Y, Z = (torch.as_tensor(a, device=dev) for a in (x, y, z))
     N = x.shape[0]
-    knn_ms = timed(torch, stream, lambda: rb.rbffd_knn3(X, Y, Z, n))
-    nbr = rb.rbffd_knn3(X, Y, Z, n)
-    ms = timed(torch, stream, lambda: rb.rbffd_weights3(X, Y, Z, nbr, 2, n))
-    w, st = rb.rbffd_weights3(X, Y, Z, nbr, 2, n)
     u = torch.sin(math.pi * X) * torch.sin(math.pi * Y) * torch.sin(math.pi * Z)
-    lap = (w * u[nbr.long()]).sum(1)
     inner = ((X > 0.03) & (X < 0.97) & (Y > 0.03) & (Y < 0.97) & (Z > 0.03) & (Z < 0.97))
-    err = (lap - (-3.0 * math.pi ** 2) * u)[inner].abs().max().item()
-    fl = weights3_flops(n)
-    # d/dz: du/dz = pi sin(pi x) sin(pi y) cos(pi z)
-    ms_dz = timed(torch, stream, lambda: rb.rbffd_weights3(X, Y, Z, nbr, 2, n, op=rb.OP3_DZ))
-    wz, stz = rb.rbffd_weights3(X, Y, Z, nbr, 2, n, op=rb.OP3_DZ)
     dz_exact = math.pi * torch.sin(math.pi * X) * torch.sin(math.pi * Y) * torch.cos(math.pi * Z)
-    err_dz = ((wz * u[nbr.long()]).sum(1) - dz_exact)[inner].abs().max().item()
-    return {"n_nodes": N, "m": 2, "n": n, "knn_ms": knn_ms, "weights_ms": ms,
-            "stencils_per_s": N / (ms * 1e-3), "flops_per_stencil": fl,
-            "frac_fp64_peak": fl * N / 1e12 / (ms * 1e-3) / FP64_PEAK_TFLOPS,
+    res = {"n_nodes": N}
+    for m, n in ((2, 20), (4, 70)):
+        knn_ms = timed(torch, stream, lambda: rb.rbffd_knn3(X, Y, Z, n))
+        nbr = rb.rbffd_knn3(X, Y, Z, n)
+        ms = timed(torch, stream, lambda: rb.rbffd_weights3(X, Y, Z, nbr, m, n))
+        w, st = rb.rbffd_weights3(X, Y, Z, nbr, m, n)
+        lap = (w * u[nbr.long()]).sum(1)
+        err = (lap - (-3.0 * math.pi ** 2) * u)[inner].abs().max().item()
+        fl = weights3_flops(n, m)
+        # d/dz: du/dz = pi sin(pi x) sin(pi y) cos(pi z)
+        ms_dz = timed(torch, stream, lambda: rb.rbffd_weights3(X, Y, Z, nbr, m, n, op=rb.OP3_DZ))
+        wz, stz = rb.rbffd_weights3(X, Y, Z, nbr, m, n, op=rb.OP3_DZ)
+        err_dz = ((wz * u[nbr.long()]).sum(1) - dz_exact)[inner].abs().max().item()
+        res[f"m{m}_n{n}"] = {
+            "knn_ms": knn_ms, "weights_ms": ms, "stencils_per_s": N / (ms * 1e-3),
+            "flops_per_stencil": fl, "frac_fp64_peak": fl * N / 1e12 / (ms * 1e-3) / FP64_PEAK_TFLOPS,
             "failed": int((st != 0).sum().item()), "max_abs_err_inner": err,
             "d_dz": {"ms": ms_dz, "failed": int((stz != 0).sum().item()),
                      "max_abs_err_inner": err_dz}}
+        del w, wz, nbr, lap
+    return res
 
 
 def extras_adjoint(torch, rb, nodes, dev, stream):

@@ -200,22 +200,26 @@ int rbffd_weights_op(const double *x, const double *y, int64_t n_nodes, const in
  * rbffd_knn3: N(x) in R^3, as rbffd_knn: the k nearest nodes (self first),
  * ascending by (d2, index) with d2 = fl(fl(fl(dx^2) + fl(dy^2)) + fl(dz^2)),
  * NaN keys never taken, -1 for unfillable slots.  nbr: [n_nodes][k] int32
- * out.  1 <= k <= min(64, n_nodes) (k > 64: RBFFD_ERR_UNSUPPORTED from
+ * out.  1 <= k <= min(80, n_nodes) (k > 80: RBFFD_ERR_UNSUPPORTED from
  * rbffd_knn3, RBFFD_ERR_ARG from the workspace query).
  * Workspace from rbffd_knn3_workspace_size (cell grid, cell-sorted copy of
  * the nodes).
  *
  * rbffd_weights3: Laplacian weights of eq. (1) in d = 3: phi(r) = r^3 with
- * lap r^3 = 12 r, the ten monomials of degree <= m = 2 in graded order
- * (1, x, y, z, x^2, xy, xz, y^2, yz, z^2; rhs 2 for x^2, y^2, z^2), the
- * scale s = max |x_k - x_i| (IEEE division by s, w_ik = z_k / s^2), dense
- * LU with partial pivoting (first maximum |entry| in the current order),
- * multipliers a * (1 / pivot), fma updates, the rhs carried along, back
- * substitution with the pivot reciprocals, as in two dimensions.  Status
- * codes and their precedence as in rbffd_weights.  nbr: [n_nodes][k_stride]
- * int32, first n columns used; w: [n_nodes][k_stride] FP64 out, zero past n;
- * status: [n_nodes] int32 out or NULL.  m must be 2 and 10 <= n <= k_stride
- * (RBFFD_ERR_ARG otherwise); n > 54 (K = n + 10 > 64) returns
+ * lap r^3 = 12 r, the M = (m+1)(m+2)(m+3)/6 monomials of degree <= m in
+ * graded order (inside a degree the x exponent descending, then the y
+ * exponent: 1, x, y, z, x^2, xy, xz, y^2, yz, z^2, x^3, ...; each evaluated
+ * as (u^a v^b) t^c with powers by repeated multiplication; rhs 2 for x^2,
+ * y^2, z^2), the scale s = max |x_k - x_i| (IEEE division by s,
+ * w_ik = z_k / s^2), dense LU with partial pivoting (first maximum |entry|
+ * in the current order), multipliers a * (1 / pivot), fma updates, the rhs
+ * carried along, back substitution with the pivot reciprocals, as in two
+ * dimensions.  Status codes and their precedence as in rbffd_weights.
+ * nbr: [n_nodes][k_stride] int32, first n columns used; w:
+ * [n_nodes][k_stride] FP64 out, zero past n; status: [n_nodes] int32 out or
+ * NULL.  m = 2 with 10 <= n <= k_stride, or m = 4 with 35 <= n <= k_stride
+ * (RBFFD_ERR_ARG otherwise); m = 2 with n > 54 (K = n + 10 > 64) and m = 4
+ * with n other than 70 (the standard support, K = 105) return
  * RBFFD_ERR_UNSUPPORTED.  No workspace.
  *
  * rbffd_weights3_op: the same for the operator op: RBFFD_OP_LAPLACIAN (as
@@ -237,18 +241,28 @@ int rbffd_weights3_op(const double *x, const double *y, const double *z, int64_t
 
 /* ==========================================================================
  * Tuning of the mixed-order batch (rbffd_weights with a per-node order and
- * the standard supports n = 12/30/56, FP64), which runs as one persistent
- * launch: blocks_per_cu blocks of 128 threads per compute unit pull tiles
- * from a work queue, largest systems first; groups_per_tile[q] sets the tile
- * size of order m = 2q+2 (in stencils for m = 6, in 2-stencil / 8-stencil
- * wavefront groups for m = 4 / m = 2).  The values only change speed, never
- * results.  This table is the library's only process-wide state; set it
- * before launching (e.g. from the autotuner's saved choice).  NULL restores
- * the defaults {2, {1, 1, 1}}.
+ * the standard supports n = 12/30/56, FP64), in one of two forms:
+ *   per_order = 0: one persistent launch: blocks_per_cu blocks of 128
+ *     threads per compute unit pull tiles from a work queue, largest
+ *     systems first; groups_per_tile[q] sets the tile size of order
+ *     m = 2q+2 (in stencils for m = 6, in 2-stencil / 8-stencil wavefront
+ *     groups for m = 4 / m = 2);
+ *   per_order = 1: one persistent launch per order on the same stream
+ *     (m = 6, 4, 2), each with its single-order kernel's block shape and
+ *     occupancy, order_blocks_per_cu[q] blocks per compute unit walking
+ *     that order's list; nothing is cleared between calls.
+ * When the factors are saved (the adjoint's forward) the one-launch form
+ * runs.  The values only change speed, never results.  This table is the
+ * library's only process-wide state; set it before launching (e.g. from
+ * the autotuner's saved choice).  NULL restores the defaults
+ * {2, {1, 1, 1}, 0, {12, 16, 4}} (the per-order grids: one block per wavefront
+ * slot of each kernel's occupancy).
  * ======================================================================== */
 typedef struct rbffd_batch_tuning {
-    int32_t blocks_per_cu;       /* 1..64 */
-    int32_t groups_per_tile[3];  /* 1..64 each, for m = 2, 4, 6 */
+    int32_t blocks_per_cu;          /* 1..64 */
+    int32_t groups_per_tile[3];     /* 1..64 each, for m = 2, 4, 6 */
+    int32_t per_order;              /* 0 or 1 */
+    int32_t order_blocks_per_cu[3]; /* 1..64 each, for m = 2, 4, 6 */
 } rbffd_batch_tuning;
 int rbffd_batch_tuning_set(const rbffd_batch_tuning *tuning /* host, or NULL */);
 int rbffd_batch_tuning_get(rbffd_batch_tuning *tuning /* host */);

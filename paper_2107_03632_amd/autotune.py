@@ -1,8 +1,9 @@
-"""Autotuner for the persistent mixed-order weights launch.
+"""Autotuner for the mixed-order weights batch.
 
-Times every candidate (blocks per compute unit, tile size per order) of the
-one-launch mixed-order batch on a given node set and keeps the fastest.  The
-tuning only changes speed, never results.  The choice is saved to
+Times every candidate of both forms on a given node set and keeps the
+fastest: the one persistent launch (blocks per compute unit, tile size per
+order) and one persistent launch per order (blocks per compute unit of each
+order's launch).  The tuning only changes speed, never results.  The choice is saved to
 batch_tuning.json next to the library, which the binding applies whenever
 the library is loaded.
 
@@ -28,6 +29,12 @@ CANDIDATES = {
     "gpt4": [1, 2],
     "gpt6": [1, 2],
 }
+# one launch per order: blocks per compute unit for m = 2, 4, 6
+ORDER_CANDIDATES = {
+    "bpc2": [8, 12, 16],
+    "bpc4": [8, 12, 16],
+    "bpc6": [3, 4, 6],
+}
 
 
 def _time_ms(fn, reps: int) -> float:
@@ -45,20 +52,35 @@ def _time_ms(fn, reps: int) -> float:
     return float(np.median(ts))
 
 
-def tune_batch(x, y, nbr, order, reps: int = 3, candidates=CANDIDATES) -> dict:
-    """Time each candidate setting; apply and return the fastest."""
+def tune_batch(x, y, nbr, order, reps: int = 3, candidates=CANDIDATES,
+               order_candidates=ORDER_CANDIDATES) -> dict:
+    """Time each candidate setting of both forms; apply and return the
+    fastest."""
     table = []
     keys = list(candidates)
     for vals in itertools.product(*(candidates[k] for k in keys)):
         c = dict(zip(keys, vals))
-        rb.batch_tuning_set(c["blocks_per_cu"], [c["gpt2"], c["gpt4"], c["gpt6"]])
+        rb.batch_tuning_set(c["blocks_per_cu"], [c["gpt2"], c["gpt4"], c["gpt6"]], 0)
         ms = _time_ms(lambda: rb.rbffd_weights(x, y, nbr, order=order), reps)
-        table.append({**c, "ms": ms})
+        table.append({**c, "per_order": 0, "ms": ms})
+    best1 = min(table, key=lambda r: r["ms"])
+    okeys = list(order_candidates)
+    for vals in itertools.product(*(order_candidates[k] for k in okeys)):
+        c = dict(zip(okeys, vals))
+        rb.batch_tuning_set(best1["blocks_per_cu"], [best1["gpt2"], best1["gpt4"], best1["gpt6"]],
+                            1, [c["bpc2"], c["bpc4"], c["bpc6"]])
+        ms = _time_ms(lambda: rb.rbffd_weights(x, y, nbr, order=order), reps)
+        table.append({**c, "per_order": 1, "ms": ms})
     best = min(table, key=lambda r: r["ms"])
-    choice = {"blocks_per_cu": best["blocks_per_cu"],
-              "groups_per_tile": [best["gpt2"], best["gpt4"], best["gpt6"]]}
-    rb.batch_tuning_set(choice["blocks_per_cu"], choice["groups_per_tile"])
-    return {"choice": choice, "ms": best["ms"], "table": table}
+    best2 = min((r for r in table if r["per_order"] == 1), key=lambda r: r["ms"])
+    choice = {"blocks_per_cu": best1["blocks_per_cu"],
+              "groups_per_tile": [best1["gpt2"], best1["gpt4"], best1["gpt6"]],
+              "per_order": best["per_order"],
+              "order_blocks_per_cu": [best2["bpc2"], best2["bpc4"], best2["bpc6"]]}
+    rb.batch_tuning_set(choice["blocks_per_cu"], choice["groups_per_tile"], choice["per_order"],
+                        choice["order_blocks_per_cu"])
+    return {"choice": choice, "ms": best["ms"], "one_launch_ms": best1["ms"],
+            "per_order_ms": best2["ms"], "table": table}
 
 
 def main(argv=None) -> int:

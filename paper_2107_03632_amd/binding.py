@@ -85,22 +85,34 @@ def _load():
 
 
 class BatchTuning(ctypes.Structure):
-    _fields_ = [("blocks_per_cu", ctypes.c_int32), ("groups_per_tile", ctypes.c_int32 * 3)]
+    _fields_ = [("blocks_per_cu", ctypes.c_int32), ("groups_per_tile", ctypes.c_int32 * 3),
+                ("per_order", ctypes.c_int32), ("order_blocks_per_cu", ctypes.c_int32 * 3)]
 
 
 TUNING_PATH = os.path.join(_HERE, "batch_tuning.json")
+DEFAULT_ORDER_BLOCKS_PER_CU = (12, 16, 4)
 
 
-def batch_tuning_set(blocks_per_cu: int, groups_per_tile) -> None:
-    """Set the persistent mixed-order launch's grid and tile sizes."""
-    t = BatchTuning(int(blocks_per_cu), (ctypes.c_int32 * 3)(*[int(v) for v in groups_per_tile]))
+def _tuning(blocks_per_cu, groups_per_tile, per_order=0,
+            order_blocks_per_cu=DEFAULT_ORDER_BLOCKS_PER_CU) -> BatchTuning:
+    i3 = ctypes.c_int32 * 3
+    return BatchTuning(int(blocks_per_cu), i3(*[int(v) for v in groups_per_tile]),
+                       int(per_order), i3(*[int(v) for v in order_blocks_per_cu]))
+
+
+def batch_tuning_set(blocks_per_cu: int, groups_per_tile, per_order: int = 0,
+                     order_blocks_per_cu=DEFAULT_ORDER_BLOCKS_PER_CU) -> None:
+    """Set the mixed-order batch's form (one launch, or one launch per
+    order) and its grid and tile sizes."""
+    t = _tuning(blocks_per_cu, groups_per_tile, per_order, order_blocks_per_cu)
     _check(_load().rbffd_batch_tuning_set(ctypes.byref(t)), "rbffd_batch_tuning_set")
 
 
 def batch_tuning_get() -> dict:
     t = BatchTuning()
     _check(_load().rbffd_batch_tuning_get(ctypes.byref(t)), "rbffd_batch_tuning_get")
-    return {"blocks_per_cu": t.blocks_per_cu, "groups_per_tile": list(t.groups_per_tile)}
+    return {"blocks_per_cu": t.blocks_per_cu, "groups_per_tile": list(t.groups_per_tile),
+            "per_order": t.per_order, "order_blocks_per_cu": list(t.order_blocks_per_cu)}
 
 
 def _apply_saved_tuning():
@@ -110,8 +122,8 @@ def _apply_saved_tuning():
     import json
     with open(TUNING_PATH) as f:
         cfg = json.load(f)["choice"]
-    t = BatchTuning(int(cfg["blocks_per_cu"]),
-                    (ctypes.c_int32 * 3)(*[int(v) for v in cfg["groups_per_tile"]]))
+    t = _tuning(cfg["blocks_per_cu"], cfg["groups_per_tile"], cfg.get("per_order", 0),
+                cfg.get("order_blocks_per_cu", DEFAULT_ORDER_BLOCKS_PER_CU))
     _check(_lib.rbffd_batch_tuning_set(ctypes.byref(t)), "rbffd_batch_tuning_set")
 
 
@@ -300,9 +312,10 @@ def rbffd_knn3(x, y, z, k: int, out=None):
 
 
 def rbffd_weights3(x, y, z, nbr, m: int = 2, n: int = 20, out=None, status=None, op=None):
-    """Weights of eq. (1) for nodes in R^3 (r^3 + monomials of degree <= 2),
-    FP64: the Laplacian, or with op one of OP_DX, OP_DY, OP3_DZ a first
-    derivative.  Returns (w [N, k_stride], status [N])."""
+    """Weights of eq. (1) for nodes in R^3 (r^3 + monomials of degree <= m,
+    m = 2 with 10 <= n <= 54, or m = 4 with n = 70), FP64: the Laplacian, or
+    with op one of OP_DX, OP_DY, OP3_DZ a first derivative.
+    Returns (w [N, k_stride], status [N])."""
     lib = _load()
     x, y, nbr, N, ks = _nodes2(x, y, nbr)
     z = _vec(z, N, torch.float64, "z")

@@ -291,7 +291,7 @@ Knn3Ws carve3(void *base, int64_t n, int32_t k) {
 using namespace rbffd;
 
 extern "C" int rbffd_knn3_workspace_size(int64_t n_nodes, int32_t k, size_t *bytes) {
-    if (!bytes || n_nodes < 1 || n_nodes >= INT32_MAX || k < 1 || k > 64 || k > n_nodes)
+    if (!bytes || n_nodes < 1 || n_nodes >= INT32_MAX || k < 1 || k > 80 || k > n_nodes)
         return RBFFD_ERR_ARG;
     *bytes = carve3(nullptr, n_nodes, k).bytes;
     return RBFFD_SUCCESS;
@@ -302,7 +302,7 @@ extern "C" int rbffd_knn3(const double *x, const double *y, const double *z, int
                           void *stream) {
     if (!x || !y || !z || !nbr || n_nodes < 1 || n_nodes >= INT32_MAX || k < 1 || k > n_nodes)
         return RBFFD_ERR_ARG;
-    if (k > 64) return RBFFD_ERR_UNSUPPORTED;
+    if (k > 80) return RBFFD_ERR_UNSUPPORTED;
     Knn3Ws w = carve3(nullptr, n_nodes, k);
     if (!workspace || workspace_bytes < w.bytes) return RBFFD_ERR_WORKSPACE;
     w = carve3(workspace, n_nodes, k);
@@ -332,8 +332,11 @@ extern "C" int rbffd_knn3(const double *x, const double *y, const double *z, int
     else if (k <= 32)
         hipLaunchKernelGGL(knn3_query<32>, dim3(nq), dim3(kQ), 0, s, gp, start, ids, xs, ys, zs,
                            n_nodes, k, nbr);
-    else
+    else if (k <= 64)
         hipLaunchKernelGGL(knn3_query<64>, dim3(nq), dim3(kQ), 0, s, gp, start, ids, xs, ys, zs,
+                           n_nodes, k, nbr);
+    else  // the m = 4 support (k = 70)
+        hipLaunchKernelGGL(knn3_query<80>, dim3(nq), dim3(kQ), 0, s, gp, start, ids, xs, ys, zs,
                            n_nodes, k, nbr);
     return last_launch_rc();
 }

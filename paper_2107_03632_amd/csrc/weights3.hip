@@ -2,7 +2,9 @@
 // polyharmonic spline r^3 (lap r^3 = 12 r in 3-D) augmented with the ten
 // monomials of degree <= 2 in (x, y, z), on the node's n nearest neighbours
 // (10 <= n <= 54, so K = n + 10 <= 64), shifted to the node and scaled to a
-// unit stencil.
+// unit stencil.  The standard supports (m = 2, n = 20 and m = 4, n = 70) run
+// the blocked LU of weights_mf.h instead (weights3_k30.hip,
+// weights3_k105_op*.hip).
 //
 // One wavefront per stencil, one row of [A P; P^T 0 | rhs] per lane, in
 // registers.  Rows never move: each lane tracks the position its row holds
@@ -303,7 +305,27 @@ int launch3(const double *x, const double *y, const double *z, int64_t n_nodes,
 }
 
 }  // namespace
+
+// the blocked LU of the matrix cores: K = 30 (m = 2, n = 20) and K = 105
+// (m = 4, n = 70), one translation unit per operator at K = 105
+int weights3_blocked_k30(const double *x, const double *y, const double *z, int64_t n_nodes,
+                         const int32_t *nbr, int32_t k_stride, int op, double *w,
+                         int32_t *status, hipStream_t stream);
+#define RBFFD_W3_K105_DECL(OP)                                                                 \
+    int weights3_blocked_k105_op##OP(const double *x, const double *y, const double *z,        \
+                                     int64_t n_nodes, const int32_t *nbr, int32_t k_stride,    \
+                                     double *w, int32_t *status, hipStream_t stream);
+RBFFD_W3_K105_DECL(0)
+RBFFD_W3_K105_DECL(1)
+RBFFD_W3_K105_DECL(2)
+RBFFD_W3_K105_DECL(3)
+#undef RBFFD_W3_K105_DECL
+
 }  // namespace rbffd
+
+#ifndef RBFFD_W3_K30_BLOCKED
+#define RBFFD_W3_K30_BLOCKED 1
+#endif
 
 using namespace rbffd;
 
@@ -312,10 +334,21 @@ extern "C" int rbffd_weights3_op(const double *x, const double *y, const double 
                                  int32_t m, int32_t n, int32_t op, double *w, int32_t *status,
                                  void *stream) {
     if (!x || !y || !z || !nbr || !w || n_nodes < 1 || n_nodes >= INT32_MAX || k_stride < 1 ||
-        n > k_stride || m != 2 || n < kMono3 || op < 0 || op > 3)
+        n > k_stride || (m != 2 && m != 4) || n < (m == 2 ? kMono3 : 35) || op < 0 || op > 3)
         return RBFFD_ERR_ARG;
-    if (n + kMono3 > 64) return RBFFD_ERR_UNSUPPORTED;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (m == 4) {
+        if (n != 70) return RBFFD_ERR_UNSUPPORTED;
+        switch (op) {
+        case 0: return weights3_blocked_k105_op0(x, y, z, n_nodes, nbr, k_stride, w, status, s);
+        case 1: return weights3_blocked_k105_op1(x, y, z, n_nodes, nbr, k_stride, w, status, s);
+        case 2: return weights3_blocked_k105_op2(x, y, z, n_nodes, nbr, k_stride, w, status, s);
+        default: return weights3_blocked_k105_op3(x, y, z, n_nodes, nbr, k_stride, w, status, s);
+        }
+    }
+    if (RBFFD_W3_K30_BLOCKED && n == 20)
+        return weights3_blocked_k30(x, y, z, n_nodes, nbr, k_stride, op, w, status, s);
+    if (n + kMono3 > 64) return RBFFD_ERR_UNSUPPORTED;
     switch (op) {
     case 0: return launch3<0>(x, y, z, n_nodes, nbr, k_stride, n, w, status, s);
     case 1: return launch3<1>(x, y, z, n_nodes, nbr, k_stride, n, w, status, s);

@@ -1,0 +1,3 @@
+// Three-dimensional weights, m = 4, n = 70: the Laplacian.
+#include "weights3_k105.h"
+RBFFD_W3_K105_INSTANCE(0)

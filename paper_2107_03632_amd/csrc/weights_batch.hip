@@ -104,9 +104,71 @@ __global__ __launch_bounds__(kPB) __attribute__((amdgpu_waves_per_eu(RBFFD_BATCH
     }
 }
 
+// ---- one persistent launch per order ---------------------------------------
+// Each class runs with the block shape, occupancy and LDS of its own
+// single-order kernel; a block walks the class's list with a grid stride
+// (every stencil of a class costs the same, so no work queue and nothing to
+// clear).  The bodies are those of the single-order kernels: same bits.
+
+#ifndef RBFFD_BATCH_OCC84
+#define RBFFD_BATCH_OCC84 2
+#endif
+#ifndef RBFFD_BATCH_OCC45
+#define RBFFD_BATCH_OCC45 4
+#endif
+#ifndef RBFFD_BATCH_OCC18
+#define RBFFD_BATCH_OCC18 3
+#endif
+
+__global__ __launch_bounds__(2 * kWave) __attribute__((amdgpu_waves_per_eu(RBFFD_BATCH_OCC84)))
+void class84_kernel(const double *__restrict__ x, const double *__restrict__ y, int64_t n_nodes,
+                    const int32_t *__restrict__ nbr, int32_t k_stride,
+                    const int32_t *__restrict__ list, const int32_t *__restrict__ count,
+                    double *__restrict__ w, int32_t *__restrict__ status) {
+    __shared__ __align__(16) char lds[wk::mf_lds_bytes<84, 56, 6>(2)];
+    const int64_t c = *count;
+    for (int64_t t = blockIdx.x; t < c; t += gridDim.x) {
+        __syncthreads();  // the previous stencil's LDS is free
+        wk::weights_mf_body<84, 56, 6, 2>(x, y, n_nodes, nbr, k_stride, list, c, w, status,
+                                          RBFFD_OK, t, lds);
+    }
+}
+
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(RBFFD_BATCH_OCC45)))
+void class45_kernel(const double *__restrict__ x, const double *__restrict__ y, int64_t n_nodes,
+                    const int32_t *__restrict__ nbr, int32_t k_stride,
+                    const int32_t *__restrict__ list, const int32_t *__restrict__ count,
+                    double *__restrict__ w, int32_t *__restrict__ status) {
+    __shared__ __align__(16) char lds[wk::mf_lds_bytes<45, 30, 4>(1)];
+    const int64_t c = *count;
+    for (int64_t t = blockIdx.x; t < c; t += gridDim.x) {
+        wk::lds_order();  // one wavefront: its LDS accesses stay in program order
+        wk::weights_mf_body<45, 30, 4, 1>(x, y, n_nodes, nbr, k_stride, list, c, w, status,
+                                          RBFFD_OK, t, lds);
+    }
+}
+
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(RBFFD_BATCH_OCC18)))
+void class18_kernel(const double *__restrict__ x, const double *__restrict__ y, int64_t n_nodes,
+                    const int32_t *__restrict__ nbr, int32_t k_stride,
+                    const int32_t *__restrict__ list, const int32_t *__restrict__ count,
+                    double *__restrict__ w, int32_t *__restrict__ status) {
+    __shared__ __align__(16) char lds[wk::ms_lds_bytes<18, kSeg18, 2, 1>()];
+    const int64_t c = *count;
+    const int64_t groups = ceil_div(c, kG18);
+    for (int64_t g = blockIdx.x; g < groups; g += gridDim.x) {
+        wk::lds_order();
+        wk::weights_ms_body<18, kSeg18, kSl18, 12, 2, 1, false>(
+            x, y, n_nodes, nbr, k_stride, list, c, 12, 2, w, status, nullptr, nullptr, nullptr,
+            nullptr, 0, RBFFD_OK, g, 0, lds);
+    }
+}
+
 // the process-wide tuning table (the library's only mutable state)
 std::atomic<int32_t> g_blocks_per_cu{2};
 std::atomic<int32_t> g_gpt[3] = {{1}, {1}, {1}};
+std::atomic<int32_t> g_per_order{0};
+std::atomic<int32_t> g_order_bpc[3] = {{12}, {16}, {4}};
 
 }  // namespace
 
@@ -121,6 +183,19 @@ int weights_fp64_batch(const double *x, const double *y, int64_t n_nodes, const 
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return hip_rc(e);
+    if (!sv_lu && g_per_order.load()) {
+        // largest systems first
+        const unsigned b6 = (unsigned)(g_order_bpc[2].load() * cus);
+        const unsigned b4 = (unsigned)(g_order_bpc[1].load() * cus);
+        const unsigned b2 = (unsigned)(g_order_bpc[0].load() * cus);
+        hipLaunchKernelGGL(class84_kernel, dim3(b6), dim3(2 * kWave), 0, stream, x, y, n_nodes,
+                           nbr, k_stride, lists + 2 * n_nodes, counts + 2, w, status);
+        hipLaunchKernelGGL(class45_kernel, dim3(b4), dim3(kWave), 0, stream, x, y, n_nodes, nbr,
+                           k_stride, lists + n_nodes, counts + 1, w, status);
+        hipLaunchKernelGGL(class18_kernel, dim3(b2), dim3(kWave), 0, stream, x, y, n_nodes, nbr,
+                           k_stride, lists, counts, w, status);
+        return last_launch_rc();
+    }
     int rc = fill_i32(queue, 0, 1, stream);
     if (rc) return rc;
     const int64_t blocks = (int64_t)g_blocks_per_cu.load() * cus;
@@ -143,13 +218,22 @@ extern "C" int rbffd_batch_tuning_set(const rbffd_batch_tuning *t) {
     if (!t) {
         rbffd::g_blocks_per_cu = 2;
         for (auto &v : rbffd::g_gpt) v = 1;
+        rbffd::g_per_order = 0;
+        rbffd::g_order_bpc[0] = 12;
+        rbffd::g_order_bpc[1] = 16;
+        rbffd::g_order_bpc[2] = 4;
         return RBFFD_SUCCESS;
     }
     if (t->blocks_per_cu < 1 || t->blocks_per_cu > 64) return RBFFD_ERR_ARG;
     for (int q = 0; q < 3; ++q)
-        if (t->groups_per_tile[q] < 1 || t->groups_per_tile[q] > 64) return RBFFD_ERR_ARG;
+        if (t->groups_per_tile[q] < 1 || t->groups_per_tile[q] > 64 ||
+            t->order_blocks_per_cu[q] < 1 || t->order_blocks_per_cu[q] > 64)
+            return RBFFD_ERR_ARG;
+    if (t->per_order != 0 && t->per_order != 1) return RBFFD_ERR_ARG;
     rbffd::g_blocks_per_cu = t->blocks_per_cu;
     for (int q = 0; q < 3; ++q) rbffd::g_gpt[q] = t->groups_per_tile[q];
+    rbffd::g_per_order = t->per_order;
+    for (int q = 0; q < 3; ++q) rbffd::g_order_bpc[q] = t->order_blocks_per_cu[q];
     return RBFFD_SUCCESS;
 }
 
@@ -157,5 +241,7 @@ extern "C" int rbffd_batch_tuning_get(rbffd_batch_tuning *t) {
     if (!t) return RBFFD_ERR_ARG;
     t->blocks_per_cu = rbffd::g_blocks_per_cu.load();
     for (int q = 0; q < 3; ++q) t->groups_per_tile[q] = rbffd::g_gpt[q].load();
+    t->per_order = rbffd::g_per_order.load();
+    for (int q = 0; q < 3; ++q) t->order_blocks_per_cu[q] = rbffd::g_order_bpc[q].load();
     return RBFFD_SUCCESS;
 }

@@ -77,6 +77,7 @@ __device__ __forceinline__ void weights_cs_wave(
         }
     }
     const double sc = sqrt(seg_all_max_d<SEG>(d2m, lane));
+    if (!isfinite(sc)) flags |= F_NONFIN;  // an offset's square overflowed
     if (sc == 0.0) flags |= F_DUP;
 
     // ---- scale; monomial table (written by wavefront 0) --------------------

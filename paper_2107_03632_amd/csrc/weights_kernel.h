@@ -59,6 +59,25 @@ __host__ __device__ constexpr int mono_deg(int j) {
 __host__ __device__ constexpr int mono_b(int j) { return j - mono_deg(j) * (mono_deg(j) + 1) / 2; }
 __host__ __device__ constexpr int mono_a(int j) { return mono_deg(j) - mono_b(j); }
 
+// graded monomial order in three variables (inside a degree the x exponent
+// descending, then the y exponent descending): exponents (a[j], b[j], c[j])
+// of p_j = x^a y^b z^c, j < MM, as a compile-time table (indexed by
+// unrolled loop counters, so every lookup folds to a constant)
+template <int MM>
+struct Mono3Table {
+    int a[MM], b[MM], c[MM];
+    constexpr Mono3Table() : a(), b(), c() {
+        int t = 0;
+        for (int d = 0; t < MM; ++d)
+            for (int ea = d; ea >= 0 && t < MM; --ea)
+                for (int eb = d - ea; eb >= 0 && t < MM; --eb, ++t) {
+                    a[t] = ea;
+                    b[t] = eb;
+                    c[t] = d - ea - eb;
+                }
+    }
+};
+
 template <int W>
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
@@ -255,6 +274,7 @@ __device__ __forceinline__ void weights_fp64_body(
         for (int v = 0; v < NW; ++v) d2max = fmax(d2max, s_red[g][v]);
     }
     const double s = sqrt(d2max);
+    if (!isfinite(s)) flags |= F_NONFIN;  // an offset's square overflowed
     if (s == 0.0) flags |= F_DUP;
 
     // ---- scale; monomials of each support node ---------------------------

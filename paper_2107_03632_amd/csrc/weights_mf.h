@@ -2,7 +2,8 @@
 // RBF-FD Laplacian stencil weights, FP64: LU blocked by panels of four
 // columns with the trailing updates on the matrix cores.  Instances: K = 84
 // (m = 6, n = 56; two wavefronts per stencil) and K = 45 (m = 4, n = 30; one
-// wavefront per stencil).
+// wavefront per stencil) in two dimensions; in three, K = 105 (m = 4,
+// n = 70; several wavefronts per stencil) and K = 30 (m = 2, n = 20).
 //
 // v_mfma_f64_16x16x4f64 forms each output as four fused multiply-adds taken
 // in k order, fma(a3, b3, fma(a2, b2, fma(a1, b1, fma(a0, b0, c)))).  A
@@ -17,7 +18,10 @@
 // zero, padding rows never pivot), in 16 x 16 tiles held transposed as MFMA
 // accumulators: in tile (I, J), lane l = 16 g + j, register r holds row
 // 16 I + j, column 16 J + g + 4 r.  With NW wavefronts per stencil,
-// wavefront w owns the tile columns J = w, w + NW, ... (all tile rows).
+// wavefront w owns the tile columns J = w, w + NW, ... (all tile rows);
+// when NW does not divide NT the last wavefronts own one column fewer.
+// With more than two wavefronts the wavefront's index is a run-time value
+// (one code path for all of them, its branches uniform).
 //
 // The four columns of a panel [c0, c0 + 4) are register (c0 % 16) / 4 of
 // the tiles of column c0 / 16 (column c0 + g in lane group g).  Their owner
@@ -54,23 +58,25 @@ __device__ __forceinline__ void lds_order() {
 }
 
 // LDS of one block: doubles first, then int32.  Panel buffers alternate
-// between consecutive panels when two wavefronts share them.  With one
+// between consecutive panels when several wavefronts share them.  With one
 // wavefront the pivot rows of a panel's end overlay its panel buffer (read
 // out before the rows are written), which keeps K = 45 at 15 wavefronts
-// per CU.
-template <int KP, int MM, int NT, int NW>
+// per CU.  In three dimensions the assembly tables hold a third offset.
+template <int KP, int MM, int NT, int NW, int DIM = 2>
 struct MfLds {
     static constexpr int NP = 16 * NT;
     static constexpr int NPB = NW > 1 ? 2 : 1;       // panel buffers
-    static constexpr int NJT = NT / NW;             // tile columns per wavefront
-    static constexpr int SZ = MsLds<KP, MM>::SZ;    // U triangle / assembly tables
+    static constexpr int NJT = (NT + NW - 1) / NW;  // tile columns per wavefront (at most)
+    static constexpr int ASZ3 = DIM == 3 ? (KP * (MM + 3) + 1) & ~1 : 0;
+    static constexpr int SZ =                        // U triangle / assembly tables
+        MsLds<KP, MM>::SZ > ASZ3 ? MsLds<KP, MM>::SZ : ASZ3;
     static constexpr int PAN = SZ;                  // [NPB][NP][5] panel, row layout (padded)
     static constexpr int UB = NW > 1 ? PAN + NPB * NP * 5 : PAN;  // [NW][NJT][4][16] pivot rows
     static constexpr int DBL =
         NW > 1 ? UB + NW * NJT * 64 : PAN + (NP * 5 > NJT * 64 ? NP * 5 : NJT * 64);
     static constexpr int REC = 0;                   // [NPB][4][2] pivot row, its position
-    static constexpr int FL = 8 * NPB;              // flags of wavefront 1
-    static constexpr int INTS = FL + 2;
+    static constexpr int FL = 8 * NPB;              // flags of wavefronts 1 .. NW - 1
+    static constexpr int INTS = FL + (NW > 2 ? NW - 1 : 2);
     static constexpr int BYTES = 8 * DBL + 4 * INTS;
 };
 
@@ -78,28 +84,43 @@ struct MfLds {
 // adjoint: row r of the factors (its multipliers left of its final
 // position, its row of U from there on) at row r, the row at each position,
 // the unit-scale solution z and the scale s.
-// OP: 0 the Laplacian, 1 d/dx, 2 d/dy (right-hand side and power of the scale).
-template <int KP, int NFIX, int MFIX, int NW, int WV, bool SAVE, int OP = 0>
+// OP: 0 the Laplacian, 1 d/dx, 2 d/dy, 3 d/dz (three dimensions only)
+// (right-hand side and power of the scale).
+// DIM 3: nodes in three dimensions (z non-null); the polyharmonic spline
+// r^3 with lap r^3 = 12 r, the monomials of degree <= MFIX in three
+// variables, each evaluated as (u^a v^b) t^c.
+// WV: this wavefront's index in the block, or -1 for a run-time index.
+template <int KP, int NFIX, int MFIX, int NW, int WV, bool SAVE, int OP = 0, int DIM = 2>
 __device__ __forceinline__ void weights_mf_wave(
-    const double *__restrict__ x, const double *__restrict__ y, int64_t n_nodes,
-    const int32_t *__restrict__ nbr, int32_t k_stride, int64_t i, double *__restrict__ w,
-    int32_t *__restrict__ status, const SaveView &sv, int32_t ok_code, char *lds) {
-    static_assert(!SAVE || NW == 1, "the factors are saved by the one-wavefront instance");
-    constexpr int MM = (MFIX + 1) * (MFIX + 2) / 2, n = NFIX, K = NFIX + MM;
+    const double *__restrict__ x, const double *__restrict__ y, const double *__restrict__ z,
+    int64_t n_nodes, const int32_t *__restrict__ nbr, int32_t k_stride, int64_t i,
+    double *__restrict__ w, int32_t *__restrict__ status, const SaveView &sv, int32_t ok_code,
+    char *lds) {
+    static_assert(!SAVE || (NW == 1 && DIM == 2),
+                  "the factors are saved by the one-wavefront 2-D instance");
+    static_assert(DIM == 2 || DIM == 3, "two or three dimensions");
+    static_assert(OP >= 0 && OP <= DIM, "operator");
+    constexpr int MM = DIM == 2 ? (MFIX + 1) * (MFIX + 2) / 2
+                                : (MFIX + 1) * (MFIX + 2) * (MFIX + 3) / 6;
+    constexpr int n = NFIX, K = NFIX + MM;
     static_assert(K == KP, "no identity padding in the blocked kernel");
     constexpr int NT = (KP + 1 + 15) / 16;  // tiles per dimension (rhs included)
     constexpr int NP = 16 * NT;
     constexpr int SL = (NP + kWave - 1) / kWave;  // rows per lane in row layout
-    static_assert(NT % NW == 0, "tile columns split evenly");
-    constexpr int NJT = NT / NW;
+    static_assert(NW <= 2 ? NT % NW == 0 : WV < 0, "tile columns of the wavefronts");
     using L = MsLds<KP, MM>;
-    using B = MfLds<KP, MM, NT, NW>;
+    using B = MfLds<KP, MM, NT, NW, DIM>;
+    constexpr int NJT = B::NJT;
+    const int wv = WV >= 0 ? WV : __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    // tile columns this wavefront owns: J = NW jt + wv for jt < njt
+    const int njt = WV >= 0 ? NJT : (NT - wv + NW - 1) / NW;
     double *sU = reinterpret_cast<double *>(lds);
     double *s_ux = sU;
     double *s_uy = sU + KP;
-    double(*s_P)[MM] = reinterpret_cast<double(*)[MM]>(sU + 2 * KP);
+    double *s_uz = sU + 2 * KP;  // (three dimensions)
+    double(*s_P)[MM] = reinterpret_cast<double(*)[MM]>(sU + DIM * KP);
     double(*s_pan)[NP][5] = reinterpret_cast<double(*)[NP][5]>(sU + B::PAN);
-    double(*s_ub)[4][16] = reinterpret_cast<double(*)[4][16]>(sU + B::UB + WV * NJT * 64);
+    double(*s_ub)[4][16] = reinterpret_cast<double(*)[4][16]>(sU + B::UB + wv * NJT * 64);
     int32_t *si = reinterpret_cast<int32_t *>(lds + 8 * B::DBL);
     int32_t(*s_rec)[4][2] = reinterpret_cast<int32_t(*)[4][2]>(si + B::REC);
     uint32_t *s_fl = reinterpret_cast<uint32_t *>(si + B::FL);
@@ -109,34 +130,40 @@ __device__ __forceinline__ void weights_mf_wave(
 
     // ---- shift and scale (row order: rows lane, lane + 64) -----------------
     uint32_t flags = 0;
-    double dx[SL], dy[SL];
+    double dx[SL], dy[SL], dz[SL];
     double d2m = 0.0;
     const double xi = x[i], yi = y[i];
+    const double zi = DIM == 3 ? z[i] : 0.0;
 #pragma unroll
     for (int s = 0; s < SL; ++s) {
         const int r = lane + kWave * s;
         dx[s] = 0.0;
         dy[s] = 0.0;
+        dz[s] = 0.0;
         if (r < n) {
             const int32_t j = nbr[i * (int64_t)k_stride + r];
             if (j < 0 || (int64_t)j >= n_nodes) {
                 flags |= F_BADIDX;
             } else {
                 const double ddx = x[j] - xi, ddy = y[j] - yi;
-                if (!isfinite(ddx) || !isfinite(ddy)) {
+                const double ddz = DIM == 3 ? z[j] - zi : 0.0;
+                if (!isfinite(ddx) || !isfinite(ddy) || (DIM == 3 && !isfinite(ddz))) {
                     flags |= F_NONFIN;
                 } else {
                     dx[s] = ddx;
                     dy[s] = ddy;
-                    const double d2 = ddx * ddx + ddy * ddy;
+                    dz[s] = ddz;
+                    const double d2 = DIM == 3 ? (ddx * ddx + ddy * ddy) + ddz * ddz
+                                               : ddx * ddx + ddy * ddy;
                     d2m = fmax(d2m, d2);
                 }
             }
         }
     }
     const double sc = sqrt(seg_all_max_d<kWave>(d2m, lane));
+    if (!isfinite(sc)) flags |= F_NONFIN;  // an offset's square overflowed
     if (sc == 0.0) flags |= F_DUP;
-    if (WV == 0) {
+    if (wv == 0) {
 #pragma unroll
         for (int s = 0; s < SL; ++s) {
             const int r = lane + kWave * s;
@@ -144,16 +171,35 @@ __device__ __forceinline__ void weights_mf_wave(
                 const double ux = dx[s] / sc, uy = dy[s] / sc;
                 s_ux[r] = ux;
                 s_uy[r] = uy;
-                double px[7], py[7];
-                px[0] = 1.0;
-                py[0] = 1.0;
+                if constexpr (DIM == 2) {
+                    double px[7], py[7];
+                    px[0] = 1.0;
+                    py[0] = 1.0;
 #pragma unroll
-                for (int e = 1; e < 7; ++e) {
-                    px[e] = px[e - 1] * ux;
-                    py[e] = py[e - 1] * uy;
+                    for (int e = 1; e < 7; ++e) {
+                        px[e] = px[e - 1] * ux;
+                        py[e] = py[e - 1] * uy;
+                    }
+#pragma unroll
+                    for (int j = 0; j < MM; ++j) s_P[r][j] = px[mono_a(j)] * py[mono_b(j)];
+                } else {
+                    const double uz = dz[s] / sc;
+                    s_uz[r] = uz;
+                    double px[MFIX + 1], py[MFIX + 1], pt[MFIX + 1];
+                    px[0] = 1.0;
+                    py[0] = 1.0;
+                    pt[0] = 1.0;
+#pragma unroll
+                    for (int e = 1; e <= MFIX; ++e) {
+                        px[e] = px[e - 1] * ux;
+                        py[e] = py[e - 1] * uy;
+                        pt[e] = pt[e - 1] * uz;
+                    }
+                    constexpr Mono3Table<MM> e3{};
+#pragma unroll
+                    for (int j = 0; j < MM; ++j)
+                        s_P[r][j] = (px[e3.a[j]] * py[e3.b[j]]) * pt[e3.c[j]];
                 }
-#pragma unroll
-                for (int j = 0; j < MM; ++j) s_P[r][j] = px[mono_a(j)] * py[mono_b(j)];
             }
         }
     }
@@ -174,19 +220,28 @@ __device__ __forceinline__ void weights_mf_wave(
         const int jr = qrow ? R - n : 0;
         const double uxr = (16 * I < n && prow) ? s_ux[R] : 0.0;
         const double uyr = (16 * I < n && prow) ? s_uy[R] : 0.0;
+        const double uzr = (DIM == 3 && 16 * I < n && prow) ? s_uz[R] : 0.0;
 #pragma unroll
         for (int jt = 0; jt < NJT; ++jt) {
-            const int J = NW * jt + WV;
+            const int J = NW * jt + wv;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int C = 16 * J + g + 4 * r;
                 double v = 0.0;
-                if (16 * J < n && C < n) {
+                if (jt >= njt) {
+                    // (no such tile column)
+                } else if (16 * J < n && C < n) {
                     double phs = 0.0;
                     if (16 * I < n) {
                         const double ex = uxr - s_ux[C];
                         const double ey = uyr - s_uy[C];
-                        const double rr = ex * ex + ey * ey;
+                        double rr;
+                        if constexpr (DIM == 2) {
+                            rr = ex * ex + ey * ey;
+                        } else {
+                            const double ez = uzr - s_uz[C];
+                            rr = (ex * ex + ey * ey) + ez * ez;
+                        }
                         if (prow && C != R && rr == 0.0) flags |= F_DUP;
                         asm volatile("" : "+v"(flags));
                         phs = rr * sqrt(rr);
@@ -196,11 +251,19 @@ __device__ __forceinline__ void weights_mf_wave(
                 } else if (16 * J + 15 >= n && 16 * J < K && C >= n && C < K) {
                     v = prow ? s_P[prow ? R : 0][C - n] : 0.0;
                 } else if (16 * J + 15 >= KP && 16 * J <= KP && C == KP) {
-                    const double r0 = uxr * uxr + uyr * uyr;
-                    const double rb =
-                        OP == 0 ? 9.0 * sqrt(r0) : -3.0 * sqrt(r0) * (OP == 1 ? uxr : uyr);
-                    const double rq =
-                        OP == 0 ? ((jr == 3 || jr == 5) ? 2.0 : 0.0) : (jr == OP ? 1.0 : 0.0);
+                    double rb, rq;
+                    if constexpr (DIM == 2) {
+                        const double r0 = uxr * uxr + uyr * uyr;
+                        rb = OP == 0 ? 9.0 * sqrt(r0) : -3.0 * sqrt(r0) * (OP == 1 ? uxr : uyr);
+                        rq = OP == 0 ? ((jr == 3 || jr == 5) ? 2.0 : 0.0) : (jr == OP ? 1.0 : 0.0);
+                    } else {
+                        // lap r^3 = 12 r in 3-D; lap of x^2, y^2, z^2 (j = 4, 7, 9) is 2
+                        const double r0 = (uxr * uxr + uyr * uyr) + uzr * uzr;
+                        rb = OP == 0 ? 12.0 * sqrt(r0)
+                                     : -3.0 * sqrt(r0) * (OP == 1 ? uxr : (OP == 2 ? uyr : uzr));
+                        rq = OP == 0 ? ((jr == 4 || jr == 7 || jr == 9) ? 2.0 : 0.0)
+                                     : (jr == OP ? 1.0 : 0.0);
+                    }
                     v = prow ? rb : (qrow ? rq : 0.0);
                 }
                 T[I][jt][r] = v;
@@ -232,7 +295,7 @@ __device__ __forceinline__ void weights_mf_wave(
         const int J0 = c0 >> 4;                  // tile column of the panel
         const int rc = (c0 & 15) >> 2;           // its register
         const int nk = KP - c0 < 4 ? KP - c0 : 4;  // column steps in the panel
-        if (J0 % NW == WV) {
+        if (J0 % NW == wv) {
             const int jt0 = J0 / NW;
             // the panel to row layout through LDS: pc[s][j] = row lane + 64 s,
             // column c0 + j
@@ -349,7 +412,7 @@ __device__ __forceinline__ void weights_mf_wave(
 #pragma unroll
         for (int k = 0; k < 4; ++k)
             if (k < nk) pr[k] = __builtin_amdgcn_readfirstlane(s_rec[pb][k][0]);
-        if (J0 % NW != WV) {
+        if (J0 % NW != wv) {
             // the owner's row bookkeeping, replayed
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
@@ -368,9 +431,9 @@ __device__ __forceinline__ void weights_mf_wave(
             }
         }
         // first tile column of this wavefront that still has trailing columns
-        const int first_jt = (J0 % NW == WV) ? ((rc < 3) ? J0 / NW : J0 / NW + 1)
-                                             : (J0 + 1) / NW;
-        if (first_jt < NJT) {  // (a partial panel is the last: nothing trails it)
+        const int first_jt = (J0 % NW == wv) ? ((rc < 3) ? J0 / NW : J0 / NW + 1)
+                                             : (J0 - wv + NW) / NW;
+        if (first_jt < njt) {  // (a partial panel is the last: nothing trails it)
             // multipliers of the panel's pivot rows in its earlier columns
             double l11[4][3];
 #pragma unroll
@@ -394,7 +457,9 @@ __device__ __forceinline__ void weights_mf_wave(
                         if (I == Ipk) {
 #pragma unroll
                             for (int jt = 0; jt < NJT; ++jt)
-                                if (jt >= first_jt) {
+                                // (with a run-time wavefront index every tile
+                                // column: fewer branches, the extra rows unread)
+                                if (WV < 0 || (jt >= first_jt && jt < njt)) {
 #pragma unroll
                                     for (int r = 0; r < 4; ++r)
                                         s_ub[jt][k][g + 4 * r] = T[I][jt][r];
@@ -409,16 +474,17 @@ __device__ __forceinline__ void weights_mf_wave(
             }
             lds_order();
             // the tile column of the next panel first: its updates are the
-            // ones the next column steps wait for
+            // ones the next column steps wait for (with a run-time wavefront
+            // index simply in order)
             const int J0n = (c0 + 4) >> 4;
-            const int jtn = (J0n % NW == WV && c0 + 4 < KP) ? J0n / NW : -1;
+            const int jtn = (J0n % NW == wv && c0 + 4 < KP) ? J0n / NW : -1;
 #pragma unroll
-            for (int pass = 0; pass < 2; ++pass) {
+            for (int pass = 0; pass < (WV < 0 ? 1 : 2); ++pass) {
 #pragma unroll
                 for (int jt = 0; jt < NJT; ++jt) {
-                    if (jt < first_jt) continue;
-                    if ((pass == 0) != (jt == jtn)) continue;
-                    const int J = NW * jt + WV;
+                    if (jt < first_jt || jt >= njt) continue;
+                    if (WV >= 0 && (pass == 0) != (jt == jtn)) continue;
+                    const int J = NW * jt + wv;
                     const int i0 = (J == J0) ? 4 * rc + 4 : 0;  // first trailing column in the tile
                     const double r0 = s_ub[jt][0][jl], r1 = s_ub[jt][1][jl];
                     const double r2 = s_ub[jt][2][jl], r3 = s_ub[jt][3][jl];
@@ -442,11 +508,12 @@ __device__ __forceinline__ void weights_mf_wave(
     }
     uint32_t fl = seg_all<kWave, OpOr>(flags, lane);
     if constexpr (NW > 1) {
-        // wavefront 1's flags to wavefront 0
-        if (WV == 1 && lane == 0) *s_fl = fl;
+        // the other wavefronts' flags to wavefront 0
+        if (wv != 0 && lane == 0) s_fl[wv - 1] = fl;
         __syncthreads();  // the rows of U and the flags are visible
-        if (WV != 0) return;
-        fl |= *s_fl;
+        if (wv != 0) return;
+#pragma unroll
+        for (int v = 0; v < NW - 1; ++v) fl |= s_fl[v];
     } else {
         lds_order();
     }
@@ -525,12 +592,13 @@ __device__ __forceinline__ void weights_mf_body(
     int64_t t, char *lds, const SaveView &sv = SaveView{}) {
     if (t >= n_rows) return;  // whole block idle
     const int64_t i = rows ? (int64_t)rows[t] : t;
+    static_assert(NW <= 2, "two-dimensional instances: one or two wavefronts");
     if (NW > 1 && ((threadIdx.x >> 6) & 1))
-        weights_mf_wave<KP, NFIX, MFIX, NW, NW - 1, SAVE, OP>(x, y, n_nodes, nbr, k_stride, i, w,
-                                                         status, sv, ok_code, lds);
+        weights_mf_wave<KP, NFIX, MFIX, NW, NW - 1, SAVE, OP>(x, y, nullptr, n_nodes, nbr,
+                                                         k_stride, i, w, status, sv, ok_code, lds);
     else
-        weights_mf_wave<KP, NFIX, MFIX, NW, 0, SAVE, OP>(x, y, n_nodes, nbr, k_stride, i, w, status,
-                                                     sv, ok_code, lds);
+        weights_mf_wave<KP, NFIX, MFIX, NW, 0, SAVE, OP>(x, y, nullptr, n_nodes, nbr, k_stride, i,
+                                                     w, status, sv, ok_code, lds);
 }
 
 template <int KP, int NFIX, int MFIX>
@@ -576,6 +644,48 @@ inline int launch_mf(const double *x, const double *y, int64_t n_nodes, const in
     hipLaunchKernelGGL((weights_mf_kernel<KP, NFIX, MFIX, NW, OCC, false, OP>),
                        dim3((unsigned)n_rows), dim3(NW * kWave), 0, stream, x, y, n_nodes, nbr,
                        k_stride, rows, n_rows_dev, n_rows, w, status, SaveView{}, ok_code);
+    return last_launch_rc();
+}
+
+// Three dimensions: one block of NW wavefronts per stencil (node i = block
+// index), no row list, no saved factors.
+template <int KP, int NFIX, int MFIX, int NW>
+__host__ __device__ constexpr int mf3_lds_bytes() {
+    constexpr int MM = (MFIX + 1) * (MFIX + 2) * (MFIX + 3) / 6;
+    constexpr int NT = (KP + 1 + 15) / 16;
+    return MfLds<KP, MM, NT, NW, 3>::BYTES;
+}
+
+template <int KP, int NFIX, int MFIX, int NW, int OCC, int OP>
+__global__ __launch_bounds__(NW * kWave)
+__attribute__((amdgpu_waves_per_eu(OCC))) void weights_mf3_kernel(
+    const double *__restrict__ x, const double *__restrict__ y, const double *__restrict__ z,
+    int64_t n_nodes, const int32_t *__restrict__ nbr, int32_t k_stride, double *__restrict__ w,
+    int32_t *__restrict__ status) {
+    __shared__ __align__(16) char lds[mf3_lds_bytes<KP, NFIX, MFIX, NW>()];
+    const int64_t i = (int64_t)blockIdx.x;
+    if constexpr (NW <= 2) {
+        if (NW > 1 && ((threadIdx.x >> 6) & 1))
+            weights_mf_wave<KP, NFIX, MFIX, NW, NW - 1, false, OP, 3>(
+                x, y, z, n_nodes, nbr, k_stride, i, w, status, SaveView{}, RBFFD_OK, lds);
+        else
+            weights_mf_wave<KP, NFIX, MFIX, NW, 0, false, OP, 3>(
+                x, y, z, n_nodes, nbr, k_stride, i, w, status, SaveView{}, RBFFD_OK, lds);
+    } else {
+        weights_mf_wave<KP, NFIX, MFIX, NW, -1, false, OP, 3>(
+            x, y, z, n_nodes, nbr, k_stride, i, w, status, SaveView{}, RBFFD_OK, lds);
+    }
+}
+
+template <int KP, int NFIX, int MFIX, int NW, int OCC, int OP>
+inline int launch_mf3(const double *x, const double *y, const double *z, int64_t n_nodes,
+                      const int32_t *nbr, int32_t k_stride, double *w, int32_t *status,
+                      hipStream_t stream) {
+    if (n_nodes <= 0) return RBFFD_SUCCESS;
+    if (n_nodes > 0x7fffffff) return RBFFD_ERR_UNSUPPORTED;
+    hipLaunchKernelGGL((weights_mf3_kernel<KP, NFIX, MFIX, NW, OCC, OP>),
+                       dim3((unsigned)n_nodes), dim3(NW * kWave), 0, stream, x, y, z, n_nodes,
+                       nbr, k_stride, w, status);
     return last_launch_rc();
 }
 

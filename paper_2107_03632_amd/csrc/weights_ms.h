@@ -262,6 +262,7 @@ __device__ __forceinline__ void weights_ms_body(
         }
     }
     const double sc = sqrt(seg_all_max_d<SEG>(d2m, lane));
+    if (!isfinite(sc)) flags |= F_NONFIN;  // an offset's square overflowed
     if (sc == 0.0) flags |= F_DUP;
 
     // ---- scale; monomial table --------------------------------------------

@@ -100,6 +100,7 @@ __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1))) void weights_mx_kernel(
             }
         }
         const double sc = sqrt(seg_all_max_d<SEG>(d2m, lane));
+        if (!isfinite(sc)) flags |= F_NONFIN;  // an offset's square overflowed
         if (sc == 0.0) flags |= F_DUP;
         double ux[SL], uy[SL];
 #pragma unroll

@@ -53,7 +53,7 @@ def lattice_with_ties():
     return x, y, z
 
 
-@pytest.mark.parametrize("k", [1, 10, 20, 27, 45, 64])
+@pytest.mark.parametrize("k", [1, 10, 20, 27, 45, 64, 70, 80])
 def test_knn3_bit_exact(k):
     x, y, z = nodes.jittered_cube(12, seed=21)
     say("knn3 cube 1728", k)
@@ -84,10 +84,10 @@ def test_knn3_flat_and_tiny():
                           oracle.knn3(x, y, z, 6))
 
 
-def check_weights3(x, y, z, nbr, n, label):
-    w_ref, st_ref = oracle.weights3(x, y, z, nbr, 2, n)
-    say(label, "n", n, "stencils", nbr.shape[0], "statuses", np.bincount(st_ref))
-    w, st = rb.rbffd_weights3(dev(x), dev(y), dev(z), dev(nbr), 2, n)
+def check_weights3(x, y, z, nbr, n, label, m=2):
+    w_ref, st_ref = oracle.weights3(x, y, z, nbr, m, n)
+    say(label, "m", m, "n", n, "stencils", nbr.shape[0], "statuses", np.bincount(st_ref))
+    w, st = rb.rbffd_weights3(dev(x), dev(y), dev(z), dev(nbr), m, n)
     w, st = host(w), host(st)
     assert np.array_equal(st, st_ref)
     ok = st_ref == 0
@@ -141,8 +141,12 @@ def test_weights3_argument_errors():
     X, Y, Z, NB = dev(x), dev(y), dev(z), dev(nbr)
     with pytest.raises(rb.RbffdError, match=r"-3"):      # K = 70 > 64
         rb.rbffd_weights3(X, Y, Z, NB, 2, 60)
-    with pytest.raises(rb.RbffdError, match=r"-1"):      # only m = 2
+    with pytest.raises(rb.RbffdError, match=r"-3"):      # m = 4: the support n = 70 only
         rb.rbffd_weights3(X, Y, Z, NB, 4, 40)
+    with pytest.raises(rb.RbffdError, match=r"-1"):      # m = 2 or 4
+        rb.rbffd_weights3(X, Y, Z, NB, 3, 40)
+    with pytest.raises(rb.RbffdError, match=r"-1"):      # m = 4: n below 35 monomials
+        rb.rbffd_weights3(X, Y, Z, NB, 4, 30)
     with pytest.raises(rb.RbffdError, match=r"-1"):      # n below the monomial count
         rb.rbffd_weights3(X, Y, Z, NB, 2, 9)
     with pytest.raises(rb.RbffdError, match=r"-1"):      # n above the row stride
@@ -226,3 +230,93 @@ def test_weights3_op_argument_errors():
     nbr = np.ascontiguousarray(oracle.knn3(x, y, z, 20))
     with pytest.raises(rb.RbffdError, match=r"-1"):
         rb.rbffd_weights3(dev(x), dev(y), dev(z), dev(nbr), 2, 20, op=4)
+
+
+# ---- m = 4 (K = 105, the blocked LU on the matrix cores) ------------------
+
+MONOS4 = [(a, b, d - a - b) for d in range(5) for a in range(d, -1, -1)
+          for b in range(d - a, -1, -1)]
+
+
+@pytest.mark.parametrize("ks", [70, 80])
+def test_weights3_m4_bit_exact(ks):
+    x, y, z = nodes.jittered_cube(11, seed=22)
+    nbr = oracle.knn3(x, y, z, 80)
+    check_weights3(x, y, z, np.ascontiguousarray(nbr[:, :ks]), 70,
+                   f"cube 1331, k_stride {ks}", m=4)
+
+
+def test_weights3_m4_lattice_ties():
+    g = np.arange(9, dtype=np.float64) / 8.0
+    Z, Y, X = np.meshgrid(g, g, g, indexing="ij")
+    x, y, z = X.ravel().copy(), Y.ravel().copy(), Z.ravel().copy()
+    nbr = np.ascontiguousarray(oracle.knn3(x, y, z, 70))
+    check_weights3(x, y, z, nbr, 70, "exact lattice 729", m=4)
+
+
+def test_weights3_m4_status_codes():
+    x, y, z = nodes.jittered_cube(7, seed=23)
+    x, y, z = np.append(x, 1e200), np.append(y, 0.5), np.append(z, 0.5)
+    nbr = oracle.knn3(x, y, z, 70)
+    nb = nbr.copy()
+    nb[3, 4] = nb[3, 2]             # duplicate support node
+    nb[4, 7] = len(x) + 1           # out of range
+    nb[5, 69] = -1
+    nb[7, 69] = len(x) - 1          # a node 1e200 away: the scale overflows
+    xx = x.copy()
+    xx[nbr[6, 5]] = np.inf          # non-finite coordinate
+    w, st = check_weights3(xx, y, z, nb, 70, "status codes", m=4)
+    assert np.all(st[3:8] != 0) and st[7] == oracle.NONFINITE and st[-1] == oracle.NONFINITE
+    # coplanar supports: the z monomials vanish -> zero pivot
+    rng = np.random.default_rng(6)
+    xp, yp = rng.random(300), rng.random(300)
+    zp = np.full(300, 0.5)
+    nbp = np.ascontiguousarray(oracle.knn3(xp, yp, zp, 70))
+    w, st = check_weights3(xp, yp, zp, nbp, 70, "coplanar", m=4)
+    assert np.all(st == oracle.SINGULAR)
+
+
+@pytest.mark.parametrize("op,oop,axis", D3)
+def test_weights3_m4_derivatives_bit_exact(op, oop, axis):
+    x, y, z = nodes.jittered_cube(10, seed=26)
+    nbr = oracle.knn3(x, y, z, 72)
+    w_ref, st_ref = oracle.weights3_op(x, y, z, nbr, 4, 70, oop)
+    say("3-D derivative m = 4", axis)
+    w, st = rb.rbffd_weights3(dev(x), dev(y), dev(z), dev(nbr), 4, 70, op=op)
+    w, st = host(w), host(st)
+    assert np.array_equal(st, st_ref)
+    assert np.array_equal(w, w_ref, equal_nan=True)
+
+
+def test_3d_m4_full_size_sampled():
+    """The jittered 100^3 lattice, k = n = 70: kNN and weights of sampled
+    rows against the oracle, and every row's weights applied to the 35
+    monomials of degree <= 4 about its centre (on the device)."""
+    x, y, z = nodes.jittered_cube(100, seed=6)
+    N = x.shape[0]
+    say("3-D cube", N, "m = 4, k = n = 70")
+    X, Y, Z = dev(x), dev(y), dev(z)
+    nb_t = rb.rbffd_knn3(X, Y, Z, 70)
+    rows = np.sort(np.random.default_rng(28).choice(N, 120, replace=False))
+    nbr_rows = host(nb_t[torch.as_tensor(rows).cuda()])
+    assert np.array_equal(nbr_rows, oracle.knn3(x, y, z, 70, queries=rows))
+    w_t, st_t = rb.rbffd_weights3(X, Y, Z, nb_t, 4, 70)
+    st = host(st_t)
+    assert np.all(st == 0)
+    # the oracle on the sampled rows (their supports: the rows above)
+    nbr_s = np.zeros((N, 70), np.int32)
+    nbr_s[rows] = nbr_rows
+    w_ref, st_ref = oracle.weights3(x, y, z, nbr_s, 4, 70, rows=rows)
+    assert np.all(st_ref == 0)
+    assert np.array_equal(host(w_t[torch.as_tensor(rows).cuda()]), w_ref)
+    nbl = nb_t.long()
+    dx, dy, dz = X[nbl] - X[:, None], Y[nbl] - Y[:, None], Z[nbl] - Z[:, None]
+    worst = 0.0
+    for (a, b, c) in MONOS4:
+        f = dx ** a * dy ** b * dz ** c
+        want = 2.0 if sorted((a, b, c)) == [0, 0, 2] else 0.0
+        wf = w_t * f
+        rel = (wf.sum(1) - want).abs() / (wf.abs().sum(1) + want)
+        worst = max(worst, rel.max().item())
+    say("  worst relative residual over the 35 monomials", worst)
+    assert worst < 1e-9

@@ -38,14 +38,19 @@ def test_batch_tuning_changes_nothing_but_speed():
     saved = rb.batch_tuning_get()
     outs = []
     try:
-        for bpc, gpt in [(1, [1, 1, 1]), (2, [4, 2, 2]), (4, [2, 1, 2]), (3, [1, 2, 1])]:
-            rb.batch_tuning_set(bpc, gpt)
-            assert rb.batch_tuning_get() == {"blocks_per_cu": bpc, "groups_per_tile": gpt}
+        for bpc, gpt, po, obpc in [(1, [1, 1, 1], 0, [12, 16, 4]), (2, [4, 2, 2], 0, [1, 1, 1]),
+                                   (4, [2, 1, 2], 0, [12, 16, 4]), (3, [1, 2, 1], 0, [12, 16, 4]),
+                                   (2, [1, 1, 1], 1, [12, 16, 4]), (2, [1, 1, 1], 1, [1, 1, 1]),
+                                   (2, [1, 1, 1], 1, [64, 3, 7])]:
+            rb.batch_tuning_set(bpc, gpt, po, obpc)
+            assert rb.batch_tuning_get() == {"blocks_per_cu": bpc, "groups_per_tile": gpt,
+                                             "per_order": po, "order_blocks_per_cu": obpc}
             w, st, _ = rb.rbffd_weights(X, Y, NB, order=O)
             torch.cuda.synchronize()
             outs.append((w.cpu().numpy(), st.cpu().numpy()))
     finally:
-        rb.batch_tuning_set(saved["blocks_per_cu"], saved["groups_per_tile"])
+        rb.batch_tuning_set(saved["blocks_per_cu"], saved["groups_per_tile"],
+                            saved["per_order"], saved["order_blocks_per_cu"])
     for w, st in outs[1:]:
         assert np.array_equal(w, outs[0][0]) and np.array_equal(st, outs[0][1])
     w_ref, st_ref = oracle.weights(ns.x, ns.y, nbr, order=ns.order)
@@ -56,9 +61,24 @@ def test_batch_tuning_changes_nothing_but_speed():
         assert e.max() <= 1e-11
     with pytest.raises(rb.RbffdError):
         rb.batch_tuning_set(0, [1, 1, 1])
+    with pytest.raises(rb.RbffdError):
+        rb.batch_tuning_set(2, [1, 1, 1], 2)
+    with pytest.raises(rb.RbffdError):
+        rb.batch_tuning_set(2, [1, 1, 1], 1, [1, 65, 1])
+    assert rb.batch_tuning_get() == saved
 
 
-def test_pipeline_graph_capture_and_replay():
+@pytest.fixture(params=[0, 1], ids=["one_launch", "per_order"])
+def batch_form(request):
+    saved = rb.batch_tuning_get()
+    rb.batch_tuning_set(saved["blocks_per_cu"], saved["groups_per_tile"], request.param,
+                        saved["order_blocks_per_cu"])
+    yield request.param
+    rb.batch_tuning_set(saved["blocks_per_cu"], saved["groups_per_tile"], saved["per_order"],
+                        saved["order_blocks_per_cu"])
+
+
+def test_pipeline_graph_capture_and_replay(batch_form):
     ns = nodes.cell_centred_square(100, seed=3, order_seed=33)
     X, Y, O = dev(ns.x), dev(ns.y), dev(ns.order)
     B = dev((np.arange(ns.n_nodes) % 23 == 0).astype(np.uint8))
@@ -101,7 +121,7 @@ def test_pipeline_graph_capture_and_replay():
         same(other, eager)
 
 
-def test_batch_full_size_sampled():
+def test_batch_full_size_sampled(batch_form):
     # the 1M-node mixed-order square in the launch the benchmark times: every
     # status clean, sampled rows equal to the oracle's weights bit for bit
     ns = nodes.workload("square_1m_mixed")

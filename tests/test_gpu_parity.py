@@ -152,6 +152,32 @@ def test_weights_status_codes():
     assert np.all(np.isnan(host(w)))
 
 
+@pytest.mark.parametrize("m,n", [(2, 12), (4, 30), (6, 56), (4, 40), (2, 20)])
+def test_weights_overflowing_offset(m, n):
+    """A support node 1e200 away (its offset's square overflows, the scale
+    is +inf): every kernel fails the stencil NONFINITE as the oracle does,
+    in FP64, with the factors saved and in mixed precision."""
+    ns = nodes.unit_square(14, seed=4)
+    x = np.append(ns.x, 1e200)
+    y = np.append(ns.y, 0.5)
+    nbr = np.ascontiguousarray(oracle.knn(x, y, n))  # the far node's own stencil too
+    rows = [5, 17, 40]
+    nbr[rows, n - 1] = x.size - 1
+    w_ref, st_ref = oracle.weights(x, y, nbr, m=m, n=n)
+    assert np.all(st_ref[rows] == oracle.NONFINITE) and st_ref[-1] == oracle.NONFINITE
+    variants = [{}]
+    if (m, n) in ((2, 12), (4, 30), (6, 56)):
+        variants += [{"save": True}, {"precision": rb.MIXED}]
+    for kw in variants:
+        say("overflowing offset", m, n, kw)
+        w, st, _ = rb.rbffd_weights(dev(x), dev(y), dev(nbr), m=m, n=n, **kw)
+        w, st = host(w), host(st)
+        if "precision" in kw:
+            st = np.where(st == rb.FELL_BACK_FP64, 0, st)
+        assert np.array_equal(st, st_ref), kw
+        assert np.array_equal(np.isnan(w[:, :n]), np.isnan(w_ref[:, :n])), kw
+
+
 def test_weights_mixed_order_matches_oracle():
     ns = nodes.cell_centred_square(60, seed=3, order_seed=33)
     say("weights mixed order", ns.n_nodes)

@@ -73,7 +73,7 @@ def test_knn3_ties_python_sort():
         assert nb[i].tolist() == want, i
 
 
-@pytest.mark.parametrize("m,n", [(2, 20), (3, 30), (4, 45)])
+@pytest.mark.parametrize("m,n", [(2, 20), (3, 30), (4, 45), (4, 70)])
 def test_weights3_reproduce_polynomials(m, n):
     x, y, z = jittered_cube(8, seed=5)
     nb = oracle.knn3(x, y, z, n)
@@ -96,10 +96,10 @@ def test_weights3_reproduce_polynomials(m, n):
     assert abs(np.dot(w[3], f)) > 1e-6 * np.abs(w[3] * f).sum()
 
 
-@pytest.mark.parametrize("m", [2, 3])
+@pytest.mark.parametrize("m", [2, 3, 4])
 def test_weights3_laplacian_of_phs_interpolant(m):
     import mpmath
-    n = {2: 20, 3: 30}[m]
+    n = {2: 20, 3: 30, 4: 70}[m]
     x, y, z = jittered_cube(7, seed=9)
     nb = oracle.knn3(x, y, z, n)
     rng = np.random.default_rng(8)
@@ -177,7 +177,7 @@ D3 = [(oracle.D3_DX, (1, 0, 0)), (oracle.D3_DY, (0, 1, 0)), (oracle.D3_DZ, (0, 0
 
 
 @pytest.mark.parametrize("op,axis", D3)
-@pytest.mark.parametrize("m,n", [(2, 20), (3, 30)])
+@pytest.mark.parametrize("m,n", [(2, 20), (3, 30), (4, 70)])
 def test_weights3_derivative_reproduce_polynomials(op, axis, m, n):
     x, y, z = jittered_cube(8, seed=15)
     nb = oracle.knn3(x, y, z, n)

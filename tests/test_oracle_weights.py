@@ -200,6 +200,31 @@ def test_status_codes():
     assert (st[4] == oracle.OK) == (nbr[13, 2] not in nb[14])
 
 
+def test_overflowing_offset_is_nonfinite():
+    """A finite offset whose square overflows (|dx| = 1e200): the scale
+    s = sqrt(max |x_k - x_i|^2) is +inf, not a number the stencil can be
+    scaled by, and the status is NONFINITE, in two and three dimensions.
+    At 1e150 (square 1e300, finite) the scale is finite and the stencil
+    goes on to the factorisation (the other nodes, scaled by 1e-150, then
+    make it singular)."""
+    ns = nodes.unit_square(6, seed=2)
+    nbr = oracle.knn(ns.x, ns.y, 12)
+    for far, want in ((1e200, oracle.NONFINITE), (1e150, oracle.SINGULAR)):
+        x = np.append(ns.x, far)
+        y = np.append(ns.y, 0.5)
+        nb = np.vstack([nbr, nbr[:1]]).astype(np.int32)
+        nb[7, 11] = x.size - 1
+        w, st = oracle.weights(x, y, nb, m=2, n=12, rows=[7, 8])
+        assert st[0] == want and st[1] == oracle.OK
+        assert np.all(np.isnan(w[0]))
+        z = np.zeros_like(x)
+        z[:-1] = np.random.default_rng(3).random(x.size - 1)
+        nb3 = np.ascontiguousarray(oracle.knn3(x, y, z, 20))
+        nb3[7, 19] = x.size - 1
+        w3, st3 = oracle.weights3(x, y, z, nb3, 2, 20, rows=[7])
+        assert st3[0] == want and np.all(np.isnan(w3[0]))
+
+
 def test_singular_collinear_support():
     # six nodes on a line: y, xy, y^2 columns of P vanish exactly
     x = np.linspace(0.0, 1.0, 6)
