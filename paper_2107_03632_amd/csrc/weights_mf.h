@@ -621,6 +621,33 @@ __attribute__((amdgpu_waves_per_eu(OCC))) void weights_mf_kernel(
                                               status, ok_code, (int64_t)blockIdx.x, lds, sv);
 }
 
+// A row list counted on the device (the mixed path's fallbacks, the
+// per-order lists of a mixed-order batch): the host knows only an upper
+// bound, so a grid of at most kListBlocks blocks walks the list with a
+// stride.  An empty or short list then costs a few thousand idle blocks, not
+// one per node (1M idle blocks took 0.21 ms).
+constexpr int64_t kListBlocks = 8192;
+
+template <int KP, int NFIX, int MFIX, int NW, int OCC, int OP>
+__global__ __launch_bounds__(NW * kWave)
+__attribute__((amdgpu_waves_per_eu(OCC))) void weights_mf_list_kernel(
+    const double *__restrict__ x, const double *__restrict__ y, int64_t n_nodes,
+    const int32_t *__restrict__ nbr, int32_t k_stride, const int32_t *__restrict__ rows,
+    const int32_t *__restrict__ n_rows_dev, double *__restrict__ w,
+    int32_t *__restrict__ status, int32_t ok_code) {
+    __shared__ __align__(16) char lds[mf_lds_bytes<KP, NFIX, MFIX>(NW)];
+    const int64_t c = *n_rows_dev;
+    for (int64_t t = blockIdx.x; t < c; t += gridDim.x) {
+        // the previous stencil's LDS is free
+        if constexpr (NW > 1)
+            __syncthreads();
+        else
+            lds_order();
+        weights_mf_body<KP, NFIX, MFIX, NW, false, OP>(x, y, n_nodes, nbr, k_stride, rows, c, w,
+                                                   status, ok_code, t, lds);
+    }
+}
+
 // sv.lu set: the saving instance (one wavefront per stencil only).
 template <int KP, int NFIX, int MFIX, int NW, int OCC, int OP = 0>
 inline int launch_mf(const double *x, const double *y, int64_t n_nodes, const int32_t *nbr,
@@ -640,6 +667,13 @@ inline int launch_mf(const double *x, const double *y, int64_t n_nodes, const in
         }
     } else {
         if (sv.lu) return RBFFD_ERR_UNSUPPORTED;
+    }
+    if (n_rows_dev) {
+        const int64_t blocks = n_rows < kListBlocks ? n_rows : kListBlocks;
+        hipLaunchKernelGGL((weights_mf_list_kernel<KP, NFIX, MFIX, NW, OCC, OP>),
+                           dim3((unsigned)blocks), dim3(NW * kWave), 0, stream, x, y, n_nodes,
+                           nbr, k_stride, rows, n_rows_dev, w, status, ok_code);
+        return last_launch_rc();
     }
     hipLaunchKernelGGL((weights_mf_kernel<KP, NFIX, MFIX, NW, OCC, false, OP>),
                        dim3((unsigned)n_rows), dim3(NW * kWave), 0, stream, x, y, n_nodes, nbr,

@@ -577,6 +577,29 @@ weights_ms_kernel(
                                                       (int64_t)blockIdx.x, 0, lds);
 }
 
+// A row list counted on the device: at most kMsListBlocks blocks walk its
+// groups with a stride (see weights_mf_list_kernel).
+constexpr int64_t kMsListBlocks = 8192;
+
+template <int KP, int SEG, int SL, int NFIX, int MFIX, int OCC, int OP>
+__global__ __launch_bounds__(kWave)
+__attribute__((amdgpu_waves_per_eu(OCC <= 0 ? 1 : OCC))) void weights_ms_list_kernel(
+    const double *__restrict__ x, const double *__restrict__ y, int64_t n_nodes,
+    const int32_t *__restrict__ nbr, int32_t k_stride, const int32_t *__restrict__ rows,
+    const int32_t *__restrict__ n_rows_dev, int32_t n_arg, int32_t m_arg,
+    double *__restrict__ w, int32_t *__restrict__ status, int32_t ok_code) {
+    __shared__ __align__(16) char lds[ms_lds_bytes<KP, SEG, MFIX, 1>()];
+    constexpr int GPB = kWave / SEG;
+    const int64_t c = *n_rows_dev;
+    const int64_t groups = (c + GPB - 1) / GPB;
+    for (int64_t g = blockIdx.x; g < groups; g += gridDim.x) {
+        wave_sync();  // the previous group's LDS is free
+        weights_ms_body<KP, SEG, SL, NFIX, MFIX, 1, false, OP>(
+            x, y, n_nodes, nbr, k_stride, rows, c, n_arg, m_arg, w, status, nullptr, nullptr,
+            nullptr, nullptr, 0, ok_code, g, 0, lds);
+    }
+}
+
 template <int KP, int SEG, int SL, int NFIX, int MFIX, int OCC = 0, int OP = 0>
 inline int launch_ms(const double *x, const double *y, int64_t n_nodes, const int32_t *nbr,
                      int32_t k_stride, const int32_t *rows, const int32_t *n_rows_dev,
@@ -587,6 +610,13 @@ inline int launch_ms(const double *x, const double *y, int64_t n_nodes, const in
     const int64_t blocks = ceil_div(n_rows, GPB);
     if (blocks > 0x7fffffff) return RBFFD_ERR_UNSUPPORTED;
     if (sv.lu && OP != 0) return RBFFD_ERR_UNSUPPORTED;  // factors: the Laplacian only
+    if (n_rows_dev && !sv.lu) {
+        const int64_t lb = blocks < kMsListBlocks ? blocks : kMsListBlocks;
+        hipLaunchKernelGGL((weights_ms_list_kernel<KP, SEG, SL, NFIX, MFIX, OCC, OP>),
+                           dim3((unsigned)lb), dim3(kWave), 0, stream, x, y, n_nodes, nbr,
+                           k_stride, rows, n_rows_dev, n, m, w, status, ok_code);
+        return last_launch_rc();
+    }
     if (sv.lu)
         hipLaunchKernelGGL((weights_ms_kernel<KP, SEG, SL, NFIX, MFIX, OCC, true, OP>),
                            dim3((unsigned)blocks), dim3(kWave), 0, stream, x, y, n_nodes, nbr,
