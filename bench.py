@@ -342,15 +342,27 @@ def main():
     if not args.no_extras:
         out["implicit_solve_unit_disk"] = extras_solve(torch, rb, nodes, dev, X, Y, B, U, F,
                                                        ns, m, n)
-        out["per_order_1M_square"] = extras_per_order(torch, rb, nodes, dev, stream)
-        out["adjoint_annulus_200k_m4"] = extras_adjoint(torch, rb, nodes, dev, stream)
-        out["time_loop_unit_disk"] = extras_time_loop(torch, rb, nodes, dev, stream)
-        out["time_loop_cache_sweep"] = extras_time_loop_sweep(torch, rb, nodes, dev, stream)
-        out["derivative_weights_unit_disk"] = extras_ops(torch, rb, stream, X, Y, ns, m, n)
-        out["laplacian_3d_cube_1m"] = extras_3d(torch, rb, nodes, dev, stream)
+        stages = [
+            ("per_order_1M_square", lambda: extras_per_order(torch, rb, nodes, dev, stream)),
+            ("adjoint_annulus_200k_m4", lambda: extras_adjoint(torch, rb, nodes, dev, stream)),
+            ("time_loop_unit_disk", lambda: extras_time_loop(torch, rb, nodes, dev, stream)),
+            ("time_loop_cache_sweep",
+             lambda: extras_time_loop_sweep(torch, rb, nodes, dev, stream)),
+            ("derivative_weights_unit_disk",
+             lambda: extras_ops(torch, rb, stream, X, Y, ns, m, n)),
+            ("laplacian_3d_cube_1m", lambda: extras_3d(torch, rb, nodes, dev, stream)),
+        ]
+        for name, fn in stages:
+            t_stage = time.perf_counter()
+            out[name] = fn()
+            print(f"bench: {name} done in {time.perf_counter() - t_stage:.1f} s",
+                  file=sys.stderr, flush=True)
 
     if not args.no_cpu_baseline:
+        t_stage = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(ns, m, n, args.cpu_stride)
+        print(f"bench: cpu_baseline done in {time.perf_counter() - t_stage:.1f} s",
+              file=sys.stderr, flush=True)
 
     print(json.dumps(out), flush=True)
 
@@ -683,14 +695,22 @@ def extras_time_loop_sweep(torch, rb, nodes, dev, stream, dt=1e-6):
             nbr = nbr60[:, :n].contiguous()
             w, st, _ = rb.rbffd_weights(X, Y, nbr, m=2, n=n)
             ws = torch.empty(ns.n_nodes * n * 12 + 1024, dtype=torch.uint8, device=dev)
-            ms = timed(torch, stream, lambda: rb.rbffd_time_steps(
-                nbr, w, n, f, u, dt, steps, is_boundary=B, u_work=work, workspace=ws))
+            run = (lambda: rb.rbffd_time_steps(nbr, w, n, f, u, dt, steps, is_boundary=B,
+                                                u_work=work, workspace=ws))
+            ms = timed(torch, stream, run)
             per = ms / steps
             nbytes = ns.n_nodes * (8 * (4 + n) + 4 * (1 + n))
-            res.append({"n_nodes": ns.n_nodes, "n": n, "steps": steps,
-                        "us_per_step": per * 1e3, "model_bytes": nbytes,
-                        "gb_per_s": nbytes / (per * 1e-3) / 1e9,
-                        "node_updates_per_s": ns.n_nodes / (per * 1e-3)})
+            row = {"n_nodes": ns.n_nodes, "n": n, "steps": steps,
+                   "us_per_step": per * 1e3, "model_bytes": nbytes,
+                   "gb_per_s": nbytes / (per * 1e-3) / 1e9,
+                   "node_updates_per_s": ns.n_nodes / (per * 1e-3)}
+            if ns.n_nodes <= 300_000:
+                # the same steps replayed from a captured graph: no host
+                # launch between steps
+                per_g = graph_timed(torch, run) / steps
+                row["us_per_step_graph"] = per_g * 1e3
+                row["gb_per_s_graph"] = nbytes / (per_g * 1e-3) / 1e9
+            res.append(row)
             del w, ws
         del nbr60
     return res

@@ -200,7 +200,7 @@ int rbffd_weights_op(const double *x, const double *y, int64_t n_nodes, const in
  * rbffd_knn3: N(x) in R^3, as rbffd_knn: the k nearest nodes (self first),
  * ascending by (d2, index) with d2 = fl(fl(fl(dx^2) + fl(dy^2)) + fl(dz^2)),
  * NaN keys never taken, -1 for unfillable slots.  nbr: [n_nodes][k] int32
- * out.  1 <= k <= min(80, n_nodes) (k > 80: RBFFD_ERR_UNSUPPORTED from
+ * out.  1 <= k <= min(128, n_nodes) (k > 128: RBFFD_ERR_UNSUPPORTED from
  * rbffd_knn3, RBFFD_ERR_ARG from the workspace query).
  * Workspace from rbffd_knn3_workspace_size (cell grid, cell-sorted copy of
  * the nodes).

@@ -7,13 +7,15 @@
 //      host-known maximum;
 //   3. counting sort of the nodes by cell; queries stream the sorted copy of
 //      (x, y, z, id);
-//   4. one thread per query, in cell order; cells are visited shell by
-//      shell around the query's cell (the cells at Chebyshev distance R)
-//      and the k best keys (d2, j), d2 = fl(fl(fl(dx*dx) + fl(dy*dy)) +
-//      fl(dz*dz)), are kept sorted in registers.  The search stops once the
-//      k-th key lies strictly inside the visited block (with a margin far
-//      above rounding error).  The keys are unique, so the result does not
-//      depend on the order in which candidates are met.
+//   4. queries in cell order: one thread per query for k <= 32, one
+//      wavefront per query above; cells are visited shell by shell around
+//      the query's cell (the cells at Chebyshev distance R) and the k best
+//      keys (d2, j), d2 = fl(fl(fl(dx*dx) + fl(dy*dy)) + fl(dz*dz)), are kept
+//      sorted (in one thread's registers, or spread over the wavefront).
+//      The search stops once the k-th key lies strictly inside the visited
+//      block (with a margin far above rounding error).  The keys are unique,
+//      so the result does not depend on the order in which candidates are
+//      met.
 
 #include <float.h>
 
@@ -258,6 +260,193 @@ __global__ __launch_bounds__(kQ) void knn3_query(const Grid3 *__restrict__ gpp,
         if (s >= KMAX - k) out[s - (KMAX - k)] = top.j[s] == INT32_MAX ? -1 : top.j[s];
 }
 
+// ---- large k: one wavefront per query -------------------------------------
+// The k best keys form one sorted list spread over the wavefront: position
+// p = 64 h + lane (h < H, capacity 64 H).  Candidates are examined 64 at a
+// time (lane l takes the l-th of the chunk, so the loads are contiguous);
+// every candidate of the chunk that precedes the current k-th key is
+// inserted in turn: each position compares it with its key, and the keys
+// from its place on shift one position up (from the lane below, or from
+// lane 63 of the previous h).  The control flow is uniform over the
+// wavefront.  A per-lane register list (knn3_query) instead needs three
+// registers per slot and, whenever any lane inserts, runs its insertion in
+// every lane.
+
+constexpr int kCoopWaves = 4;  // queries (wavefronts) per block
+
+__device__ __forceinline__ double bcast3_d(double v, int lane) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// the value of the lane below (lane 0 receives lane 63's: the caller
+// replaces it)
+__device__ __forceinline__ int32_t from_below_i(int32_t v, int lane) {
+    return __builtin_amdgcn_ds_bpermute(((lane + 63) & 63) << 2, v);
+}
+__device__ __forceinline__ double from_below_d(double v, int lane) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)from_below_i((int32_t)(uint32_t)b, lane);
+    const uint32_t hi = (uint32_t)from_below_i((int32_t)(uint32_t)(b >> 32), lane);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+template <int H>
+struct WaveList {
+    double d[H];
+    int32_t j[H];
+
+    __device__ __forceinline__ void init() {
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+            d[h] = __builtin_inf();
+            j[h] = INT32_MAX;
+        }
+    }
+    // key at position q (uniform)
+    __device__ __forceinline__ void at(int q, double &kd, int32_t &kj) const {
+        const int l = q & 63, hq = q >> 6;
+        double vd = d[0];
+        int32_t vj = j[0];
+#pragma unroll
+        for (int h = 1; h < H; ++h)
+            if (hq == h) {
+                vd = d[h];
+                vj = j[h];
+            }
+        kd = bcast3_d(vd, l);
+        kj = __builtin_amdgcn_readlane(vj, l);
+    }
+    // insert (cd, cj), a key that precedes position k - 1's; keys are
+    // unique, so the positions it precedes form a suffix
+    __device__ __forceinline__ void insert(double cd, int32_t cj, int lane) {
+        bool lt[H];
+#pragma unroll
+        for (int h = 0; h < H; ++h) lt[h] = key_less(cd, cj, d[h], j[h]);
+        double pd[H];
+        int32_t pj[H];
+        bool plt[H];
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+            pd[h] = from_below_d(d[h], lane);
+            pj[h] = from_below_i(j[h], lane);
+            plt[h] = from_below_i(lt[h] ? 1 : 0, lane) != 0;
+            if (lane == 0) {
+                // position 64 h - 1: lane 63 of the previous h (none for h = 0)
+                if (h == 0) {
+                    plt[h] = false;
+                } else {
+                    pd[h] = bcast3_d(d[h - 1], 63);
+                    pj[h] = __builtin_amdgcn_readlane(j[h - 1], 63);
+                    plt[h] = __builtin_amdgcn_readlane(lt[h - 1] ? 1 : 0, 63) != 0;
+                }
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+            d[h] = plt[h] ? pd[h] : (lt[h] ? cd : d[h]);
+            j[h] = plt[h] ? pj[h] : (lt[h] ? cj : j[h]);
+        }
+    }
+};
+
+template <int H>
+__device__ __forceinline__ void scan3_wave(WaveList<H> &top, double &wd, int32_t &wj, int kq,
+                                           int p0, int p1, double qx, double qy, double qz,
+                                           const int32_t *__restrict__ ids,
+                                           const double *__restrict__ xs,
+                                           const double *__restrict__ ys,
+                                           const double *__restrict__ zs, int lane) {
+    for (int base = p0; base < p1; base += kWave) {
+        const int p = base + lane;
+        double cd = __builtin_inf();
+        int32_t cj = INT32_MAX;
+        bool take = false;
+        if (p < p1) {
+            const double dx = xs[p] - qx;
+            const double dy = ys[p] - qy;
+            const double dz = zs[p] - qz;
+            cd = (dx * dx + dy * dy) + dz * dz;
+            cj = ids[p];
+            take = key_less(cd, cj, wd, wj);
+        }
+        uint64_t m = __ballot(take);
+        while (m) {
+            const int src = __ffsll((unsigned long long)m) - 1;
+            m &= m - 1;
+            const double vd = bcast3_d(cd, src);
+            const int32_t vj = __builtin_amdgcn_readlane(cj, src);
+            if (!key_less(vd, vj, wd, wj)) continue;  // the k-th key moved since
+            top.insert(vd, vj, lane);
+            top.at(kq, wd, wj);
+        }
+    }
+}
+
+template <int H>
+__global__ __launch_bounds__(kCoopWaves * kWave) void knn3_query_wave(
+    const Grid3 *__restrict__ gpp, const int32_t *__restrict__ start,
+    const int32_t *__restrict__ ids, const double *__restrict__ xs,
+    const double *__restrict__ ys, const double *__restrict__ zs, int64_t n, int32_t k,
+    int32_t *__restrict__ nbr) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t t = (int64_t)blockIdx.x * kCoopWaves + (threadIdx.x >> 6);
+    if (t >= n) return;  // whole wavefronts
+    const Grid3 gp = *gpp;
+    const int32_t qi = ids[t];
+    const double qx = xs[t], qy = ys[t], qz = zs[t];
+    WaveList<H> top;
+    top.init();
+    double wd = __builtin_inf();  // the current k-th key
+    int32_t wj = INT32_MAX;
+    const int kq = k - 1;
+    const int cx = coord3(qx, gp.xmin, gp.inv_cs, gp.gx);
+    const int cy = coord3(qy, gp.ymin, gp.inv_cs, gp.gy);
+    const int cz = coord3(qz, gp.zmin, gp.inv_cs, gp.gz);
+    const int max_r = max(gp.gx, max(gp.gy, gp.gz));
+    const double margin = 1e-6 * gp.cs;
+    for (int R = 0; R <= max_r; ++R) {
+        const int x0 = cx - R, x1 = cx + R, y0 = cy - R, y1 = cy + R, z0 = cz - R, z1 = cz + R;
+        const int xa = max(x0, 0), xb = min(x1, gp.gx - 1);
+        const int ya = max(y0, 0), yb = min(y1, gp.gy - 1);
+        const int za = max(z0, 0), zb = min(z1, gp.gz - 1);
+        for (int zz = za; zz <= zb; ++zz) {
+            for (int yy = ya; yy <= yb; ++yy) {
+                const int row = (zz * gp.gy + yy) * gp.gx;
+                if (zz == z0 || zz == z1 || yy == y0 || yy == y1) {
+                    scan3_wave<H>(top, wd, wj, kq, start[row + xa], start[row + xb + 1], qx, qy,
+                                  qz, ids, xs, ys, zs, lane);
+                } else {
+                    if (x0 >= 0)
+                        scan3_wave<H>(top, wd, wj, kq, start[row + x0], start[row + x0 + 1], qx,
+                                      qy, qz, ids, xs, ys, zs, lane);
+                    if (x1 < gp.gx)
+                        scan3_wave<H>(top, wd, wj, kq, start[row + x1], start[row + x1 + 1], qx,
+                                      qy, qz, ids, xs, ys, zs, lane);
+                }
+            }
+        }
+        double lb = __builtin_inf();
+        if (x0 > 0) lb = fmin(lb, qx - (gp.xmin + x0 * gp.cs));
+        if (x1 < gp.gx - 1) lb = fmin(lb, (gp.xmin + (x1 + 1) * gp.cs) - qx);
+        if (y0 > 0) lb = fmin(lb, qy - (gp.ymin + y0 * gp.cs));
+        if (y1 < gp.gy - 1) lb = fmin(lb, (gp.ymin + (y1 + 1) * gp.cs) - qy);
+        if (z0 > 0) lb = fmin(lb, qz - (gp.zmin + z0 * gp.cs));
+        if (z1 < gp.gz - 1) lb = fmin(lb, (gp.zmin + (z1 + 1) * gp.cs) - qz);
+        if (lb == __builtin_inf()) break;  // the whole grid has been visited
+        lb -= margin;
+        if (wj != INT32_MAX && lb > 0.0 && wd < lb * lb) break;
+    }
+    int32_t *out = nbr + (int64_t)qi * k;
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        const int q = kWave * h + lane;
+        if (q < k) out[q] = top.j[h] == INT32_MAX ? -1 : top.j[h];
+    }
+}
+
 struct Knn3Ws {
     Grid3 *gp;
     double *part;
@@ -291,7 +480,7 @@ Knn3Ws carve3(void *base, int64_t n, int32_t k) {
 using namespace rbffd;
 
 extern "C" int rbffd_knn3_workspace_size(int64_t n_nodes, int32_t k, size_t *bytes) {
-    if (!bytes || n_nodes < 1 || n_nodes >= INT32_MAX || k < 1 || k > 80 || k > n_nodes)
+    if (!bytes || n_nodes < 1 || n_nodes >= INT32_MAX || k < 1 || k > 128 || k > n_nodes)
         return RBFFD_ERR_ARG;
     *bytes = carve3(nullptr, n_nodes, k).bytes;
     return RBFFD_SUCCESS;
@@ -302,7 +491,7 @@ extern "C" int rbffd_knn3(const double *x, const double *y, const double *z, int
                           void *stream) {
     if (!x || !y || !z || !nbr || n_nodes < 1 || n_nodes >= INT32_MAX || k < 1 || k > n_nodes)
         return RBFFD_ERR_ARG;
-    if (k > 80) return RBFFD_ERR_UNSUPPORTED;
+    if (k > 128) return RBFFD_ERR_UNSUPPORTED;
     Knn3Ws w = carve3(nullptr, n_nodes, k);
     if (!workspace || workspace_bytes < w.bytes) return RBFFD_ERR_WORKSPACE;
     w = carve3(workspace, n_nodes, k);
@@ -332,11 +521,17 @@ extern "C" int rbffd_knn3(const double *x, const double *y, const double *z, int
     else if (k <= 32)
         hipLaunchKernelGGL(knn3_query<32>, dim3(nq), dim3(kQ), 0, s, gp, start, ids, xs, ys, zs,
                            n_nodes, k, nbr);
-    else if (k <= 64)
-        hipLaunchKernelGGL(knn3_query<64>, dim3(nq), dim3(kQ), 0, s, gp, start, ids, xs, ys, zs,
-                           n_nodes, k, nbr);
-    else  // the m = 4 support (k = 70)
-        hipLaunchKernelGGL(knn3_query<80>, dim3(nq), dim3(kQ), 0, s, gp, start, ids, xs, ys, zs,
-                           n_nodes, k, nbr);
+    else {
+        // one wavefront per query (k = 70: the m = 4 support); on the 1M-node
+        // cube against per-lane register lists of 64 / 80 slots: k = 33
+        // 6.2 ms (8.1), k = 64 11.2 ms (14.4), k = 70 20.5 ms (36.0)
+        const unsigned nw = (unsigned)ceil_div(n_nodes, kCoopWaves);
+        if (k <= 64)
+            hipLaunchKernelGGL(knn3_query_wave<1>, dim3(nw), dim3(kCoopWaves * kWave), 0, s, gp,
+                               start, ids, xs, ys, zs, n_nodes, k, nbr);
+        else
+            hipLaunchKernelGGL(knn3_query_wave<2>, dim3(nw), dim3(kCoopWaves * kWave), 0, s, gp,
+                               start, ids, xs, ys, zs, n_nodes, k, nbr);
+    }
     return last_launch_rc();
 }

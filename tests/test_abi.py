@@ -93,8 +93,8 @@ def test_argument_errors_before_any_launch(lib):
                                               ctypes.POINTER(ctypes.c_size_t)]
     sz3 = ctypes.c_size_t(0)
     assert lib.rbffd_knn3_workspace_size(1000, 20, ctypes.byref(sz3)) == 0 and sz3.value > 0
-    assert lib.rbffd_knn3_workspace_size(1000, 80, ctypes.byref(sz3)) == 0
-    assert lib.rbffd_knn3_workspace_size(1000, 81, ctypes.byref(sz3)) == -1
+    assert lib.rbffd_knn3_workspace_size(1000, 128, ctypes.byref(sz3)) == 0
+    assert lib.rbffd_knn3_workspace_size(1000, 129, ctypes.byref(sz3)) == -1
     sz = ctypes.c_size_t(0)
     lib.rbffd_solve_workspace_size.argtypes = [ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]
     assert lib.rbffd_solve_workspace_size(1000, ctypes.byref(sz)) == 0

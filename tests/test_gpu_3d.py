@@ -53,7 +53,7 @@ def lattice_with_ties():
     return x, y, z
 
 
-@pytest.mark.parametrize("k", [1, 10, 20, 27, 45, 64, 70, 80])
+@pytest.mark.parametrize("k", [1, 10, 20, 27, 33, 45, 64, 65, 70, 80, 100, 128])
 def test_knn3_bit_exact(k):
     x, y, z = nodes.jittered_cube(12, seed=21)
     say("knn3 cube 1728", k)
@@ -62,7 +62,7 @@ def test_knn3_bit_exact(k):
     assert np.array_equal(got, ref)
 
 
-@pytest.mark.parametrize("k", [7, 20, 33])
+@pytest.mark.parametrize("k", [7, 20, 33, 70, 128])
 def test_knn3_ties_dups_nan(k):
     x, y, z = lattice_with_ties()
     say("knn3 lattice 343 with ties", k)
@@ -82,6 +82,10 @@ def test_knn3_flat_and_tiny():
     x, y, z = rng.random((3, 6))
     assert np.array_equal(host(rb.rbffd_knn3(dev(x), dev(y), dev(z), 6)),
                           oracle.knn3(x, y, z, 6))
+    # exactly k nodes with the one-wavefront-per-query kernel (k > 32)
+    x, y, z = rng.random((3, 90))
+    assert np.array_equal(host(rb.rbffd_knn3(dev(x), dev(y), dev(z), 90)),
+                          oracle.knn3(x, y, z, 90))
 
 
 def check_weights3(x, y, z, nbr, n, label, m=2):

@@ -110,3 +110,36 @@ def test_time_loop_bit_exact_mid_size(n_target):
                             is_boundary=dev(ns.is_boundary))
         torch.cuda.synchronize()
         assert np.array_equal(u.cpu().numpy(), ref), f"N={ns.n_nodes} steps={steps}"
+
+
+def test_time_loop_graph_replay():
+    """The step loop captured in a graph: every replay (u reset eagerly
+    between replays) gives the oracle's bits."""
+    ns = nodes.unit_disk(3000, 200, seed=14)
+    nbr, w, f, u0 = _problem(ns, 2, 12)
+    steps = 7
+    ref = oracle.time_steps(nbr, w, 12, f, u0, 1e-6, steps, is_boundary=ns.is_boundary)
+    NB, W, F, B = dev(nbr), dev(w), dev(f), dev(ns.is_boundary)
+    U0 = dev(u0)
+    u = U0.clone()
+    work = torch.empty_like(u)
+    ws = torch.empty(ns.n_nodes * 12 * 12 + 1024, dtype=torch.uint8, device="cuda")
+
+    def run():
+        rb.rbffd_time_steps(NB, W, 12, F, u, 1e-6, steps, is_boundary=B, u_work=work,
+                            workspace=ws)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        run()  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        run()
+    for rep in range(3):
+        u.copy_(U0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(u.cpu().numpy(), ref), rep
