@@ -180,8 +180,8 @@ int rbffd_weights(const double *x, const double *y, int64_t n_nodes,
  * Same operation sequence, pivoting, status codes and layouts as
  * rbffd_weights (x, y [n_nodes]; nbr [n_nodes][k_stride]; w out
  * [n_nodes][k_stride], zero past n; status [n_nodes] or NULL).  The
- * derivative operators exist for the standard supports (m, n) = (2, 12),
- * (4, 30), (6, 56) (RBFFD_ERR_UNSUPPORTED otherwise), FP64, all nodes.
+ * derivative operators take any support with K = n + (m+1)(m+2)/2 <= 96
+ * (RBFFD_ERR_UNSUPPORTED above), FP64, all nodes.
  * Errors: RBFFD_ERR_ARG for null pointers, an op outside the list, m not in
  * {2, 4, 6}, n < (m+1)(m+2)/2 or n > k_stride.  No workspace.
  * ======================================================================== */

@@ -209,7 +209,8 @@ struct Shape {
 
 // One block (G/64 wavefronts, or one wavefront holding 64/G groups) computes
 // the stencils of block-group `grp` of the row list.
-template <int KP, int G, int NFIX, int MFIX>
+// OP: 0 the Laplacian, 1 d/dx, 2 d/dy (right-hand side and power of the scale).
+template <int KP, int G, int NFIX, int MFIX, int OP = 0>
 __device__ __forceinline__ void weights_fp64_body(
     const double *__restrict__ x, const double *__restrict__ y, int64_t n_nodes,
     const int32_t *__restrict__ nbr, int32_t k_stride, const int32_t *__restrict__ rows,
@@ -322,8 +323,9 @@ __device__ __forceinline__ void weights_fp64_body(
     double yv;
     {
         const double r0 = ux * ux + uy * uy;
-        const double rb = 9.0 * sqrt(r0);
-        yv = prow ? rb : ((qrow && (jr == 3 || jr == 5)) ? 2.0 : 0.0);
+        const double rb = OP == 0 ? 9.0 * sqrt(r0) : -3.0 * sqrt(r0) * (OP == 1 ? ux : uy);
+        const bool one = OP == 0 ? (jr == 3 || jr == 5) : jr == OP;
+        yv = prow ? rb : ((qrow && one) ? (OP == 0 ? 2.0 : 1.0) : 0.0);
     }
 
     // materialise the flags here: otherwise the duplicate checks sink to the
@@ -463,7 +465,8 @@ __device__ __forceinline__ void weights_fp64_body(
     if (!valid) return;
     double *wi = w + i * (int64_t)k_stride;
     const bool good = st == RBFFD_OK;
-    if (pos < n) wi[pos] = good ? zmine / (s * s) : __builtin_nan("");
+    const double s2 = OP == 0 ? s * s : s;  // the operator's power of the scale
+    if (pos < n) wi[pos] = good ? zmine / s2 : __builtin_nan("");
     for (int q = n + r; q < k_stride; q += G) wi[q] = 0.0;
     if (r == 0 && status) status[i] = good ? ok_code : st;
     if (sv_lu) {
@@ -485,7 +488,7 @@ __device__ __forceinline__ void weights_fp64_body(
 
 // OCC: minimum waves per SIMD the register allocation must allow (0: the
 // compiler's choice).
-template <int KP, int G, int NFIX, int MFIX, int OCC>
+template <int KP, int G, int NFIX, int MFIX, int OCC, int OP = 0>
 __global__ __launch_bounds__(block_threads(G))
 __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1))) void weights_fp64_kernel(
     const double *__restrict__ x, const double *__restrict__ y, int64_t n_nodes,
@@ -495,9 +498,9 @@ __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1))) void weights_fp64_kernel
     double *__restrict__ sv_z, double *__restrict__ sv_s, uint8_t *__restrict__ sv_perm,
     int32_t sv_kmax, int32_t ok_code) {
     if (n_rows_dev) n_rows = *n_rows_dev;
-    weights_fp64_body<KP, G, NFIX, MFIX>(x, y, n_nodes, nbr, k_stride, rows, n_rows, n_arg, m_arg,
-                                         w, status, sv_lu, sv_z, sv_s, sv_perm, sv_kmax, ok_code,
-                                         (int64_t)blockIdx.x);
+    weights_fp64_body<KP, G, NFIX, MFIX, OP>(x, y, n_nodes, nbr, k_stride, rows, n_rows, n_arg,
+                                             m_arg, w, status, sv_lu, sv_z, sv_s, sv_perm,
+                                             sv_kmax, ok_code, (int64_t)blockIdx.x);
 }
 
 struct SaveView {
@@ -506,16 +509,17 @@ struct SaveView {
     int32_t kmax = 0;
 };
 
-template <int KP, int G, int NFIX, int MFIX, int OCC = 0>
+template <int KP, int G, int NFIX, int MFIX, int OCC = 0, int OP = 0>
 inline int launch_fp64(const double *x, const double *y, int64_t n_nodes, const int32_t *nbr,
                        int32_t k_stride, const int32_t *rows, const int32_t *n_rows_dev,
                        int64_t n_rows, int n, int m, double *w, int32_t *status,
                        const SaveView &sv, int32_t ok_code, hipStream_t stream) {
     using S = Shape<KP, G>;
     if (n_rows <= 0) return RBFFD_SUCCESS;
+    if (sv.lu && OP != 0) return RBFFD_ERR_UNSUPPORTED;  // factors: the Laplacian only
     const int64_t blocks = ceil_div(n_rows, S::kGroups);
     if (blocks > 0x7fffffff) return RBFFD_ERR_UNSUPPORTED;
-    hipLaunchKernelGGL((weights_fp64_kernel<KP, G, NFIX, MFIX, OCC>), dim3((unsigned)blocks),
+    hipLaunchKernelGGL((weights_fp64_kernel<KP, G, NFIX, MFIX, OCC, OP>), dim3((unsigned)blocks),
                        dim3(S::kBlock), 0, stream, x, y, n_nodes, nbr, k_stride, rows,
                        n_rows_dev, n_rows, n, m, w, status, sv.lu, sv.z, sv.s, sv.perm,
                        sv.kmax, ok_code);

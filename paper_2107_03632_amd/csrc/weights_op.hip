@@ -2,7 +2,7 @@
 // of m = 2 and 4, and the C entry point rbffd_weights_op.  The kernels are
 // the Laplacian's (one row per lane for K = 18, the blocked LU for K = 45
 // and 84) with the operator's right-hand side and scale; K = 84 lives in
-// weights_op_k84.hip.
+// weights_op_k84.hip, the other supports (K <= 96) in weights_op_padded.hip.
 #include "weights_ms.h"
 #include "weights_mf.h"
 
@@ -16,6 +16,9 @@ int weights_fp64_class(const double *x, const double *y, int64_t n_nodes, const 
 int weights_op_k84(const double *x, const double *y, int64_t n_nodes, const int32_t *nbr,
                    int32_t k_stride, int64_t n_rows, int op, double *w, int32_t *status,
                    hipStream_t stream);
+int weights_op_padded(const double *x, const double *y, int64_t n_nodes, const int32_t *nbr,
+                      int32_t k_stride, int64_t n_rows, int n, int m, int op, double *w,
+                      int32_t *status, hipStream_t stream);
 
 namespace {
 
@@ -49,7 +52,8 @@ extern "C" int rbffd_weights_op(const double *x, const double *y, int64_t n_node
         return weights_fp64_class(x, y, n_nodes, nbr, k_stride, nullptr, nullptr, n_nodes, n, m,
                                   w, status, nullptr, nullptr, nullptr, nullptr, 0, RBFFD_OK, s);
     const bool standard = (m == 2 && n == 12) || (m == 4 && n == 30) || (m == 6 && n == 56);
-    if (!standard) return RBFFD_ERR_UNSUPPORTED;
+    if (!standard)
+        return weights_op_padded(x, y, n_nodes, nbr, k_stride, n_nodes, n, m, op, w, status, s);
     if (m == 6) return weights_op_k84(x, y, n_nodes, nbr, k_stride, n_nodes, op, w, status, s);
     return op == RBFFD_OP_DX ? op_small<RBFFD_OP_DX>(x, y, n_nodes, nbr, k_stride, n_nodes, m, w,
                                                      status, s)

@@ -118,8 +118,9 @@ def test_op_argument_errors():
     ns = nodes.unit_disk(500, 60, seed=33)
     nbr = np.ascontiguousarray(oracle.knn(ns.x, ns.y, 40))
     X, Y, NB = dev(ns.x), dev(ns.y), dev(nbr)
-    with pytest.raises(rb.RbffdError, match=r"-3"):      # not a standard (m, n)
-        rb.rbffd_weights_op(X, Y, NB, 4, 40, rb.OP_DX)
+    with pytest.raises(rb.RbffdError, match=r"-3"):      # K = 70 + 28 = 98 > 96
+        NB70 = dev(np.zeros((ns.n_nodes, 70), np.int32))
+        rb.rbffd_weights_op(X, Y, NB70, 6, 70, rb.OP_DX)
     with pytest.raises(rb.RbffdError, match=r"-1"):      # unknown operator
         rb.rbffd_weights_op(X, Y, NB, 4, 30, 3)
     with pytest.raises(rb.RbffdError, match=r"-1"):      # n above the row stride
@@ -157,3 +158,30 @@ def test_op_full_size_sampled(m, n):
                     (op == rb.OP_DY and (a, b) == (0, 1)) else 0.0
                 rel = np.abs(got - want) / (np.abs(w * f).sum(axis=1) + want)
                 assert rel.max() < 1e-9, (name, a, b, rel.max())
+
+
+# supports other than the standard three: the padded instances (K <= 32,
+# K <= 64: the multi-slot kernel; K <= 96: the two-wavefront kernel)
+PADDED = [(2, 6), (2, 20), (4, 20), (4, 40), (6, 36), (6, 60), (4, 64)]
+
+
+@pytest.mark.parametrize("m,n", PADDED)
+def test_op_padded_supports(m, n):
+    ns = nodes.unit_disk(3000, 200, seed=34)
+    nbr = oracle.knn(ns.x, ns.y, 72)
+    for ks in (n, 72):
+        nb = np.ascontiguousarray(nbr[:, :ks])
+        for op, oop, name in OPS:
+            w_ref, st_ref = oracle.weights_op(ns.x, ns.y, nb, m, n, oop)
+            w, st = rb.rbffd_weights_op(dev(ns.x), dev(ns.y), dev(nb), m, n, op)
+            w, st = host(w), host(st)
+            ok = st_ref == 0
+            a, b = w[ok][:, :n], w_ref[ok][:, :n]
+            rel = np.abs(a - b).max(axis=1) / np.abs(b).max(axis=1)
+            exact = np.mean(np.all(a == b, axis=1))
+            say(f"{name} m={m} n={n} k_stride={ks}: statuses {np.bincount(st_ref)}, "
+                f"max rel err {rel.max():.2e}, bit-exact stencils {exact:.4f}")
+            assert np.array_equal(st, st_ref)
+            assert rel.max() <= 1e-11
+            assert np.all(np.isnan(w[~ok][:, :n]))
+            assert np.all(w[:, n:] == 0.0)

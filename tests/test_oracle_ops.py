@@ -23,7 +23,7 @@ def monos(m):
     return [(a, d - a) for d in range(m + 1) for a in range(d, -1, -1)]
 
 
-@pytest.mark.parametrize("m,n", [(2, 12), (4, 30), (6, 56)])
+@pytest.mark.parametrize("m,n", [(2, 12), (4, 30), (6, 56), (2, 20), (4, 40), (6, 60)])
 @pytest.mark.parametrize("op", [oracle.D_DX, oracle.D_DY])
 def test_derivative_reproduces_polynomials(m, n, op):
     ns = nodes.unit_square(20, seed=41)
