@@ -295,7 +295,30 @@ def main():
         r, st = step(True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    ms_step = 1e3 * elapsed / args.steps
+    ms_eager = 1e3 * elapsed / args.steps
+
+    # The same step captured once in a graph and replayed: every kernel of
+    # the step runs at every replay (its outputs in the graph's pool), with
+    # no host work between the launches.  The headline figure.
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step(False)  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        r_g, st_g = step(False)
+    for _ in range(args.warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    ms_step = 1e3 * (time.perf_counter() - t0) / args.steps
+    if not (torch.equal(r_g, r) and torch.equal(st_g, st)):
+        raise SystemExit("bench: the graph replay differs from the eager step")
     w_ms = [a.elapsed_time(b) for a, b in ev]
     w_ms_avg = float(np.mean(w_ms))
     bad = int((st != 0).sum().item())
@@ -318,6 +341,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
+        "ms_per_step_eager": ms_eager,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -325,6 +349,8 @@ def main():
         "data": "synthetic (seeded jittered lattice on the unit disk)",
         "config": {"workload": "unit disk, 100k jittered lattice nodes + 1000 boundary, "
                                "m=4, n=30, FP64: kNN -> weights -> CSR -> W u - f",
+                   "launch": "the step captured in a graph, replayed once per step "
+                             "(ms_per_step_eager: the same step launched from the host)",
                    "n_nodes": N, "m": m, "n": n, "global_batch": N, "parallelism": "none"},
         # the FP64 MFMA peak of this chip equals its FP64 vector peak; the
         # kernel is bound by its vector instruction stream (column steps)
