@@ -1,15 +1,16 @@
 #pragma once
 // Two stencils per wavefront for the blocked LU of weights_mf.h, for systems
-// whose padded size is 32 (K + 1 <= 32: 2 x 2 tiles of 16 x 16).
+// whose padded size is 32 or 48 (K + 1 <= 48: 2 x 2 or 3 x 3 tiles of
+// 16 x 16).
 //
-// The panel's column steps work in row layout, one row per lane, and a
-// 32-row system leaves half of the wavefront idle there.  Here the two
-// halves carry two stencils: lane l holds row l & 31 of stencil l >> 5.  The
-// pivot search (a 32-lane reduction), the reciprocal, the multipliers and
-// the row bookkeeping of a column then serve both stencils with one
-// instruction stream, and so does the back substitution.  The tiles, the
-// panel transposes and the trailing MFMA updates stay per stencil: a
-// matrix-core instruction takes the whole wavefront.
+// The panel's column steps work in row layout.  Here the two halves of the
+// wavefront carry two stencils: lane l holds rows (l & 31) + 32 s (s < SL)
+// of stencil l >> 5.  The pivot search (a 32-lane reduction), the
+// reciprocal, the multipliers and the row bookkeeping of a column then serve
+// both stencils with one instruction stream, and so does the back
+// substitution.  The tiles, the panel transposes and the trailing MFMA
+// updates stay per stencil: a matrix-core instruction takes the whole
+// wavefront.
 //
 // The arithmetic of each stencil is that of weights_mf.h (same shift,
 // scale, assembly, pivot rule, multipliers, fused updates in the same order,
@@ -21,16 +22,18 @@ namespace rbffd {
 namespace wk {
 
 // LDS per stencil: the U triangle / assembly tables, then the panel in row
-// layout [32][5] (the pivot rows of a panel's end overlay it, read out
-// first); the pivot record of the panel [4][2] int32 per stencil follows
-// both stencils' doubles.
+// layout [NP][5] (the pivot rows of a panel's end, [NT][4][16], overlay it,
+// read out first); the pivot record of the panel [4][2] int32 per stencil
+// follows both stencils' doubles.
 template <int KP, int MM, int DIM>
 struct Mf2Lds {
     using L = MsLds<KP, MM>;
+    static constexpr int NT = (KP + 1 + 15) / 16;
+    static constexpr int NP = 16 * NT;
     static constexpr int ASZ3 = DIM == 3 ? (KP * (MM + 3) + 1) & ~1 : 0;
     static constexpr int SZ = L::SZ > ASZ3 ? L::SZ : ASZ3;
-    static constexpr int PAN = SZ;                               // [32][5]
-    static constexpr int PER = SZ + (32 * 5 > 2 * 64 ? 32 * 5 : 2 * 64);
+    static constexpr int PAN = SZ;                               // [NP][5]
+    static constexpr int PER = SZ + (NP * 5 > NT * 64 ? NP * 5 : NT * 64);
     static constexpr int DBL = 2 * PER;
     static constexpr int BYTES = 8 * DBL + 4 * 2 * 8;
 };
@@ -68,10 +71,11 @@ __device__ __forceinline__ void weights_mf2_wave(
                                 : (MFIX + 1) * (MFIX + 2) * (MFIX + 3) / 6;
     constexpr int n = NFIX, K = NFIX + MM;
     static_assert(K == KP, "no identity padding in the blocked kernel");
-    constexpr int NT = 2;
-    static_assert((KP + 1 + 15) / 16 == NT, "two tiles per dimension");
     using L = MsLds<KP, MM>;
     using B = Mf2Lds<KP, MM, DIM>;
+    constexpr int NT = B::NT, NP = B::NP;
+    static_assert(NT == 2 || NT == 3, "two or three tiles per dimension");
+    constexpr int SL = (NP + 31) / 32;  // rows per lane in row layout
 
     const int lane = threadIdx.x & (kWave - 1);
     const int h = lane >> 5;      // this lane's stencil in the row layout
@@ -87,38 +91,50 @@ __device__ __forceinline__ void weights_mf2_wave(
     int32_t *s_rec = reinterpret_cast<int32_t *>(lds + 8 * B::DBL);  // [2][4][2]
     double *sU = sU_of(h);  // this lane's stencil
 
-    // ---- shift and scale (row r of stencil h) ------------------------------
+    // ---- shift and scale (rows r + 32 s of stencil h) ---------------------
     uint32_t flags = 0;
-    double dx = 0.0, dy = 0.0, dz = 0.0, d2m = 0.0;
+    double dx[SL], dy[SL], dz[SL];
+    double d2m = 0.0;
     const double xi = x[i], yi = y[i];
     const double zi = DIM == 3 ? z[i] : 0.0;
-    if (r < n) {
-        const int32_t j = nbr[i * (int64_t)k_stride + r];
-        if (j < 0 || (int64_t)j >= n_nodes) {
-            flags |= F_BADIDX;
-        } else {
-            const double ddx = x[j] - xi, ddy = y[j] - yi;
-            const double ddz = DIM == 3 ? z[j] - zi : 0.0;
-            if (!isfinite(ddx) || !isfinite(ddy) || (DIM == 3 && !isfinite(ddz))) {
-                flags |= F_NONFIN;
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+        const int rs = r + 32 * s;
+        dx[s] = 0.0;
+        dy[s] = 0.0;
+        dz[s] = 0.0;
+        if (rs < n) {
+            const int32_t j = nbr[i * (int64_t)k_stride + rs];
+            if (j < 0 || (int64_t)j >= n_nodes) {
+                flags |= F_BADIDX;
             } else {
-                dx = ddx;
-                dy = ddy;
-                dz = ddz;
-                d2m = DIM == 3 ? (ddx * ddx + ddy * ddy) + ddz * ddz : ddx * ddx + ddy * ddy;
+                const double ddx = x[j] - xi, ddy = y[j] - yi;
+                const double ddz = DIM == 3 ? z[j] - zi : 0.0;
+                if (!isfinite(ddx) || !isfinite(ddy) || (DIM == 3 && !isfinite(ddz))) {
+                    flags |= F_NONFIN;
+                } else {
+                    dx[s] = ddx;
+                    dy[s] = ddy;
+                    dz[s] = ddz;
+                    const double d2 = DIM == 3 ? (ddx * ddx + ddy * ddy) + ddz * ddz
+                                               : ddx * ddx + ddy * ddy;
+                    d2m = fmax(d2m, d2);
+                }
             }
         }
     }
     const double sc = sqrt(seg_all_max_d<32>(d2m, lane));
     if (!isfinite(sc)) flags |= F_NONFIN;  // an offset's square overflowed
     if (sc == 0.0) flags |= F_DUP;
-    {
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+        const int rs = r + 32 * s;
         double *s_ux = sU, *s_uy = sU + KP, *s_uz = sU + 2 * KP;
         double(*s_P)[MM] = reinterpret_cast<double(*)[MM]>(sU + DIM * KP);
-        if (r < n) {
-            const double ux = dx / sc, uy = dy / sc;
-            s_ux[r] = ux;
-            s_uy[r] = uy;
+        if (rs < n) {
+            const double ux = dx[s] / sc, uy = dy[s] / sc;
+            s_ux[rs] = ux;
+            s_uy[rs] = uy;
             if constexpr (DIM == 2) {
                 double px[7], py[7];
                 px[0] = 1.0;
@@ -129,10 +145,10 @@ __device__ __forceinline__ void weights_mf2_wave(
                     py[e] = py[e - 1] * uy;
                 }
 #pragma unroll
-                for (int j = 0; j < MM; ++j) s_P[r][j] = px[mono_a(j)] * py[mono_b(j)];
+                for (int j = 0; j < MM; ++j) s_P[rs][j] = px[mono_a(j)] * py[mono_b(j)];
             } else {
-                const double uz = dz / sc;
-                s_uz[r] = uz;
+                const double uz = dz[s] / sc;
+                s_uz[rs] = uz;
                 double px[MFIX + 1], py[MFIX + 1], pt[MFIX + 1];
                 px[0] = 1.0;
                 py[0] = 1.0;
@@ -146,7 +162,7 @@ __device__ __forceinline__ void weights_mf2_wave(
                 constexpr Mono3Table<MM> e3{};
 #pragma unroll
                 for (int j = 0; j < MM; ++j)
-                    s_P[r][j] = (px[e3.a[j]] * py[e3.b[j]]) * pt[e3.c[j]];
+                    s_P[rs][j] = (px[e3.a[j]] * py[e3.b[j]]) * pt[e3.c[j]];
             }
         }
     }
@@ -228,8 +244,13 @@ __device__ __forceinline__ void weights_mf2_wave(
     lds_order();  // the assembly tables' space becomes the rows of U
 
     // ---- LU, panels of four columns ----------------------------------------
-    int pos = r;
-    bool done = r >= KP;
+    int pos[SL];
+    bool done[SL];
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+        pos[s] = r + 32 * s;
+        done[s] = pos[s] >= KP;
+    }
 #pragma unroll
     for (int c0 = 0; c0 < KP; c0 += 4) {
         const int J0 = c0 >> 4;             // tile column of the panel
@@ -244,64 +265,105 @@ __device__ __forceinline__ void weights_mf2_wave(
         }
         lds_order();
         double(*s_panh)[5] = reinterpret_cast<double(*)[5]>(sU + B::PAN);
-        double pc[4];
+        double pc[SL][4];
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) pc[jj] = s_panh[r][jj];
+        for (int s = 0; s < SL; ++s) {
+            const int rs = r + 32 * s;
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) pc[s][jj] = rs < NP ? s_panh[rs < NP ? rs : 0][jj] : 0.0;
+        }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             if (k >= nk) break;
             const int c = c0 + k;
-            // pivot search per half: exact key (|a| bits, position)
-            const uint64_t bits = (uint64_t)__double_as_longlong(pc[k]) & 0x7fffffffffffffffull;
-            const uint32_t kh = done ? 0u : (uint32_t)(bits >> 32) + 1u;
+            // pivot search over the lane's slots, then per half: exact key
+            // (|a| bits, position)
+            uint64_t bb = 0;
+            int bp = 0x7fffffff, bsl = 0;
+            double bv = 0.0;
+            bool ba = false;
+#pragma unroll
+            for (int s = 0; s < SL; ++s) {
+                const uint64_t bits =
+                    (uint64_t)__double_as_longlong(pc[s][k]) & 0x7fffffffffffffffull;
+                const bool take = !done[s] && (!ba || bits > bb || (bits == bb && pos[s] < bp));
+                bb = take ? bits : bb;
+                bp = take ? pos[s] : bp;
+                bsl = take ? s : bsl;
+                bv = take ? pc[s][k] : bv;
+                ba = ba || !done[s];
+            }
+            const uint32_t kh = ba ? (uint32_t)(bb >> 32) + 1u : 0u;
             const uint32_t mh = seg_all<32, OpMax>(kh, lane);
-            uint64_t chunk = __ballot(!done && kh == mh);
+            uint64_t chunk = __ballot(ba && kh == mh);
             uint32_t c0m = (uint32_t)chunk, c1m = (uint32_t)(chunk >> 32);
             if (__builtin_expect(((c0m & (c0m - 1u)) | (c1m & (c1m - 1u))) != 0u, 0)) {
-                uint32_t h2 = kh, l2 = done ? 0u : (uint32_t)bits;
-                int p2 = done ? 0x7fffffff : pos;
+                uint32_t h2 = kh, l2 = ba ? (uint32_t)bb : 0u;
+                int p2 = ba ? bp : 0x7fffffff;
                 seg_argmax_full<32>(h2, l2, p2);
-                chunk = __ballot(!done && pos == p2);
+                chunk = __ballot(ba && bp == p2);
                 c0m = (uint32_t)chunk;
                 c1m = (uint32_t)(chunk >> 32);
             }
             const int w0 = __builtin_amdgcn_readfirstlane(__ffs((int)c0m) - 1);
             const int w1 = __builtin_amdgcn_readfirstlane(__ffs((int)c1m) - 1 + 32);
             const int win = h ? w1 : w0;
-            const int kp = bcast2_i(pos, w0, w1, h);
-            const double piv = bcast2_d(pc[k], w0, w1, h);
+            const int bs = bcast2_i(bsl, w0, w1, h);  // the winner's slot
+            const int kp = bcast2_i(bp, w0, w1, h);
+            const double piv = bcast2_d(bv, w0, w1, h);
             const double inv = 1.0 / piv;
             // row c of U, panel columns c .. c0 + 3 (up to the rhs)
             if (lane == win) {
 #pragma unroll
-                for (int jj = k; jj < 4; ++jj)
-                    if (c0 + jj <= KP) sU[L::ubase(c) + 2 * (c0 + jj)] = pc[jj];
+                for (int jj = k; jj < 4; ++jj) {
+                    double v = pc[0][jj];
+#pragma unroll
+                    for (int s = 1; s < SL; ++s) v = bs == s ? pc[s][jj] : v;
+                    if (c0 + jj <= KP) sU[L::ubase(c) + 2 * (c0 + jj)] = v;
+                }
             }
             double uq[4];
 #pragma unroll
-            for (int jj = k + 1; jj < 4; ++jj)
-                uq[jj] = c0 + jj <= KP ? bcast2_d(pc[jj], w0, w1, h) : 0.0;
-            // multipliers, in place (zero for pivoted rows and the pivot)
-            const bool upd = !done && lane != win;
-            const double lmv = upd ? pc[k] * inv : 0.0;
-            pc[k] = lmv;
+            for (int jj = k + 1; jj < 4; ++jj) {
+                double v = pc[0][jj];
 #pragma unroll
-            for (int jj = k + 1; jj < 4; ++jj)
-                if (c0 + jj <= KP) pc[jj] = fma(-lmv, uq[jj], pc[jj]);
-            const bool isp = lane == win;
-            pos = isp ? c : ((!done && pos == c) ? kp : pos);
-            done = done || isp;
-            int dn = done ? 1 : 0;
-            asm volatile("" : "+v"(pos), "+v"(dn));
-            done = dn != 0;
+                for (int s = 1; s < SL; ++s) v = bs == s ? pc[s][jj] : v;
+                uq[jj] = c0 + jj <= KP ? bcast2_d(v, w0, w1, h) : 0.0;
+            }
+            // multipliers, in place (zero for pivoted rows and the pivot)
+#pragma unroll
+            for (int s = 0; s < SL; ++s) {
+                const bool isp = lane == win && bs == s;
+                const bool upd = !done[s] && !isp;
+                const double lmv = upd ? pc[s][k] * inv : 0.0;
+                pc[s][k] = lmv;
+#pragma unroll
+                for (int jj = k + 1; jj < 4; ++jj)
+                    if (c0 + jj <= KP) pc[s][jj] = fma(-lmv, uq[jj], pc[s][jj]);
+            }
+#pragma unroll
+            for (int s = 0; s < SL; ++s) {
+                const bool isp = lane == win && bs == s;
+                pos[s] = isp ? c : ((!done[s] && pos[s] == c) ? kp : pos[s]);
+                done[s] = done[s] || isp;
+                int dn = done[s] ? 1 : 0;
+                asm volatile("" : "+v"(pos[s]), "+v"(dn));
+                done[s] = dn != 0;
+            }
             if (r == 0) {
-                s_rec[(h * 4 + k) * 2 + 0] = win - 32 * h;  // the pivot's row
+                s_rec[(h * 4 + k) * 2 + 0] = (win - 32 * h) + 32 * bs;  // the pivot's row
                 s_rec[(h * 4 + k) * 2 + 1] = kp;
             }
         }
         // the panel's multipliers, row layout
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) s_panh[r][jj] = pc[jj];
+        for (int s = 0; s < SL; ++s) {
+            const int rs = r + 32 * s;
+            if (rs < NP) {
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) s_panh[rs][jj] = pc[s][jj];
+            }
+        }
         lds_order();
 
         // ---- panel end: the trailing tile columns of both stencils ---------
@@ -373,25 +435,29 @@ __device__ __forceinline__ void weights_mf2_wave(
     lds_order();
 
     // ---- back substitution, both stencils at once (32-lane segments) -------
-    int ub[1];
-    double yb[1], mb[1], zm[1];
+    int ub[SL];
+    double yb[SL], mb[SL], zm[SL];
     double ur[1][1];
     uint32_t lukey = 0;
-    {
-        const int rr = r < KP ? r : KP - 1;
-        ub[0] = h * B::PER + L::ubase(rr);
-        yb[0] = sbase[ub[0] + 2 * KP];
-        const double d = sbase[ub[0] + 2 * rr];
-        mb[0] = 1.0 / d;
-        zm[0] = 0.0;
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+        const int r0 = r + 32 * s;
+        const int rr = r0 < KP ? r0 : KP - 1;
+        ub[s] = h * B::PER + L::ubase(rr);
+        yb[s] = sbase[ub[s] + 2 * KP];
+        const double d = sbase[ub[s] + 2 * rr];
+        mb[s] = 1.0 / d;
+        zm[s] = 0.0;
         const uint32_t f = !isfinite(d) ? L_NONFIN : (d == 0.0 ? L_SING : 0u);
-        const uint32_t key = ((uint32_t)(KP - r) << 2) | f;
-        if (r < KP && f) lukey = key;
+        const uint32_t key = ((uint32_t)(KP - r0) << 2) | f;
+        if (r0 < KP && f && key > lukey) lukey = key;
     }
     const uint32_t luflag = seg_all<32, OpMax>(lukey, lane) & 3u;
-    bc_step<KP, 32, 1, KP - 1, false>(sbase, ub, ur[0], yb, mb, zm, r, false);
+    bc_step<KP, 32, SL, KP - 1, false>(sbase, ub, ur[0], yb, mb, zm, r, false);
 
-    if (r < K && !isfinite(zm[0])) fl |= F_ZBAD;
+#pragma unroll
+    for (int s = 0; s < SL; ++s)
+        if (r + 32 * s < K && !isfinite(zm[s])) fl |= F_ZBAD;
     fl = seg_all<32, OpOr>(fl, lane);
     int st = RBFFD_OK;
     if (fl & F_BADIDX) st = RBFFD_BAD_INDEX;
@@ -404,7 +470,11 @@ __device__ __forceinline__ void weights_mf2_wave(
     double *wi = w + i * (int64_t)k_stride;
     const double s2 = OP == 0 ? sc * sc : sc;  // the operator's power of the scale
     const bool good = st == RBFFD_OK;
-    if (r < n) wi[r] = good ? zm[0] / s2 : __builtin_nan("");
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+        const int rs = r + 32 * s;
+        if (rs < n) wi[rs] = good ? zm[s] / s2 : __builtin_nan("");
+    }
     for (int q = n + r; q < k_stride; q += 32) wi[q] = 0.0;
     if (r == 0 && status) status[i] = good ? ok_code : st;
 }
