@@ -219,8 +219,8 @@ int rbffd_weights_op(const double *x, const double *y, int64_t n_nodes, const in
  * [n_nodes][k_stride] FP64 out, zero past n; status: [n_nodes] int32 out or
  * NULL.  m = 2 with 10 <= n <= k_stride, or m = 4 with 35 <= n <= k_stride
  * (RBFFD_ERR_ARG otherwise); m = 2 with n > 54 (K = n + 10 > 64) and m = 4
- * with n other than 70 (the standard support, K = 105) return
- * RBFFD_ERR_UNSUPPORTED.  No workspace.
+ * with n > 76 (K = n + 35 > 111) return RBFFD_ERR_UNSUPPORTED.  No
+ * workspace.
  *
  * rbffd_weights3_op: the same for the operator op: RBFFD_OP_LAPLACIAN (as
  * rbffd_weights3), RBFFD_OP_DX, RBFFD_OP_DY, RBFFD_OP3_DZ: rhs_k =

@@ -23,10 +23,12 @@ import torch
 from . import binding as rb
 from . import nodes
 
+# one launch: blocks per compute unit (the K = 84 body's 40 KB of LDS
+# keeps four resident; more queue behind them) and stencils per tile
 CANDIDATES = {
-    "blocks_per_cu": [1, 2, 3, 4],
+    "blocks_per_cu": [2, 3, 4, 6, 8],
     "gpt2": [1, 2, 4],
-    "gpt4": [1, 2],
+    "gpt4": [1, 2, 4],
     "gpt6": [1, 2],
 }
 # one launch per order: blocks per compute unit for m = 2, 4, 6

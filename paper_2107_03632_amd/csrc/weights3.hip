@@ -2,9 +2,9 @@
 // polyharmonic spline r^3 (lap r^3 = 12 r in 3-D) augmented with the ten
 // monomials of degree <= 2 in (x, y, z), on the node's n nearest neighbours
 // (10 <= n <= 54, so K = n + 10 <= 64), shifted to the node and scaled to a
-// unit stencil.  The standard supports (m = 2, n = 20 and m = 4, n = 70) run
-// the blocked LU of weights_mf.h instead (weights3_k30.hip,
-// weights3_k105_op*.hip).
+// unit stencil.  m = 2, n = 20 and every m = 4 support (35 <= n <= 76) run
+// the blocked LU of weights_mf.h / weights_mf2.h instead (weights3_k30.hip,
+// weights3_k105_op*.hip for n = 70, weights3_m4any_op*.hip).
 //
 // One wavefront per stencil, one row of [A P; P^T 0 | rhs] per lane, in
 // registers.  Rows never move: each lane tracks the position its row holds
@@ -320,6 +320,16 @@ RBFFD_W3_K105_DECL(1)
 RBFFD_W3_K105_DECL(2)
 RBFFD_W3_K105_DECL(3)
 #undef RBFFD_W3_K105_DECL
+// m = 4 on the other supports (35 <= n <= 76): identity padding to K = 111
+#define RBFFD_W3_M4_ANY_DECL(OP)                                                               \
+    int weights3_blocked_m4_any_op##OP(const double *x, const double *y, const double *z,      \
+                                       int64_t n_nodes, const int32_t *nbr, int32_t k_stride,  \
+                                       int n, double *w, int32_t *status, hipStream_t stream);
+RBFFD_W3_M4_ANY_DECL(0)
+RBFFD_W3_M4_ANY_DECL(1)
+RBFFD_W3_M4_ANY_DECL(2)
+RBFFD_W3_M4_ANY_DECL(3)
+#undef RBFFD_W3_M4_ANY_DECL
 
 }  // namespace rbffd
 
@@ -337,8 +347,17 @@ extern "C" int rbffd_weights3_op(const double *x, const double *y, const double 
         n > k_stride || (m != 2 && m != 4) || n < (m == 2 ? kMono3 : 35) || op < 0 || op > 3)
         return RBFFD_ERR_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (m == 4 && n != 70) {
+        if (n > 76) return RBFFD_ERR_UNSUPPORTED;
+        switch (op) {
+        case 0: return weights3_blocked_m4_any_op0(x, y, z, n_nodes, nbr, k_stride, n, w, status, s);
+        case 1: return weights3_blocked_m4_any_op1(x, y, z, n_nodes, nbr, k_stride, n, w, status, s);
+        case 2: return weights3_blocked_m4_any_op2(x, y, z, n_nodes, nbr, k_stride, n, w, status, s);
+        default:
+            return weights3_blocked_m4_any_op3(x, y, z, n_nodes, nbr, k_stride, n, w, status, s);
+        }
+    }
     if (m == 4) {
-        if (n != 70) return RBFFD_ERR_UNSUPPORTED;
         switch (op) {
         case 0: return weights3_blocked_k105_op0(x, y, z, n_nodes, nbr, k_stride, w, status, s);
         case 1: return weights3_blocked_k105_op1(x, y, z, n_nodes, nbr, k_stride, w, status, s);

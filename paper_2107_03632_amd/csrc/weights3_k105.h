@@ -25,3 +25,15 @@
             x, y, z, n_nodes, nbr, k_stride, w, status, stream);                               \
     }                                                                                          \
     }
+
+// Other supports of m = 4 (35 <= n <= 76): the same kernel at KP = 111 (seven
+// tiles, rhs in column 111) with a run-time n and identity padding up to 111.
+#define RBFFD_W3_M4_ANY_INSTANCE(OP)                                                           \
+    namespace rbffd {                                                                          \
+    int weights3_blocked_m4_any_op##OP(const double *x, const double *y, const double *z,      \
+                                       int64_t n_nodes, const int32_t *nbr, int32_t k_stride,  \
+                                       int n, double *w, int32_t *status, hipStream_t stream) { \
+        return wk::launch_mf3<111, 0, 4, RBFFD_NW_MF3_K105, RBFFD_OCC_MF3_K105, OP>(           \
+            x, y, z, n_nodes, nbr, k_stride, w, status, stream, n);                            \
+    }                                                                                          \
+    }

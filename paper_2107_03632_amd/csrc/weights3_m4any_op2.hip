@@ -1,0 +1,4 @@
+// Three-dimensional weights, m = 4, supports 35 <= n <= 76 (identity padding
+// to K = 111): d/dy.
+#include "weights3_k105.h"
+RBFFD_W3_M4_ANY_INSTANCE(2)

@@ -3,7 +3,8 @@
 // columns with the trailing updates on the matrix cores.  Instances: K = 84
 // (m = 6, n = 56; two wavefronts per stencil) and K = 45 (m = 4, n = 30; one
 // wavefront per stencil) in two dimensions; in three, K = 105 (m = 4,
-// n = 70; several wavefronts per stencil) and K = 30 (m = 2, n = 20).
+// n = 70; several wavefronts per stencil).  weights_mf2.h holds the form
+// with two stencils per wavefront (the 3-D K = 30).
 //
 // v_mfma_f64_16x16x4f64 forms each output as four fused multiply-adds taken
 // in k order, fma(a3, b3, fma(a2, b2, fma(a1, b1, fma(a0, b0, c)))).  A
@@ -90,20 +91,26 @@ struct MfLds {
 // r^3 with lap r^3 = 12 r, the monomials of degree <= MFIX in three
 // variables, each evaluated as (u^a v^b) t^c.
 // WV: this wavefront's index in the block, or -1 for a run-time index.
+// NFIX = 0: the support size is n_arg (K = n_arg + M <= KP), and the rows
+// and columns K .. KP - 1 are identity padding: they hold zeros in the
+// first K columns and rows, so no real row takes a multiplier from them or
+// a pivot from them (a real row holds a lower position), and the real
+// unknowns come out as without the padding.
 template <int KP, int NFIX, int MFIX, int NW, int WV, bool SAVE, int OP = 0, int DIM = 2>
 __device__ __forceinline__ void weights_mf_wave(
     const double *__restrict__ x, const double *__restrict__ y, const double *__restrict__ z,
     int64_t n_nodes, const int32_t *__restrict__ nbr, int32_t k_stride, int64_t i,
     double *__restrict__ w, int32_t *__restrict__ status, const SaveView &sv, int32_t ok_code,
-    char *lds) {
+    char *lds, int n_arg = 0) {
     static_assert(!SAVE || (NW == 1 && DIM == 2),
                   "the factors are saved by the one-wavefront 2-D instance");
     static_assert(DIM == 2 || DIM == 3, "two or three dimensions");
     static_assert(OP >= 0 && OP <= DIM, "operator");
     constexpr int MM = DIM == 2 ? (MFIX + 1) * (MFIX + 2) / 2
                                 : (MFIX + 1) * (MFIX + 2) * (MFIX + 3) / 6;
-    constexpr int n = NFIX, K = NFIX + MM;
-    static_assert(K == KP, "no identity padding in the blocked kernel");
+    static_assert(NFIX == 0 || NFIX + MM == KP, "identity padding only with a run-time n");
+    static_assert(NFIX > 0 || !SAVE, "the factors: fixed supports only");
+    const int n = NFIX ? NFIX : n_arg, K = n + MM;
     constexpr int NT = (KP + 1 + 15) / 16;  // tiles per dimension (rhs included)
     constexpr int NP = 16 * NT;
     constexpr int SL = (NP + kWave - 1) / kWave;  // rows per lane in row layout
@@ -250,6 +257,8 @@ __device__ __forceinline__ void weights_mf_wave(
                     v = prow ? phs : (qrow ? pt : 0.0);
                 } else if (16 * J + 15 >= n && 16 * J < K && C >= n && C < K) {
                     v = prow ? s_P[prow ? R : 0][C - n] : 0.0;
+                } else if (NFIX == 0 && C >= K && C < KP) {
+                    v = C == R ? 1.0 : 0.0;  // identity padding
                 } else if (16 * J + 15 >= KP && 16 * J <= KP && C == KP) {
                     double rb, rq;
                     if constexpr (DIM == 2) {
@@ -695,31 +704,34 @@ __global__ __launch_bounds__(NW * kWave)
 __attribute__((amdgpu_waves_per_eu(OCC))) void weights_mf3_kernel(
     const double *__restrict__ x, const double *__restrict__ y, const double *__restrict__ z,
     int64_t n_nodes, const int32_t *__restrict__ nbr, int32_t k_stride, double *__restrict__ w,
-    int32_t *__restrict__ status) {
+    int32_t *__restrict__ status, int32_t n_arg) {
     __shared__ __align__(16) char lds[mf3_lds_bytes<KP, NFIX, MFIX, NW>()];
     const int64_t i = (int64_t)blockIdx.x;
     if constexpr (NW <= 2) {
         if (NW > 1 && ((threadIdx.x >> 6) & 1))
             weights_mf_wave<KP, NFIX, MFIX, NW, NW - 1, false, OP, 3>(
-                x, y, z, n_nodes, nbr, k_stride, i, w, status, SaveView{}, RBFFD_OK, lds);
+                x, y, z, n_nodes, nbr, k_stride, i, w, status, SaveView{}, RBFFD_OK, lds, n_arg);
         else
             weights_mf_wave<KP, NFIX, MFIX, NW, 0, false, OP, 3>(
-                x, y, z, n_nodes, nbr, k_stride, i, w, status, SaveView{}, RBFFD_OK, lds);
+                x, y, z, n_nodes, nbr, k_stride, i, w, status, SaveView{}, RBFFD_OK, lds, n_arg);
     } else {
         weights_mf_wave<KP, NFIX, MFIX, NW, -1, false, OP, 3>(
-            x, y, z, n_nodes, nbr, k_stride, i, w, status, SaveView{}, RBFFD_OK, lds);
+            x, y, z, n_nodes, nbr, k_stride, i, w, status, SaveView{}, RBFFD_OK, lds, n_arg);
     }
 }
 
+// n: the support size when NFIX = 0 (K = n + M <= KP), else ignored.
 template <int KP, int NFIX, int MFIX, int NW, int OCC, int OP>
 inline int launch_mf3(const double *x, const double *y, const double *z, int64_t n_nodes,
                       const int32_t *nbr, int32_t k_stride, double *w, int32_t *status,
-                      hipStream_t stream) {
+                      hipStream_t stream, int n = NFIX) {
+    constexpr int MM = (MFIX + 1) * (MFIX + 2) * (MFIX + 3) / 6;
     if (n_nodes <= 0) return RBFFD_SUCCESS;
     if (n_nodes > 0x7fffffff) return RBFFD_ERR_UNSUPPORTED;
+    if (n < 1 || n + MM > KP || (NFIX && n != NFIX)) return RBFFD_ERR_UNSUPPORTED;
     hipLaunchKernelGGL((weights_mf3_kernel<KP, NFIX, MFIX, NW, OCC, OP>),
                        dim3((unsigned)n_nodes), dim3(NW * kWave), 0, stream, x, y, z, n_nodes,
-                       nbr, k_stride, w, status);
+                       nbr, k_stride, w, status, (int32_t)n);
     return last_launch_rc();
 }
 

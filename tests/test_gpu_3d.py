@@ -145,8 +145,9 @@ def test_weights3_argument_errors():
     X, Y, Z, NB = dev(x), dev(y), dev(z), dev(nbr)
     with pytest.raises(rb.RbffdError, match=r"-3"):      # K = 70 > 64
         rb.rbffd_weights3(X, Y, Z, NB, 2, 60)
-    with pytest.raises(rb.RbffdError, match=r"-3"):      # m = 4: the support n = 70 only
-        rb.rbffd_weights3(X, Y, Z, NB, 4, 40)
+    with pytest.raises(rb.RbffdError, match=r"-3"):      # m = 4: n <= 76 (K <= 111)
+        NB80 = dev(np.zeros((x.size, 80), np.int32))
+        rb.rbffd_weights3(X, Y, Z, NB80, 4, 77)
     with pytest.raises(rb.RbffdError, match=r"-1"):      # m = 2 or 4
         rb.rbffd_weights3(X, Y, Z, NB, 3, 40)
     with pytest.raises(rb.RbffdError, match=r"-1"):      # m = 4: n below 35 monomials
@@ -240,6 +241,22 @@ def test_weights3_op_argument_errors():
 
 MONOS4 = [(a, b, d - a - b) for d in range(5) for a in range(d, -1, -1)
           for b in range(d - a, -1, -1)]
+
+
+@pytest.mark.parametrize("n", [35, 40, 56, 69, 71, 76])
+def test_weights3_m4_other_supports_bit_exact(n):
+    """m = 4 on supports other than 70: identity padding to K = 111 in the
+    blocked kernel, the oracle's doubles and statuses."""
+    x, y, z = nodes.jittered_cube(11, seed=29)
+    nbr = oracle.knn3(x, y, z, 80)
+    check_weights3(x, y, z, np.ascontiguousarray(nbr[:, :n]), n, f"cube 1331, n {n}", m=4)
+    check_weights3(x, y, z, nbr, n, f"cube 1331, n {n}, k_stride 80", m=4)
+    for op, oop, axis in D3:
+        w_ref, st_ref = oracle.weights3_op(x, y, z, nbr, 4, n, oop)
+        w, st = rb.rbffd_weights3(dev(x), dev(y), dev(z), dev(nbr), 4, n, op=op)
+        w, st = host(w), host(st)
+        assert np.array_equal(st, st_ref)
+        assert np.array_equal(w, w_ref, equal_nan=True)
 
 
 @pytest.mark.parametrize("ks", [70, 80])
