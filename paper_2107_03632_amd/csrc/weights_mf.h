@@ -58,23 +58,49 @@ __device__ __forceinline__ void lds_order() {
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
+// Rows of U when one wavefront owns the stencil: row r (entries r .. KP,
+// the right-hand side last) packed right after row r - 1, entry q at
+// ubase(r) + q.  (Several wavefronts per stencil keep the pair-interleaved
+// rows of MsLds, entry q at ubase(r) + 2 q.)
+template <int KP, int MM>
+struct MfULds {
+    static constexpr int US = 1;  // stride of a row's entries
+    __host__ __device__ static constexpr int ubase(int r) { return r * KP - r * (r - 1) / 2; }
+    static constexpr int USZ = ubase(KP - 1) + KP + 1;
+    static constexpr int ASZ = KP * (MM + 2);  // ux, uy, monomials
+    static constexpr int SZ = ((USZ > ASZ ? USZ : ASZ) + 1) & ~1;
+};
+
+template <bool ONE, int KP, int MM>
+struct MfUSel {
+    using type = MsLds<KP, MM>;
+};
+template <int KP, int MM>
+struct MfUSel<true, KP, MM> {
+    using type = MfULds<KP, MM>;
+};
+
 // LDS of one block: doubles first, then int32.  Panel buffers alternate
 // between consecutive panels when several wavefronts share them.  With one
 // wavefront the pivot rows of a panel's end overlay its panel buffer (read
-// out before the rows are written), which keeps K = 45 at 15 wavefronts
-// per CU.  In three dimensions the assembly tables hold a third offset.
+// out before the rows are written), and the packed rows of U with unpadded
+// panel rows keep K = 45 under 10 KB per wavefront: 16 wavefronts per CU
+// (15 with the interleaved rows and panel rows padded to five).  In three
+// dimensions the assembly tables hold a third offset.
 template <int KP, int MM, int NT, int NW, int DIM = 2>
 struct MfLds {
+    using U = typename MfUSel<NW == 1, KP, MM>::type;  // rows of U
     static constexpr int NP = 16 * NT;
     static constexpr int NPB = NW > 1 ? 2 : 1;       // panel buffers
+    static constexpr int PS = NW > 1 ? 5 : 4;        // panel row stride (doubles)
     static constexpr int NJT = (NT + NW - 1) / NW;  // tile columns per wavefront (at most)
     static constexpr int ASZ3 = DIM == 3 ? (KP * (MM + 3) + 1) & ~1 : 0;
     static constexpr int SZ =                        // U triangle / assembly tables
-        MsLds<KP, MM>::SZ > ASZ3 ? MsLds<KP, MM>::SZ : ASZ3;
-    static constexpr int PAN = SZ;                  // [NPB][NP][5] panel, row layout (padded)
-    static constexpr int UB = NW > 1 ? PAN + NPB * NP * 5 : PAN;  // [NW][NJT][4][16] pivot rows
+        U::SZ > ASZ3 ? U::SZ : ASZ3;
+    static constexpr int PAN = SZ;                  // [NPB][NP][PS] panel, row layout
+    static constexpr int UB = NW > 1 ? PAN + NPB * NP * PS : PAN;  // [NW][NJT][4][16] pivot rows
     static constexpr int DBL =
-        NW > 1 ? UB + NW * NJT * 64 : PAN + (NP * 5 > NJT * 64 ? NP * 5 : NJT * 64);
+        NW > 1 ? UB + NW * NJT * 64 : PAN + (NP * PS > NJT * 64 ? NP * PS : NJT * 64);
     static constexpr int REC = 0;                   // [NPB][4][2] pivot row, its position
     static constexpr int FL = 8 * NPB;              // flags of wavefronts 1 .. NW - 1
     static constexpr int INTS = FL + (NW > 2 ? NW - 1 : 2);
@@ -115,8 +141,8 @@ __device__ __forceinline__ void weights_mf_wave(
     constexpr int NP = 16 * NT;
     constexpr int SL = (NP + kWave - 1) / kWave;  // rows per lane in row layout
     static_assert(NW <= 2 ? NT % NW == 0 : WV < 0, "tile columns of the wavefronts");
-    using L = MsLds<KP, MM>;
     using B = MfLds<KP, MM, NT, NW, DIM>;
+    using L = typename B::U;
     constexpr int NJT = B::NJT;
     const int wv = WV >= 0 ? WV : __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     // tile columns this wavefront owns: J = NW jt + wv for jt < njt
@@ -126,7 +152,7 @@ __device__ __forceinline__ void weights_mf_wave(
     double *s_uy = sU + KP;
     double *s_uz = sU + 2 * KP;  // (three dimensions)
     double(*s_P)[MM] = reinterpret_cast<double(*)[MM]>(sU + DIM * KP);
-    double(*s_pan)[NP][5] = reinterpret_cast<double(*)[NP][5]>(sU + B::PAN);
+    double(*s_pan)[NP][B::PS] = reinterpret_cast<double(*)[NP][B::PS]>(sU + B::PAN);
     double(*s_ub)[4][16] = reinterpret_cast<double(*)[4][16]>(sU + B::UB + wv * NJT * 64);
     int32_t *si = reinterpret_cast<int32_t *>(lds + 8 * B::DBL);
     int32_t(*s_rec)[4][2] = reinterpret_cast<int32_t(*)[4][2]>(si + B::REC);
@@ -361,7 +387,7 @@ __device__ __forceinline__ void weights_mf_wave(
 #pragma unroll
                     for (int j = k; j < 4; ++j)
                         if (c0 + j <= KP)
-                            sU[L::ubase(c) + 2 * (c0 + j)] = b1 ? pc[SL - 1][j] : pc[0][j];
+                            sU[L::ubase(c) + L::US * (c0 + j)] = b1 ? pc[SL - 1][j] : pc[0][j];
                 }
                 double uq[4];
 #pragma unroll
@@ -504,7 +530,7 @@ __device__ __forceinline__ void weights_mf_wave(
                         fma(-l11[3][2], u2, fma(-l11[3][1], u1, fma(-l11[3][0], u0, r3)));
                     const double ug = g == 0 ? u0 : (g == 1 ? u1 : (g == 2 ? u2 : u3));
                     const int q = 16 * J + jl;
-                    if (jl >= i0 && q <= KP) sU[L::ubase(c0 + g) + 2 * q] = ug;
+                    if (jl >= i0 && q <= KP) sU[L::ubase(c0 + g) + L::US * q] = ug;
                     const double Aop = jl >= i0 ? -ug : 0.0;
 #pragma unroll
                     for (int I = 0; I < NT; ++I)
@@ -537,8 +563,8 @@ __device__ __forceinline__ void weights_mf_wave(
         const int r0 = lane + kWave * s;
         const int r = r0 < KP ? r0 : KP - 1;
         ub[s] = L::ubase(r);
-        yb[s] = sU[ub[s] + 2 * KP];
-        const double d = sU[ub[s] + 2 * r];
+        yb[s] = sU[ub[s] + L::US * KP];
+        const double d = sU[ub[s] + L::US * r];
         mb[s] = 1.0 / d;
         zm[s] = 0.0;
         const uint32_t f = !isfinite(d) ? L_NONFIN : (d == 0.0 ? L_SING : 0u);
@@ -546,7 +572,7 @@ __device__ __forceinline__ void weights_mf_wave(
         if (r0 < KP && f && key > lukey) lukey = key;
     }
     const uint32_t luflag = seg_all<kWave, OpMax>(lukey, lane) & 3u;
-    bc_step<KP, kWave, SL, KP - 1, false>(sU, ub, ur[0], yb, mb, zm, lane, false);
+    bc_step<KP, kWave, SL, KP - 1, false, L::US>(sU, ub, ur[0], yb, mb, zm, lane, false);
 
 #pragma unroll
     for (int s = 0; s < SL; ++s)
@@ -580,7 +606,7 @@ __device__ __forceinline__ void weights_mf_wave(
         double *lu = sv.lu + i * (int64_t)sv.kmax * sv.kmax;
         for (int p = 0; p < K; ++p) {
             const int r = __builtin_amdgcn_readfirstlane(s_row[p]);
-            for (int q = p + lane; q < K; q += kWave) lu[(int64_t)r * K + q] = sU[L::ubase(p) + 2 * q];
+            for (int q = p + lane; q < K; q += kWave) lu[(int64_t)r * K + q] = sU[L::ubase(p) + L::US * q];
             if (lane == 0) sv.perm[i * (int64_t)sv.kmax + p] = (uint8_t)r;
         }
 #pragma unroll

@@ -142,6 +142,7 @@ __device__ __forceinline__ void seg_argmax_full(uint32_t &kh, uint32_t &kl, int 
 // that never merge into 128-bit ones (which would need contiguous registers).
 template <int KP, int MM>
 struct MsLds {
+    static constexpr int US = 2;  // stride of a row's entries
     // start of the region of rows 2p, 2p+1
     __host__ __device__ static constexpr int region(int p) { return 2 * p * (KP + 2 - p); }
     // entry q of row r sits at ubase(r) + 2 q
@@ -172,8 +173,8 @@ __device__ __forceinline__ void wave_sync() {
 // One column of the back substitution (column C, then C-1, ... down to 0):
 // the source lane of the broadcast must be a compile-time constant.
 // PRE: the lane's rows of U were copied to registers ur[s][q] (row-major,
-// stride KP) beforehand.
-template <int KP, int SEG, int SL, int C, bool PRE>
+// stride KP) beforehand.  US: the stride of a row's entries in sU.
+template <int KP, int SEG, int SL, int C, bool PRE, int US = 2>
 __device__ __forceinline__ void bc_step(const double *sU, const int *ub, const double *ur,
                                         double *yb, const double *mb, double *zm, int l0,
                                         bool upper8) {
@@ -185,10 +186,10 @@ __device__ __forceinline__ void bc_step(const double *sU, const int *ub, const d
 #pragma unroll
         for (int s = 0; s < SL; ++s)
             if (SEG * s < C) {
-                const double uc = PRE ? ur[s * KP + C] : sU[ub[s] + 2 * C];
+                const double uc = PRE ? ur[s * KP + C] : sU[ub[s] + US * C];
                 yb[s] = fma(-uc, z, yb[s]);
             }
-        bc_step<KP, SEG, SL, C - 1, PRE>(sU, ub, ur, yb, mb, zm, l0, upper8);
+        bc_step<KP, SEG, SL, C - 1, PRE, US>(sU, ub, ur, yb, mb, zm, l0, upper8);
     }
 }
 
