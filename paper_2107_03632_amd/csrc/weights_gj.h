@@ -319,7 +319,9 @@ __device__ __forceinline__ void weights_gj_wave(
             }
             const uint32_t kh = ba ? bb + 1u : 0u;
             const uint32_t mh = seg_all<kWave, OpMax>(kh, lane);
-            uint64_t chunk = __ballot(ba && kh == mh);
+            // (some row is always left, so mh >= 1 and only rows still in the
+            // search can equal it)
+            uint64_t chunk = __ballot(kh == mh);
             if (__builtin_expect((chunk & (chunk - 1ull)) != 0ull, 0)) {
                 uint32_t h2 = kh, l2 = 0u;
                 int p2 = ba ? bp : 0x7fffffff;

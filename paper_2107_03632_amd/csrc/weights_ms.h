@@ -50,8 +50,12 @@ struct OpOr {
 };
 
 // All-reduce over each SEG-lane segment; every lane receives the result.
-// Inside a 16-lane row: DPP exchanges; across rows: permlane16_swap (rows
-// 2k <-> 2k+1) and permlane32_swap (halves), all in the VALU (no LDS).
+// Inside a 16-lane row: DPP exchanges.  Across the rows of a 32-lane
+// segment: permlane16_swap (rows 2k <-> 2k+1).  Over the whole wavefront:
+// row 0 into row 1 and row 2 into row 3 (row_bcast:15), then lane 31 into
+// rows 2 and 3 (row_bcast:31), after which lane 63 holds the result and
+// readlane makes it uniform.  All in the VALU (no LDS); zero is the
+// identity of both operations, so the rows a broadcast skips see zero.
 template <int SEG, class Op>
 __device__ __forceinline__ uint32_t seg_all(uint32_t v, int /*lane*/) {
     static_assert(SEG == 4 || SEG == 8 || SEG == 16 || SEG == 32 || SEG == 64, "segment width");
@@ -59,12 +63,13 @@ __device__ __forceinline__ uint32_t seg_all(uint32_t v, int /*lane*/) {
     if constexpr (SEG >= 8) v = Op::f(v, dpp_u32<0x141>(v));   // row_half_mirror
     v = Op::f(v, dpp_u32<0x4E>(v));                            // quad_perm [2,3,0,1]
     v = Op::f(v, dpp_u32<0xB1>(v));                            // quad_perm [1,0,3,2]
-    if constexpr (SEG >= 32) {
-        const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
-        v = Op::f(r[0], r[1]);
-    }
     if constexpr (SEG == 64) {
-        const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        v = Op::f(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));
+        v = Op::f(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));
+        return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+    }
+    if constexpr (SEG == 32) {
+        const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
         v = Op::f(r[0], r[1]);
     }
     return v;
