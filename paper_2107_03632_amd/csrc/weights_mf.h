@@ -48,6 +48,27 @@ namespace wk {
 
 typedef double mf_v4d __attribute__((ext_vector_type(4)));
 
+// 1 / b with the same bits as the general division 1.0 / b.  For |b| in
+// [2^-500, 2^501) that division's prescale steps, its scaled fused step and
+// its fix-up leave every value unchanged, and what remains is the
+// hardware's reciprocal estimate followed by three Newton steps
+// y <- y + y (1 - b y), each a pair of fused multiply-adds (the third is
+// the division's quotient correction, the quotient of 1 by b being y).
+// Other b (also zero, infinities and NaN) go through the division.
+__device__ __forceinline__ double recip_div(double b) {
+    const uint32_t ex = (uint32_t)((uint64_t)__double_as_longlong(b) >> 52) & 0x7ffu;
+    if (__builtin_expect(ex - 523u <= 1000u, 1)) {
+        double y = __builtin_amdgcn_rcp(b);
+        double e = fma(-b, y, 1.0);
+        y = fma(y, e, y);
+        e = fma(-b, y, 1.0);
+        y = fma(y, e, y);
+        e = fma(-b, y, 1.0);
+        return fma(e, y, y);
+    }
+    return 1.0 / b;
+}
+
 // LDS traffic of one wavefront is processed in issue order, so a write by
 // one lane is seen by a later read of another lane of the same wavefront
 // without waiting for the write to complete; this only keeps the compiler
@@ -351,21 +372,30 @@ __device__ __forceinline__ void weights_mf_wave(
             for (int k = 0; k < 4; ++k) {
                 if (k >= nk) break;
                 const int c = c0 + k;
-                // pivot search over the slots: exact key (|a| bits, position)
+                // pivot search over the slots: exact key (|a| bits, position);
+                // bb, bp and bv are read only where ba holds
                 uint64_t bb = 0;
-                int bp = 0x7fffffff, bsl = 0;
+                int bp = 0, bsl = 0;
                 double bv = 0.0;
                 bool ba = false;
+                if constexpr (SL == 1) {
+                    bb = (uint64_t)__double_as_longlong(pc[0][k]) & 0x7fffffffffffffffull;
+                    bp = pos[0];
+                    bv = pc[0][k];
+                    ba = !done[0];
+                } else {
 #pragma unroll
-                for (int s = 0; s < SL; ++s) {
-                    const uint64_t bits =
-                        (uint64_t)__double_as_longlong(pc[s][k]) & 0x7fffffffffffffffull;
-                    const bool take = !done[s] && (!ba || bits > bb || (bits == bb && pos[s] < bp));
-                    bb = take ? bits : bb;
-                    bp = take ? pos[s] : bp;
-                    bsl = take ? s : bsl;
-                    bv = take ? pc[s][k] : bv;
-                    ba = ba || !done[s];
+                    for (int s = 0; s < SL; ++s) {
+                        const uint64_t bits =
+                            (uint64_t)__double_as_longlong(pc[s][k]) & 0x7fffffffffffffffull;
+                        const bool take =
+                            !done[s] && (!ba || bits > bb || (bits == bb && pos[s] < bp));
+                        bb = take ? bits : bb;
+                        bp = take ? pos[s] : bp;
+                        bsl = take ? s : bsl;
+                        bv = take ? pc[s][k] : bv;
+                        ba = ba || !done[s];
+                    }
                 }
                 const uint32_t kh = ba ? (uint32_t)(bb >> 32) + 1u : 0u;
                 const uint32_t mh = seg_all<kWave, OpMax>(kh, lane);
@@ -382,7 +412,9 @@ __device__ __forceinline__ void weights_mf_wave(
                 const int bs = __builtin_amdgcn_readlane(bsl, win);
                 const int kp = __builtin_amdgcn_readlane(bp, win);
                 const double piv = readlane_d(bv, win);
-                const double inv = 1.0 / piv;
+                // (the larger instances keep the division: a fallback copy in
+                // every column step measured slower there)
+                const double inv = NT <= 3 ? recip_div(piv) : 1.0 / piv;
                 const bool b1 = bs != 0;
                 // row c of U, panel columns c .. c0 + 3 (up to the rhs)
                 if (lane == win) {
