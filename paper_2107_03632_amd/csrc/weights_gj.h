@@ -302,20 +302,28 @@ __device__ __forceinline__ void weights_gj_wave(
             if (k >= nk) break;
             const int c = c0 + k;
             // pivot search: exact key (|a| bits, position) over the rows not
-            // yet pivoted
+            // yet pivoted; bb, bp and bv are read only where ba holds
             uint32_t bb = 0;
-            int bp = 0x7fffffff, bsl = 0;
+            int bp = 0, bsl = 0;
             float bv = 0.f;
             bool ba = false;
+            if constexpr (SL == 1) {
+                bb = __float_as_uint(pc[0][k]) & 0x7fffffffu;
+                bp = pos[0];
+                bv = pc[0][k];
+                ba = !done[0];
+            } else {
 #pragma unroll
-            for (int s = 0; s < SL; ++s) {
-                const uint32_t bits = __float_as_uint(pc[s][k]) & 0x7fffffffu;
-                const bool take = !done[s] && (!ba || bits > bb || (bits == bb && pos[s] < bp));
-                bb = take ? bits : bb;
-                bp = take ? pos[s] : bp;
-                bsl = take ? s : bsl;
-                bv = take ? pc[s][k] : bv;
-                ba = ba || !done[s];
+                for (int s = 0; s < SL; ++s) {
+                    const uint32_t bits = __float_as_uint(pc[s][k]) & 0x7fffffffu;
+                    const bool take =
+                        !done[s] && (!ba || bits > bb || (bits == bb && pos[s] < bp));
+                    bb = take ? bits : bb;
+                    bp = take ? pos[s] : bp;
+                    bsl = take ? s : bsl;
+                    bv = take ? pc[s][k] : bv;
+                    ba = ba || !done[s];
+                }
             }
             const uint32_t kh = ba ? bb + 1u : 0u;
             const uint32_t mh = seg_all<kWave, OpMax>(kh, lane);

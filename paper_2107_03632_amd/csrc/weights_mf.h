@@ -102,23 +102,26 @@ struct MfUSel<true, KP, MM> {
 };
 
 // LDS of one block: doubles first, then int32.  Panel buffers alternate
-// between consecutive panels when several wavefronts share them.  With one
-// wavefront the pivot rows of a panel's end overlay its panel buffer (read
-// out before the rows are written), and the packed rows of U with unpadded
-// panel rows keep K = 45 under 10 KB per wavefront: 16 wavefronts per CU
-// (15 with the interleaved rows and panel rows padded to five).  In three
-// dimensions the assembly tables hold a third offset.
+// between consecutive panels when several wavefronts share them; there a
+// panel is row-major with rows padded to five doubles.  With one wavefront
+// the panel is column-major (entry (r, j) at j NP + r: a row's four entries
+// are four conflict-free reads at fixed offsets, and the tile layout's
+// sixteen rows of one column are consecutive), the pivot rows of a panel's
+// end overlay its panel buffer (read out before the rows are written), and
+// with the packed rows of U that keeps K = 45 under 10 KB per wavefront:
+// 16 wavefronts per CU (15 with the interleaved rows and padded panel
+// rows).  In three dimensions the assembly tables hold a third offset.
 template <int KP, int MM, int NT, int NW, int DIM = 2>
 struct MfLds {
     using U = typename MfUSel<NW == 1, KP, MM>::type;  // rows of U
     static constexpr int NP = 16 * NT;
     static constexpr int NPB = NW > 1 ? 2 : 1;       // panel buffers
-    static constexpr int PS = NW > 1 ? 5 : 4;        // panel row stride (doubles)
+    static constexpr int PS = NW > 1 ? 5 : 4;        // panel doubles per row
     static constexpr int NJT = (NT + NW - 1) / NW;  // tile columns per wavefront (at most)
     static constexpr int ASZ3 = DIM == 3 ? (KP * (MM + 3) + 1) & ~1 : 0;
     static constexpr int SZ =                        // U triangle / assembly tables
         U::SZ > ASZ3 ? U::SZ : ASZ3;
-    static constexpr int PAN = SZ;                  // [NPB][NP][PS] panel, row layout
+    static constexpr int PAN = SZ;                  // [NPB][NP][5] or [4][NP] panel
     static constexpr int UB = NW > 1 ? PAN + NPB * NP * PS : PAN;  // [NW][NJT][4][16] pivot rows
     static constexpr int DBL =
         NW > 1 ? UB + NW * NJT * 64 : PAN + (NP * PS > NJT * 64 ? NP * PS : NJT * 64);
@@ -173,7 +176,11 @@ __device__ __forceinline__ void weights_mf_wave(
     double *s_uy = sU + KP;
     double *s_uz = sU + 2 * KP;  // (three dimensions)
     double(*s_P)[MM] = reinterpret_cast<double(*)[MM]>(sU + DIM * KP);
-    double(*s_pan)[NP][B::PS] = reinterpret_cast<double(*)[NP][B::PS]>(sU + B::PAN);
+    double *const s_pan0 = sU + B::PAN;
+    // entry (r, j) of panel buffer pb
+    auto pan = [s_pan0](int pb, int r, int j) -> double & {
+        return NW > 1 ? s_pan0[(pb * NP + r) * 5 + j] : s_pan0[j * NP + r];
+    };
     double(*s_ub)[4][16] = reinterpret_cast<double(*)[4][16]>(sU + B::UB + wv * NJT * 64);
     int32_t *si = reinterpret_cast<int32_t *>(lds + 8 * B::DBL);
     int32_t(*s_rec)[4][2] = reinterpret_cast<int32_t(*)[4][2]>(si + B::REC);
@@ -356,14 +363,14 @@ __device__ __forceinline__ void weights_mf_wave(
             // the panel to row layout through LDS: pc[s][j] = row lane + 64 s,
             // column c0 + j
 #pragma unroll
-            for (int I = 0; I < NT; ++I) s_pan[pb][16 * I + jl][g] = T[I][jt0][rc];
+            for (int I = 0; I < NT; ++I) pan(pb, 16 * I + jl, g) = T[I][jt0][rc];
             lds_order();
             double pc[SL][4];
 #pragma unroll
             for (int s = 0; s < SL; ++s) {
                 const int r = lane + kWave * s;
 #pragma unroll
-                for (int j = 0; j < 4; ++j) pc[s][j] = r < NP ? s_pan[pb][r < NP ? r : 0][j] : 0.0;
+                for (int j = 0; j < 4; ++j) pc[s][j] = r < NP ? pan(pb, r < NP ? r : 0, j) : 0.0;
             }
             uint32_t updm[SL];  // bit j: the row took a multiplier in column c0 + j
 #pragma unroll
@@ -458,7 +465,7 @@ __device__ __forceinline__ void weights_mf_wave(
                 const int r = lane + kWave * s;
                 if (r < NP) {
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) s_pan[pb][r][j] = pc[s][j];
+                    for (int j = 0; j < 4; ++j) pan(pb, r, j) = pc[s][j];
                 }
                 if constexpr (SAVE) {
                     // the multipliers of L, where the row took them
@@ -508,12 +515,12 @@ __device__ __forceinline__ void weights_mf_wave(
 #pragma unroll
             for (int m2 = 1; m2 < 4; ++m2)
 #pragma unroll
-                for (int k2 = 0; k2 < m2; ++k2) l11[m2][k2] = s_pan[pb][pr[m2]][k2];
+                for (int k2 = 0; k2 < m2; ++k2) l11[m2][k2] = pan(pb, pr[m2], k2);
             // B operands: lane (g, j) holds the multiplier of row 16 I + j in
             // panel column c0 + g
             double Bop[NT];
 #pragma unroll
-            for (int I = 0; I < NT; ++I) Bop[I] = s_pan[pb][16 * I + jl][g];
+            for (int I = 0; I < NT; ++I) Bop[I] = pan(pb, 16 * I + jl, g);
             lds_order();  // (with one wavefront the rows below overlay the panel)
             // the panel's pivot rows, in every trailing tile column of this
             // wavefront, to LDS (one uniform branch per row)
@@ -632,7 +639,7 @@ __device__ __forceinline__ void weights_mf_wave(
     if constexpr (SAVE) {
         // the row at each position (in the free panel buffer), then each
         // row of U at its row's index, lanes along the columns
-        int32_t *s_row = reinterpret_cast<int32_t *>(s_pan);
+        int32_t *s_row = reinterpret_cast<int32_t *>(s_pan0);
 #pragma unroll
         for (int s = 0; s < SL; ++s)
             if (pos[s] < K) s_row[pos[s]] = lane + kWave * s;
