@@ -610,7 +610,8 @@ def extras_3d(torch, rb, nodes, dev, stream):
     weights per launch, the weights' fraction of the FP64 peak, and the
     largest error of the weights applied to u = sin(pi x) sin(pi y)
     sin(pi z) (lap u = -3 pi^2 u) over nodes at least 3 h inside the cube;
-    the same for the d/dz weights."""
+    the same for the d/dz weights; and the mixed-order batch (orders 2 / 4
+    per node)."""
     x, y, z = nodes.jittered_cube(100, seed=6)
     X, Y, Z = (torch.as_tensor(a, device=dev) for a in (x, y, z))
     N = x.shape[0]
@@ -637,6 +638,21 @@ def extras_3d(torch, rb, nodes, dev, stream):
             "d_dz": {"ms": ms_dz, "failed": int((stz != 0).sum().item()),
                      "max_abs_err_inner": err_dz}}
         del w, wz, nbr, lap
+    # per-node order uniform on {2, 4} (seeded): one call, bucketed on the
+    # device, against the two single-order launches scaled to their shares
+    nbr = rb.rbffd_knn3(X, Y, Z, 70)
+    order = torch.as_tensor(np.random.default_rng(36).choice(np.array([2, 4], np.int8), N),
+                            device=dev)
+    ms = timed(torch, stream, lambda: rb.rbffd_weights3_batch(X, Y, Z, nbr, order))
+    _, st = rb.rbffd_weights3_batch(X, Y, Z, nbr, order)
+    n4 = int((order == 4).sum().item())
+    single = (n4 * res["m4_n70"]["weights_ms"] + (N - n4) * res["m2_n20"]["weights_ms"]) / N
+    fl = n4 * weights3_flops(70, 4) + (N - n4) * weights3_flops(20, 2)
+    res["mixed_order_m2_m4"] = {
+        "ms": ms, "stencils_per_s": N / (ms * 1e-3), "n_order4": n4,
+        "speedup_vs_single_order_launches": single / ms,
+        "frac_fp64_peak": fl / 1e12 / (ms * 1e-3) / FP64_PEAK_TFLOPS,
+        "failed": int((st != 0).sum().item())}
     return res
 
 

@@ -51,7 +51,7 @@ extern "C" {
 #define RBFFD_NONFINITE 3       /* non-finite coordinate, pivot or solution */
 #define RBFFD_BAD_INDEX 4       /* a support index lies outside [0, n_nodes) */
 #define RBFFD_DUPLICATE 5       /* two support nodes coincide */
-#define RBFFD_BAD_ORDER 6       /* per-node order not in {2,4,6} */
+#define RBFFD_BAD_ORDER 6       /* per-node order not in {2,4,6} ({2,4} in 3-D) */
 
 /* ---- precision ---------------------------------------------------------- */
 /* outcome of rbffd_solve (its `info` output) */
@@ -229,6 +229,24 @@ int rbffd_weights_op(const double *x, const double *y, int64_t n_nodes, const in
  * else 0; w_ik = z_k / s.  An op outside the list is RBFFD_ERR_ARG.
  * ======================================================================== */
 #define RBFFD_OP3_DZ 3
+/* rbffd_weights3_batch: the Laplacian weights of rbffd_weights3 for nodes
+ * of mixed order (the batching form of section V, in d = 3): order
+ * [n_nodes] int8 (device) gives each node's m, 2 or 4, on the supports
+ * n = 20 (m = 2, K = 30) and n = 70 (m = 4, K = 105); nbr [n_nodes]
+ * [k_stride] with k_stride >= 70 (the first n_i columns of row i are
+ * used); w [n_nodes][k_stride] FP64 out, zero past n_i; status [n_nodes]
+ * or NULL.  The nodes are bucketed by order on the device and each class
+ * runs its single-order kernel over its list, so every node's weights and
+ * status are those of rbffd_weights3 at its order, bit for bit.  A node
+ * whose order is neither 2 nor 4 gets NaN weights and RBFFD_BAD_ORDER.
+ * workspace: rbffd_weights3_batch_workspace_size bytes of device memory
+ * (owned by the caller, RBFFD_ERR_WORKSPACE if short); no host
+ * synchronisation.  Argument errors as in rbffd_weights3. */
+int rbffd_weights3_batch_workspace_size(int64_t n_nodes, size_t *bytes /* host */);
+int rbffd_weights3_batch(const double *x, const double *y, const double *z, int64_t n_nodes,
+                         const int32_t *nbr, int32_t k_stride, const int8_t *order, double *w,
+                         int32_t *status, void *workspace, size_t workspace_bytes,
+                         void *stream);
 int rbffd_knn3_workspace_size(int64_t n_nodes, int32_t k, size_t *bytes /* host */);
 int rbffd_knn3(const double *x, const double *y, const double *z, int64_t n_nodes, int32_t k,
                int32_t *nbr, void *workspace, size_t workspace_bytes, void *stream);

@@ -66,6 +66,8 @@ def _load():
             "rbffd_knn3": ([P, P, P, I64, I32, P, P, ctypes.c_size_t, P], ctypes.c_int),
             "rbffd_weights3": ([P, P, P, I64, P, I32, I32, I32, P, P, P], ctypes.c_int),
             "rbffd_weights3_op": ([P, P, P, I64, P, I32, I32, I32, I32, P, P, P], ctypes.c_int),
+            "rbffd_weights3_batch_workspace_size": ([I64, PSZ], ctypes.c_int),
+            "rbffd_weights3_batch": ([P, P, P, I64, P, I32, P, P, P, P, SZ, P], ctypes.c_int),
             "rbffd_solve_workspace_size": ([I64, PSZ], ctypes.c_int),
             "rbffd_solve": ([I64, P, P, P, P, P, ctypes.c_double, I32,
                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
@@ -313,8 +315,8 @@ def rbffd_knn3(x, y, z, k: int, out=None):
 
 def rbffd_weights3(x, y, z, nbr, m: int = 2, n: int = 20, out=None, status=None, op=None):
     """Weights of eq. (1) for nodes in R^3 (r^3 + monomials of degree <= m,
-    m = 2 with 10 <= n <= 54, or m = 4 with n = 70), FP64: the Laplacian, or
-    with op one of OP_DX, OP_DY, OP3_DZ a first derivative.
+    m = 2 with 10 <= n <= 54, or m = 4 with 35 <= n <= 76), FP64: the
+    Laplacian, or with op one of OP_DX, OP_DY, OP3_DZ a first derivative.
     Returns (w [N, k_stride], status [N])."""
     lib = _load()
     x, y, nbr, N, ks = _nodes2(x, y, nbr)
@@ -328,6 +330,26 @@ def rbffd_weights3(x, y, z, nbr, m: int = 2, n: int = 20, out=None, status=None,
         _check(lib.rbffd_weights3_op(_p(x), _p(y), _p(z), N, _p(nbr), ks, int(m), int(n),
                                      int(op), _p(w), _p(st), _stream(x.device)),
                "rbffd_weights3_op")
+    return w, st
+
+
+def rbffd_weights3_batch(x, y, z, nbr, order, out=None, status=None):
+    """3-D Laplacian weights for a per-node order (int8 [N], 2 or 4) on the
+    supports n = 20 / 70: nbr [N, k_stride] with k_stride >= 70.  Each
+    node's weights and status are rbffd_weights3's at its order.
+    Returns (w [N, k_stride], status [N])."""
+    lib = _load()
+    x, y, nbr, N, ks = _nodes2(x, y, nbr)
+    z = _vec(z, N, torch.float64, "z")
+    order = _vec(order, N, torch.int8, "order")
+    if ks < 70:
+        raise ValueError(f"nbr needs at least 70 columns for the m = 4 class, got {ks}")
+    w = _out(out, (N, ks), torch.float64, "out", x.device)
+    st = _out(status, (N,), torch.int32, "status", x.device)
+    ws = _workspace(_size(lib.rbffd_weights3_batch_workspace_size, N), x.device)
+    _check(lib.rbffd_weights3_batch(_p(x), _p(y), _p(z), N, _p(nbr), ks, _p(order), _p(w),
+                                    _p(st), _p(ws), ws.numel(), _stream(x.device)),
+           "rbffd_weights3_batch")
     return w, st
 
 

@@ -787,6 +787,56 @@ __attribute__((amdgpu_waves_per_eu(OCC))) void weights_mf3_kernel(
     }
 }
 
+// The same over a row list counted on the device (a class of a 3-D
+// mixed-order batch): a grid of at most kListBlocks blocks walks the list
+// with a stride; stencil t of the list is node rows[t].
+template <int KP, int NFIX, int MFIX, int NW, int OCC, int OP>
+__global__ __launch_bounds__(NW * kWave)
+__attribute__((amdgpu_waves_per_eu(OCC))) void weights_mf3_list_kernel(
+    const double *__restrict__ x, const double *__restrict__ y, const double *__restrict__ z,
+    int64_t n_nodes, const int32_t *__restrict__ nbr, int32_t k_stride,
+    const int32_t *__restrict__ rows, const int32_t *__restrict__ n_rows_dev,
+    double *__restrict__ w, int32_t *__restrict__ status) {
+    __shared__ __align__(16) char lds[mf3_lds_bytes<KP, NFIX, MFIX, NW>()];
+    static_assert(NFIX > 0, "fixed supports");
+    const int64_t c = *n_rows_dev;
+    for (int64_t t = blockIdx.x; t < c; t += gridDim.x) {
+        // the previous stencil's LDS is free (wavefront 0 ends its back
+        // substitution alone)
+        if constexpr (NW > 1)
+            __syncthreads();
+        else
+            lds_order();
+        const int64_t i = rows[t];
+        if constexpr (NW <= 2) {
+            if (NW > 1 && ((threadIdx.x >> 6) & 1))
+                weights_mf_wave<KP, NFIX, MFIX, NW, NW - 1, false, OP, 3>(
+                    x, y, z, n_nodes, nbr, k_stride, i, w, status, SaveView{}, RBFFD_OK, lds);
+            else
+                weights_mf_wave<KP, NFIX, MFIX, NW, 0, false, OP, 3>(
+                    x, y, z, n_nodes, nbr, k_stride, i, w, status, SaveView{}, RBFFD_OK, lds);
+        } else {
+            weights_mf_wave<KP, NFIX, MFIX, NW, -1, false, OP, 3>(
+                x, y, z, n_nodes, nbr, k_stride, i, w, status, SaveView{}, RBFFD_OK, lds);
+        }
+    }
+}
+
+// rows, n_rows_dev: a device list of at most max_rows node ids and its
+// length.
+template <int KP, int NFIX, int MFIX, int NW, int OCC, int OP>
+inline int launch_mf3_list(const double *x, const double *y, const double *z, int64_t n_nodes,
+                           const int32_t *nbr, int32_t k_stride, const int32_t *rows,
+                           const int32_t *n_rows_dev, int64_t max_rows, double *w,
+                           int32_t *status, hipStream_t stream) {
+    if (max_rows <= 0) return RBFFD_SUCCESS;
+    const int64_t blocks = max_rows < kListBlocks ? max_rows : kListBlocks;
+    hipLaunchKernelGGL((weights_mf3_list_kernel<KP, NFIX, MFIX, NW, OCC, OP>),
+                       dim3((unsigned)blocks), dim3(NW * kWave), 0, stream, x, y, z, n_nodes,
+                       nbr, k_stride, rows, n_rows_dev, w, status);
+    return last_launch_rc();
+}
+
 // n: the support size when NFIX = 0 (K = n + M <= KP), else ignored.
 template <int KP, int NFIX, int MFIX, int NW, int OCC, int OP>
 inline int launch_mf3(const double *x, const double *y, const double *z, int64_t n_nodes,

@@ -495,5 +495,28 @@ __attribute__((amdgpu_waves_per_eu(OCC))) void weights_mf2_kernel(
                                               w, status, ok_code, lds[wave]);
 }
 
+// The same over a row list counted on the device (a class of a 3-D
+// mixed-order batch): a grid of at most kListBlocks2 blocks walks the list
+// with a stride, two list entries per wavefront.
+constexpr int64_t kListBlocks2 = 8192;
+
+template <int KP, int NFIX, int MFIX, int OP, int DIM, int WPB, int OCC>
+__global__ __launch_bounds__(WPB * kWave)
+__attribute__((amdgpu_waves_per_eu(OCC))) void weights_mf2_list_kernel(
+    const double *__restrict__ x, const double *__restrict__ y, const double *__restrict__ z,
+    int64_t n_nodes, const int32_t *__restrict__ nbr, int32_t k_stride,
+    const int32_t *__restrict__ rows, const int32_t *__restrict__ n_rows_dev,
+    double *__restrict__ w, int32_t *__restrict__ status, int32_t ok_code) {
+    __shared__ __align__(16) char lds[WPB][mf2_lds_bytes<KP, NFIX, MFIX, DIM>()];
+    const int wave = threadIdx.x >> 6;
+    const int64_t c = *n_rows_dev;
+    for (int64_t i0 = 2 * ((int64_t)blockIdx.x * WPB + wave); i0 < c;
+         i0 += 2 * (int64_t)gridDim.x * WPB) {
+        lds_order();  // one wavefront: its LDS accesses stay in program order
+        weights_mf2_wave<KP, NFIX, MFIX, OP, DIM>(x, y, z, n_nodes, nbr, k_stride, rows, i0, c,
+                                                  w, status, ok_code, lds[wave]);
+    }
+}
+
 }  // namespace wk
 }  // namespace rbffd

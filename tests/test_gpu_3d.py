@@ -341,3 +341,94 @@ def test_3d_m4_full_size_sampled():
         worst = max(worst, rel.max().item())
     say("  worst relative residual over the 35 monomials", worst)
     assert worst < 1e-9
+
+
+# ---- mixed-order batch in three dimensions (rbffd_weights3_batch) --------
+
+def _batch3_ref(x, y, z, nbr, order):
+    """The oracle's weights at each node's order (n = 20 for m = 2, 70 for
+    m = 4); NaN weights and BAD_ORDER where the order is neither."""
+    N, ks = nbr.shape
+    w = np.full((N, ks), np.nan)
+    st = np.full(N, rb.BAD_ORDER, np.int32)
+    for m, n in ((2, 20), (4, 70)):
+        rows = np.nonzero(order == m)[0]
+        if rows.size:
+            w[rows], st[rows] = oracle.weights3(x, y, z, nbr, m, n, rows=rows)
+    return w, st
+
+
+@pytest.mark.parametrize("mix", ["mixed", "all2", "all4", "bad"])
+def test_weights3_batch_bit_exact(mix):
+    """Per-node orders 2 / 4 (and invalid ones) on a 12^3 jittered lattice
+    with a stride of 72 columns: every node's weights and status are the
+    oracle's at its order, double for double."""
+    x, y, z = nodes.jittered_cube(12, seed=31)
+    N = x.shape[0]
+    nbr = np.concatenate([oracle.knn3(x, y, z, 70), np.zeros((N, 2), np.int32)], axis=1)
+    rng = np.random.default_rng(32)
+    order = {"mixed": rng.choice(np.array([2, 4], np.int8), N),
+             "all2": np.full(N, 2, np.int8), "all4": np.full(N, 4, np.int8),
+             "bad": rng.choice(np.array([2, 4, 3, 0, 6, -1], np.int8), N)}[mix]
+    say("3-D batch", mix, N)
+    w_ref, st_ref = _batch3_ref(x, y, z, nbr, order)
+    w, st = rb.rbffd_weights3_batch(dev(x), dev(y), dev(z), dev(nbr), dev(order))
+    w, st = host(w), host(st)
+    assert np.array_equal(st, st_ref)
+    assert np.array_equal(w, w_ref, equal_nan=True)
+
+
+def test_weights3_batch_full_size_matches_single_order():
+    """The jittered 100^3 lattice with orders drawn uniformly from {2, 4}:
+    the batch gives, bit for bit, the single-order launches' weights at each
+    node's order, and sampled rows match the oracle."""
+    x, y, z = nodes.jittered_cube(100, seed=6)
+    N = x.shape[0]
+    say("3-D batch cube", N)
+    X, Y, Z = dev(x), dev(y), dev(z)
+    nb_t = rb.rbffd_knn3(X, Y, Z, 70)
+    order = np.random.default_rng(33).choice(np.array([2, 4], np.int8), N)
+    O = dev(order)
+    w_b, st_b = rb.rbffd_weights3_batch(X, Y, Z, nb_t, O)
+    st_b = host(st_b)
+    assert np.all(st_b == 0)
+    for m, n in ((2, 20), (4, 70)):
+        sel = torch.as_tensor(order == m).cuda()
+        w_s, st_s = rb.rbffd_weights3(X, Y, Z, nb_t, m, n)
+        assert torch.equal(w_b[sel], w_s[sel]), m
+        del w_s, st_s
+    rows = np.sort(np.random.default_rng(34).choice(N, 60, replace=False))
+    nbr_rows = host(nb_t[torch.as_tensor(rows).cuda()])
+    nbr_s = np.zeros((N, 70), np.int32)
+    nbr_s[rows] = nbr_rows
+    w_ref = np.zeros((rows.size, 70))
+    for m, n in ((2, 20), (4, 70)):
+        pick = order[rows] == m
+        if pick.any():
+            w_ref[pick], st_r = oracle.weights3(x, y, z, nbr_s, m, n, rows=rows[pick])
+            assert np.all(st_r == 0)
+    assert np.array_equal(host(w_b[torch.as_tensor(rows).cuda()]), w_ref)
+
+
+def test_weights3_batch_argument_errors():
+    x, y, z = nodes.jittered_cube(5, seed=35)
+    N = x.shape[0]
+    nbr = oracle.knn3(x, y, z, 70)
+    X, Y, Z = dev(x), dev(y), dev(z)
+    order = dev(np.full(N, 2, np.int8))
+    with pytest.raises(ValueError):  # fewer than 70 columns
+        rb.rbffd_weights3_batch(X, Y, Z, dev(nbr[:, :60]), order)
+    with pytest.raises(ValueError):  # order of the wrong length
+        rb.rbffd_weights3_batch(X, Y, Z, dev(nbr), dev(np.full(N - 1, 2, np.int8)))
+    lib = rb._load()
+    NB = dev(nbr)
+    w = torch.empty((N, 70), dtype=torch.float64, device="cuda")
+    ws = torch.empty(16, dtype=torch.uint8, device="cuda")
+    rc = lib.rbffd_weights3_batch(rb._p(X), rb._p(Y), rb._p(Z), N, rb._p(NB), 70,
+                                  rb._p(order), rb._p(w), None, rb._p(ws), 16,
+                                  rb._stream(X.device))
+    assert rc == -2  # RBFFD_ERR_WORKSPACE
+    rc = lib.rbffd_weights3_batch(rb._p(X), rb._p(Y), rb._p(Z), N, rb._p(NB), 60,
+                                  rb._p(order), rb._p(w), None, rb._p(ws), 16,
+                                  rb._stream(X.device))
+    assert rc == -1  # RBFFD_ERR_ARG
