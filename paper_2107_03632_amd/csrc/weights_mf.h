@@ -788,8 +788,11 @@ __attribute__((amdgpu_waves_per_eu(OCC))) void weights_mf3_kernel(
 }
 
 // The same over a row list counted on the device (a class of a 3-D
-// mixed-order batch): a grid of at most kListBlocks blocks walks the list
-// with a stride; stencil t of the list is node rows[t].
+// mixed-order batch): one block per possible entry, block t computing node
+// rows[t] or returning at once past the count.  (A capped grid walking the
+// list kept more values live across its loop: 256 VGPRs with spills
+// against 168; the idle blocks of a half-empty list cost about 0.2 ms per
+// million.)
 template <int KP, int NFIX, int MFIX, int NW, int OCC, int OP>
 __global__ __launch_bounds__(NW * kWave)
 __attribute__((amdgpu_waves_per_eu(OCC))) void weights_mf3_list_kernel(
@@ -799,26 +802,19 @@ __attribute__((amdgpu_waves_per_eu(OCC))) void weights_mf3_list_kernel(
     double *__restrict__ w, int32_t *__restrict__ status) {
     __shared__ __align__(16) char lds[mf3_lds_bytes<KP, NFIX, MFIX, NW>()];
     static_assert(NFIX > 0, "fixed supports");
-    const int64_t c = *n_rows_dev;
-    for (int64_t t = blockIdx.x; t < c; t += gridDim.x) {
-        // the previous stencil's LDS is free (wavefront 0 ends its back
-        // substitution alone)
-        if constexpr (NW > 1)
-            __syncthreads();
-        else
-            lds_order();
-        const int64_t i = rows[t];
-        if constexpr (NW <= 2) {
-            if (NW > 1 && ((threadIdx.x >> 6) & 1))
-                weights_mf_wave<KP, NFIX, MFIX, NW, NW - 1, false, OP, 3>(
-                    x, y, z, n_nodes, nbr, k_stride, i, w, status, SaveView{}, RBFFD_OK, lds);
-            else
-                weights_mf_wave<KP, NFIX, MFIX, NW, 0, false, OP, 3>(
-                    x, y, z, n_nodes, nbr, k_stride, i, w, status, SaveView{}, RBFFD_OK, lds);
-        } else {
-            weights_mf_wave<KP, NFIX, MFIX, NW, -1, false, OP, 3>(
+    const int64_t t = (int64_t)blockIdx.x;
+    if (t >= *n_rows_dev) return;  // whole block idle
+    const int64_t i = rows[t];
+    if constexpr (NW <= 2) {
+        if (NW > 1 && ((threadIdx.x >> 6) & 1))
+            weights_mf_wave<KP, NFIX, MFIX, NW, NW - 1, false, OP, 3>(
                 x, y, z, n_nodes, nbr, k_stride, i, w, status, SaveView{}, RBFFD_OK, lds);
-        }
+        else
+            weights_mf_wave<KP, NFIX, MFIX, NW, 0, false, OP, 3>(
+                x, y, z, n_nodes, nbr, k_stride, i, w, status, SaveView{}, RBFFD_OK, lds);
+    } else {
+        weights_mf_wave<KP, NFIX, MFIX, NW, -1, false, OP, 3>(
+            x, y, z, n_nodes, nbr, k_stride, i, w, status, SaveView{}, RBFFD_OK, lds);
     }
 }
 
@@ -830,9 +826,9 @@ inline int launch_mf3_list(const double *x, const double *y, const double *z, in
                            const int32_t *n_rows_dev, int64_t max_rows, double *w,
                            int32_t *status, hipStream_t stream) {
     if (max_rows <= 0) return RBFFD_SUCCESS;
-    const int64_t blocks = max_rows < kListBlocks ? max_rows : kListBlocks;
+    if (max_rows > 0x7fffffff) return RBFFD_ERR_UNSUPPORTED;
     hipLaunchKernelGGL((weights_mf3_list_kernel<KP, NFIX, MFIX, NW, OCC, OP>),
-                       dim3((unsigned)blocks), dim3(NW * kWave), 0, stream, x, y, z, n_nodes,
+                       dim3((unsigned)max_rows), dim3(NW * kWave), 0, stream, x, y, z, n_nodes,
                        nbr, k_stride, rows, n_rows_dev, w, status);
     return last_launch_rc();
 }
