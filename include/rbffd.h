@@ -259,7 +259,7 @@ int rbffd_weights3_op(const double *x, const double *y, const double *z, int64_t
 
 /* ==========================================================================
  * Tuning of the mixed-order batch (rbffd_weights with a per-node order and
- * the standard supports n = 12/30/56, FP64), in one of two forms:
+ * the standard supports n = 12/30/56, FP64), in one of three forms:
  *   per_order = 0: one persistent launch: blocks_per_cu blocks of 128
  *     threads per compute unit pull tiles from a work queue, largest
  *     systems first; groups_per_tile[q] sets the tile size of order
@@ -268,7 +268,10 @@ int rbffd_weights3_op(const double *x, const double *y, const double *z, int64_t
  *   per_order = 1: one persistent launch per order on the same stream
  *     (m = 6, 4, 2), each with its single-order kernel's block shape and
  *     occupancy, order_blocks_per_cu[q] blocks per compute unit walking
- *     that order's list; nothing is cleared between calls.
+ *     that order's list; nothing is cleared between calls;
+ *   per_order = 2: one launch per order (m = 6, 4, 2) of the single-order
+ *     kernels themselves, one block (or one 8-stencil group at m = 2) per
+ *     possible list entry, those past the list's length returning at once.
  * When the factors are saved (the adjoint's forward) the one-launch form
  * runs.  The values only change speed, never results.  This table is the
  * library's only process-wide state; set it before launching (e.g. from
@@ -279,7 +282,7 @@ int rbffd_weights3_op(const double *x, const double *y, const double *z, int64_t
 typedef struct rbffd_batch_tuning {
     int32_t blocks_per_cu;          /* 1..64 */
     int32_t groups_per_tile[3];     /* 1..64 each, for m = 2, 4, 6 */
-    int32_t per_order;              /* 0 or 1 */
+    int32_t per_order;              /* 0, 1 or 2 */
     int32_t order_blocks_per_cu[3]; /* 1..64 each, for m = 2, 4, 6 */
 } rbffd_batch_tuning;
 int rbffd_batch_tuning_set(const rbffd_batch_tuning *tuning /* host, or NULL */);

@@ -1,9 +1,10 @@
 """Autotuner for the mixed-order weights batch.
 
-Times every candidate of both forms on a given node set and keeps the
-fastest: the one persistent launch (blocks per compute unit, tile size per
-order) and one persistent launch per order (blocks per compute unit of each
-order's launch).  The tuning only changes speed, never results.  The choice is saved to
+Times every candidate of the three forms on a given node set and keeps
+the fastest: the one persistent launch (blocks per compute unit, tile size
+per order), one persistent launch per order (blocks per compute unit of
+each order's launch), and one launch per order of the single-order kernels
+with a block per list entry (no parameters).  The tuning only changes speed, never results.  The choice is saved to
 batch_tuning.json next to the library, which the binding applies whenever
 the library is loaded.
 
@@ -73,6 +74,9 @@ def tune_batch(x, y, nbr, order, reps: int = 3, candidates=CANDIDATES,
                             1, [c["bpc2"], c["bpc4"], c["bpc6"]])
         ms = _time_ms(lambda: rb.rbffd_weights(x, y, nbr, order=order), reps)
         table.append({**c, "per_order": 1, "ms": ms})
+    rb.batch_tuning_set(best1["blocks_per_cu"], [best1["gpt2"], best1["gpt4"], best1["gpt6"]], 2)
+    ms = _time_ms(lambda: rb.rbffd_weights(x, y, nbr, order=order), reps)
+    table.append({"per_order": 2, "ms": ms})
     best = min(table, key=lambda r: r["ms"])
     best2 = min((r for r in table if r["per_order"] == 1), key=lambda r: r["ms"])
     choice = {"blocks_per_cu": best1["blocks_per_cu"],
@@ -82,7 +86,7 @@ def tune_batch(x, y, nbr, order, reps: int = 3, candidates=CANDIDATES,
     rb.batch_tuning_set(choice["blocks_per_cu"], choice["groups_per_tile"], choice["per_order"],
                         choice["order_blocks_per_cu"])
     return {"choice": choice, "ms": best["ms"], "one_launch_ms": best1["ms"],
-            "per_order_ms": best2["ms"], "table": table}
+            "per_order_ms": best2["ms"], "per_order_block_per_entry_ms": ms, "table": table}
 
 
 def main(argv=None) -> int:

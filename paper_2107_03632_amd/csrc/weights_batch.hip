@@ -22,6 +22,7 @@
 
 #include "weights_cs.h"
 #include "weights_mf.h"
+#include "weights_ms.h"
 
 namespace rbffd {
 namespace {
@@ -183,6 +184,26 @@ int weights_fp64_batch(const double *x, const double *y, int64_t n_nodes, const 
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return hip_rc(e);
+    if (!sv_lu && g_per_order.load() == 2) {
+        // one launch per order with the single-order kernels themselves:
+        // one block (K = 84, 45) or one group of 8 stencils (K = 18) per
+        // possible list entry, the blocks past the list's length returning
+        // at once (no loop: the looping kernels above keep more values live
+        // and spill)
+        const int64_t N = n_nodes;
+        hipLaunchKernelGGL((wk::weights_mf_kernel<84, 56, 6, 2, 2, false, 0>), dim3((unsigned)N),
+                           dim3(2 * kWave), 0, stream, x, y, n_nodes, nbr, k_stride,
+                           lists + 2 * N, counts + 2, N, w, status, wk::SaveView{}, RBFFD_OK);
+        hipLaunchKernelGGL((wk::weights_mf_kernel<45, 30, 4, 1, 4, false, 0>), dim3((unsigned)N),
+                           dim3(kWave), 0, stream, x, y, n_nodes, nbr, k_stride, lists + N,
+                           counts + 1, N, w, status, wk::SaveView{}, RBFFD_OK);
+        hipLaunchKernelGGL((wk::weights_ms_kernel<18, kSeg18, kSl18, 12, 2, RBFFD_BATCH_OCC18,
+                                                  false, 0>),
+                           dim3((unsigned)ceil_div(N, kG18)), dim3(kWave), 0, stream, x, y,
+                           n_nodes, nbr, k_stride, lists, counts, N, 12, 2, w, status, nullptr,
+                           nullptr, nullptr, nullptr, 0, RBFFD_OK);
+        return last_launch_rc();
+    }
     if (!sv_lu && g_per_order.load()) {
         // largest systems first
         const unsigned b6 = (unsigned)(g_order_bpc[2].load() * cus);
@@ -229,7 +250,7 @@ extern "C" int rbffd_batch_tuning_set(const rbffd_batch_tuning *t) {
         if (t->groups_per_tile[q] < 1 || t->groups_per_tile[q] > 64 ||
             t->order_blocks_per_cu[q] < 1 || t->order_blocks_per_cu[q] > 64)
             return RBFFD_ERR_ARG;
-    if (t->per_order != 0 && t->per_order != 1) return RBFFD_ERR_ARG;
+    if (t->per_order < 0 || t->per_order > 2) return RBFFD_ERR_ARG;
     rbffd::g_blocks_per_cu = t->blocks_per_cu;
     for (int q = 0; q < 3; ++q) rbffd::g_gpt[q] = t->groups_per_tile[q];
     rbffd::g_per_order = t->per_order;

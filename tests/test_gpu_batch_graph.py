@@ -41,7 +41,7 @@ def test_batch_tuning_changes_nothing_but_speed():
         for bpc, gpt, po, obpc in [(1, [1, 1, 1], 0, [12, 16, 4]), (2, [4, 2, 2], 0, [1, 1, 1]),
                                    (4, [2, 1, 2], 0, [12, 16, 4]), (3, [1, 2, 1], 0, [12, 16, 4]),
                                    (2, [1, 1, 1], 1, [12, 16, 4]), (2, [1, 1, 1], 1, [1, 1, 1]),
-                                   (2, [1, 1, 1], 1, [64, 3, 7])]:
+                                   (2, [1, 1, 1], 1, [64, 3, 7]), (2, [1, 1, 1], 2, [12, 16, 4])]:
             rb.batch_tuning_set(bpc, gpt, po, obpc)
             assert rb.batch_tuning_get() == {"blocks_per_cu": bpc, "groups_per_tile": gpt,
                                              "per_order": po, "order_blocks_per_cu": obpc}
@@ -62,13 +62,13 @@ def test_batch_tuning_changes_nothing_but_speed():
     with pytest.raises(rb.RbffdError):
         rb.batch_tuning_set(0, [1, 1, 1])
     with pytest.raises(rb.RbffdError):
-        rb.batch_tuning_set(2, [1, 1, 1], 2)
+        rb.batch_tuning_set(2, [1, 1, 1], 3)
     with pytest.raises(rb.RbffdError):
         rb.batch_tuning_set(2, [1, 1, 1], 1, [1, 65, 1])
     assert rb.batch_tuning_get() == saved
 
 
-@pytest.fixture(params=[0, 1], ids=["one_launch", "per_order"])
+@pytest.fixture(params=[0, 1, 2], ids=["one_launch", "per_order", "per_order_blocks"])
 def batch_form(request):
     saved = rb.batch_tuning_get()
     rb.batch_tuning_set(saved["blocks_per_cu"], saved["groups_per_tile"], request.param,
