@@ -1,9 +1,12 @@
-// Mixed-order batch of FP64 stencils in one persistent launch.
+// Mixed-order batch of FP64 stencils.
 //
 // The nodes have been bucketed by order (m = 2, 4, 6 -> system sizes 18, 45,
-// 84).  A fixed grid of 128-thread blocks pulls tiles from an atomic work
-// queue, largest systems first so the long tiles start early and the short
-// ones fill the tail:
+// 84).  Three forms, chosen by the tuning table: one persistent launch
+// (below), one looping launch per order (class*_kernel), or one launch per
+// order of the single-order kernels with a block per list entry.  In the
+// persistent launch a fixed grid of 128-thread blocks pulls tiles from an
+// atomic work queue, largest systems first so the long tiles start early
+// and the short ones fill the tail:
 //   * an order-6 tile is gpt[2] stencils, each spread over both wavefronts
 //     of the block: the blocked LU with the trailing updates on the matrix
 //     cores (weights_mf.h), or, when the factors are saved for the adjoint,
