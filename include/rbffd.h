@@ -191,6 +191,22 @@ int rbffd_weights(const double *x, const double *y, int64_t n_nodes,
 int rbffd_weights_op(const double *x, const double *y, int64_t n_nodes, const int32_t *nbr,
                      int32_t k_stride, int32_t m, int32_t n, int32_t op, double *w,
                      int32_t *status, void *stream);
+/* rbffd_weights_op_batch: the d/dx or d/dy weights of rbffd_weights_op for
+ * nodes of mixed order (the batching form of section V applied to the
+ * derivative operators): order [n_nodes] int8 (device), m_i in {2, 4, 6}
+ * on the standard supports n = 12 / 30 / 56; nbr [n_nodes][k_stride] with
+ * k_stride >= 56; op RBFFD_OP_DX or RBFFD_OP_DY.  Bucketed by order on the
+ * device, then one launch per order (K = 84 first) of rbffd_weights_op's
+ * kernels with a block per possible list entry, so each node's weights and
+ * status are rbffd_weights_op's at its order, bit for bit; a node whose
+ * order is not 2, 4 or 6 gets NaN weights and RBFFD_BAD_ORDER.
+ * workspace: rbffd_weights_op_batch_workspace_size bytes of device memory
+ * (RBFFD_ERR_WORKSPACE if short).  No host synchronisation. */
+int rbffd_weights_op_batch_workspace_size(int64_t n_nodes, size_t *bytes /* host */);
+int rbffd_weights_op_batch(const double *x, const double *y, int64_t n_nodes,
+                           const int32_t *nbr, int32_t k_stride, const int8_t *order,
+                           int32_t op, double *w, int32_t *status, void *workspace,
+                           size_t workspace_bytes, void *stream);
 
 /* ==========================================================================
  * Three-dimensional nodes (eq. (1) and eq. (2) hold for any dimension d; the

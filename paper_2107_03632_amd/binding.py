@@ -62,6 +62,8 @@ def _load():
             "rbffd_time_steps": ([I64, P, I32, I32, P, P, P, ctypes.c_double, I64, P, P, P, SZ,
                                   P], ctypes.c_int),
             "rbffd_weights_op": ([P, P, I64, P, I32, I32, I32, I32, P, P, P], ctypes.c_int),
+            "rbffd_weights_op_batch_workspace_size": ([I64, PSZ], ctypes.c_int),
+            "rbffd_weights_op_batch": ([P, P, I64, P, I32, P, I32, P, P, P, SZ, P], ctypes.c_int),
             "rbffd_knn3_workspace_size": ([I64, I32, PSZ], ctypes.c_int),
             "rbffd_knn3": ([P, P, P, I64, I32, P, P, ctypes.c_size_t, P], ctypes.c_int),
             "rbffd_weights3": ([P, P, P, I64, P, I32, I32, I32, P, P, P], ctypes.c_int),
@@ -330,6 +332,25 @@ def rbffd_weights3(x, y, z, nbr, m: int = 2, n: int = 20, out=None, status=None,
         _check(lib.rbffd_weights3_op(_p(x), _p(y), _p(z), N, _p(nbr), ks, int(m), int(n),
                                      int(op), _p(w), _p(st), _stream(x.device)),
                "rbffd_weights3_op")
+    return w, st
+
+
+def rbffd_weights_op_batch(x, y, nbr, order, op: int, out=None, status=None):
+    """d/dx (OP_DX) or d/dy (OP_DY) weights for a per-node order (int8 [N],
+    2, 4 or 6) on the supports n = 12 / 30 / 56: nbr [N, k_stride] with
+    k_stride >= 56.  Each node's weights and status are rbffd_weights_op's at
+    its order.  Returns (w [N, k_stride], status [N])."""
+    lib = _load()
+    x, y, nbr, N, ks = _nodes2(x, y, nbr)
+    order = _vec(order, N, torch.int8, "order")
+    if ks < 56:
+        raise ValueError(f"nbr needs at least 56 columns for the m = 6 class, got {ks}")
+    w = _out(out, (N, ks), torch.float64, "out", x.device)
+    st = _out(status, (N,), torch.int32, "status", x.device)
+    ws = _workspace(_size(lib.rbffd_weights_op_batch_workspace_size, N), x.device)
+    _check(lib.rbffd_weights_op_batch(_p(x), _p(y), N, _p(nbr), ks, _p(order), int(op), _p(w),
+                                      _p(st), _p(ws), ws.numel(), _stream(x.device)),
+           "rbffd_weights_op_batch")
     return w, st
 
 

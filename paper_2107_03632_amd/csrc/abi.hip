@@ -137,6 +137,14 @@ OrderWs carve_order(void *base, int64_t n_nodes, bool has_order, bool mixed) {
 bool valid_m(int m) { return m == 2 || m == 4 || m == 6; }
 
 }  // namespace
+
+// The bucketing above for the operator batch: counts [3] must be zero.
+int bucket_orders(const int8_t *order, int64_t n_nodes, int32_t k_stride, int32_t *counts,
+                  int32_t *lists, double *w, int32_t *status, hipStream_t s) {
+    hipLaunchKernelGGL(bucket_by_order, dim3((unsigned)ceil_div(n_nodes, kThreads)),
+                       dim3(kThreads), 0, s, order, n_nodes, k_stride, counts, lists, w, status);
+    return last_launch_rc();
+}
 }  // namespace rbffd
 
 using namespace rbffd;

@@ -725,11 +725,15 @@ __attribute__((amdgpu_waves_per_eu(OCC))) void weights_mf_list_kernel(
 }
 
 // sv.lu set: the saving instance (one wavefront per stencil only).
+// n_rows_dev set: a device-counted list of at most n_rows entries, walked
+// by a capped grid, or with per_entry by one block per possible entry (the
+// blocks past the count return at once; no loop, so the register allocation
+// of the plain kernel).
 template <int KP, int NFIX, int MFIX, int NW, int OCC, int OP = 0>
 inline int launch_mf(const double *x, const double *y, int64_t n_nodes, const int32_t *nbr,
                      int32_t k_stride, const int32_t *rows, const int32_t *n_rows_dev,
                      int64_t n_rows, double *w, int32_t *status, const SaveView &sv,
-                     int32_t ok_code, hipStream_t stream) {
+                     int32_t ok_code, hipStream_t stream, bool per_entry = false) {
     if (n_rows <= 0) return RBFFD_SUCCESS;
     if (n_rows > 0x7fffffff) return RBFFD_ERR_UNSUPPORTED;
     if (sv.lu && OP != 0) return RBFFD_ERR_UNSUPPORTED;  // factors: the Laplacian only
@@ -744,7 +748,7 @@ inline int launch_mf(const double *x, const double *y, int64_t n_nodes, const in
     } else {
         if (sv.lu) return RBFFD_ERR_UNSUPPORTED;
     }
-    if (n_rows_dev) {
+    if (n_rows_dev && !per_entry) {
         const int64_t blocks = n_rows < kListBlocks ? n_rows : kListBlocks;
         hipLaunchKernelGGL((weights_mf_list_kernel<KP, NFIX, MFIX, NW, OCC, OP>),
                            dim3((unsigned)blocks), dim3(NW * kWave), 0, stream, x, y, n_nodes,

@@ -610,13 +610,14 @@ template <int KP, int SEG, int SL, int NFIX, int MFIX, int OCC = 0, int OP = 0>
 inline int launch_ms(const double *x, const double *y, int64_t n_nodes, const int32_t *nbr,
                      int32_t k_stride, const int32_t *rows, const int32_t *n_rows_dev,
                      int64_t n_rows, int n, int m, double *w, int32_t *status,
-                     const SaveView &sv, int32_t ok_code, hipStream_t stream) {
+                     const SaveView &sv, int32_t ok_code, hipStream_t stream,
+                     bool per_entry = false) {
     constexpr int GPB = kWave / SEG;
     if (n_rows <= 0) return RBFFD_SUCCESS;
     const int64_t blocks = ceil_div(n_rows, GPB);
     if (blocks > 0x7fffffff) return RBFFD_ERR_UNSUPPORTED;
     if (sv.lu && OP != 0) return RBFFD_ERR_UNSUPPORTED;  // factors: the Laplacian only
-    if (n_rows_dev && !sv.lu) {
+    if (n_rows_dev && !sv.lu && !per_entry) {  // (per_entry: one group per block)
         const int64_t lb = blocks < kMsListBlocks ? blocks : kMsListBlocks;
         hipLaunchKernelGGL((weights_ms_list_kernel<KP, SEG, SL, NFIX, MFIX, OCC, OP>),
                            dim3((unsigned)lb), dim3(kWave), 0, stream, x, y, n_nodes, nbr,

@@ -14,25 +14,45 @@ int weights_fp64_class(const double *x, const double *y, int64_t n_nodes, const 
                        double *sv_lu, double *sv_z, double *sv_s, uint8_t *sv_perm,
                        int32_t sv_kmax, int32_t ok_code, hipStream_t stream);
 int weights_op_k84(const double *x, const double *y, int64_t n_nodes, const int32_t *nbr,
-                   int32_t k_stride, int64_t n_rows, int op, double *w, int32_t *status,
-                   hipStream_t stream);
+                   int32_t k_stride, const int32_t *rows, const int32_t *n_rows_dev,
+                   int64_t n_rows, int op, double *w, int32_t *status, hipStream_t stream);
+int bucket_orders(const int8_t *order, int64_t n_nodes, int32_t k_stride, int32_t *counts,
+                  int32_t *lists, double *w, int32_t *status, hipStream_t s);
 int weights_op_padded(const double *x, const double *y, int64_t n_nodes, const int32_t *nbr,
                       int32_t k_stride, int64_t n_rows, int n, int m, int op, double *w,
                       int32_t *status, hipStream_t stream);
 
 namespace {
 
+// rows, n_rows_dev: null (every node), or a device-counted list of at most
+// n_rows node ids (one block per possible entry).
 template <int OP>
 int op_small(const double *x, const double *y, int64_t n_nodes, const int32_t *nbr,
              int32_t k_stride, int64_t n_rows, int m, double *w, int32_t *status,
-             hipStream_t stream) {
+             hipStream_t stream, const int32_t *rows = nullptr,
+             const int32_t *n_rows_dev = nullptr) {
     const wk::SaveView none;
     if (m == 2)
-        return wk::launch_ms<18, 8, 3, 12, 2, 3, OP>(x, y, n_nodes, nbr, k_stride, nullptr,
-                                                     nullptr, n_rows, 12, 2, w, status, none,
-                                                     RBFFD_OK, stream);
-    return wk::launch_mf<45, 30, 4, 1, 4, OP>(x, y, n_nodes, nbr, k_stride, nullptr, nullptr,
-                                              n_rows, w, status, none, RBFFD_OK, stream);
+        return wk::launch_ms<18, 8, 3, 12, 2, 3, OP>(x, y, n_nodes, nbr, k_stride, rows,
+                                                     n_rows_dev, n_rows, 12, 2, w, status, none,
+                                                     RBFFD_OK, stream, true);
+    return wk::launch_mf<45, 30, 4, 1, 4, OP>(x, y, n_nodes, nbr, k_stride, rows, n_rows_dev,
+                                              n_rows, w, status, none, RBFFD_OK, stream, true);
+}
+
+struct OpBatchWs {
+    int32_t *counts;  // [3]
+    int32_t *lists;   // [3][n_nodes]
+    size_t bytes;
+};
+
+OpBatchWs carve_op_batch(void *base, int64_t n_nodes) {
+    Carver c(base);
+    OpBatchWs b;
+    b.counts = c.take<int32_t>(64);
+    b.lists = c.take<int32_t>((size_t)3 * n_nodes);
+    b.bytes = c.bytes();
+    return b;
 }
 
 }  // namespace
@@ -54,9 +74,48 @@ extern "C" int rbffd_weights_op(const double *x, const double *y, int64_t n_node
     const bool standard = (m == 2 && n == 12) || (m == 4 && n == 30) || (m == 6 && n == 56);
     if (!standard)
         return weights_op_padded(x, y, n_nodes, nbr, k_stride, n_nodes, n, m, op, w, status, s);
-    if (m == 6) return weights_op_k84(x, y, n_nodes, nbr, k_stride, n_nodes, op, w, status, s);
+    if (m == 6)
+        return weights_op_k84(x, y, n_nodes, nbr, k_stride, nullptr, nullptr, n_nodes, op, w,
+                              status, s);
     return op == RBFFD_OP_DX ? op_small<RBFFD_OP_DX>(x, y, n_nodes, nbr, k_stride, n_nodes, m, w,
                                                      status, s)
                              : op_small<RBFFD_OP_DY>(x, y, n_nodes, nbr, k_stride, n_nodes, m, w,
                                                      status, s);
+}
+
+extern "C" int rbffd_weights_op_batch_workspace_size(int64_t n_nodes, size_t *bytes) {
+    if (!bytes || n_nodes < 1 || n_nodes >= INT32_MAX) return RBFFD_ERR_ARG;
+    *bytes = carve_op_batch(nullptr, n_nodes).bytes;
+    return RBFFD_SUCCESS;
+}
+
+extern "C" int rbffd_weights_op_batch(const double *x, const double *y, int64_t n_nodes,
+                                      const int32_t *nbr, int32_t k_stride, const int8_t *order,
+                                      int32_t op, double *w, int32_t *status, void *workspace,
+                                      size_t workspace_bytes, void *stream) {
+    if (!x || !y || !nbr || !order || !w || n_nodes < 1 || n_nodes >= INT32_MAX ||
+        k_stride < 56 || (op != RBFFD_OP_DX && op != RBFFD_OP_DY))
+        return RBFFD_ERR_ARG;
+    OpBatchWs b = carve_op_batch(nullptr, n_nodes);
+    if (!workspace || workspace_bytes < b.bytes) return RBFFD_ERR_WORKSPACE;
+    b = carve_op_batch(workspace, n_nodes);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int rc = fill_i32(b.counts, 0, 64, s);
+    if (rc) return rc;
+    if ((rc = bucket_orders(order, n_nodes, k_stride, b.counts, b.lists, w, status, s))) return rc;
+    // the largest systems first
+    rc = weights_op_k84(x, y, n_nodes, nbr, k_stride, b.lists + 2 * n_nodes, b.counts + 2,
+                        n_nodes, op, w, status, s);
+    if (rc) return rc;
+    for (int q = 1; q >= 0; --q) {
+        const int m = 2 * q + 2;
+        const int32_t *rows = b.lists + (int64_t)q * n_nodes;
+        rc = op == RBFFD_OP_DX
+                 ? op_small<RBFFD_OP_DX>(x, y, n_nodes, nbr, k_stride, n_nodes, m, w, status, s,
+                                         rows, b.counts + q)
+                 : op_small<RBFFD_OP_DY>(x, y, n_nodes, nbr, k_stride, n_nodes, m, w, status, s,
+                                         rows, b.counts + q);
+        if (rc) return rc;
+    }
+    return RBFFD_SUCCESS;
 }

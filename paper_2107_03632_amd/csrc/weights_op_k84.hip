@@ -3,16 +3,18 @@
 #include "weights_mf.h"
 
 namespace rbffd {
+// rows, n_rows_dev: null (every node), or a device-counted list of at most
+// n_rows node ids (one block per possible entry).
 int weights_op_k84(const double *x, const double *y, int64_t n_nodes, const int32_t *nbr,
-                   int32_t k_stride, int64_t n_rows, int op, double *w, int32_t *status,
-                   hipStream_t stream) {
+                   int32_t k_stride, const int32_t *rows, const int32_t *n_rows_dev,
+                   int64_t n_rows, int op, double *w, int32_t *status, hipStream_t stream) {
     const wk::SaveView none;
     if (op == RBFFD_OP_DX)
-        return wk::launch_mf<84, 56, 6, 2, 2, RBFFD_OP_DX>(x, y, n_nodes, nbr, k_stride, nullptr,
-                                                           nullptr, n_rows, w, status, none,
-                                                           RBFFD_OK, stream);
-    return wk::launch_mf<84, 56, 6, 2, 2, RBFFD_OP_DY>(x, y, n_nodes, nbr, k_stride, nullptr,
-                                                       nullptr, n_rows, w, status, none,
-                                                       RBFFD_OK, stream);
+        return wk::launch_mf<84, 56, 6, 2, 2, RBFFD_OP_DX>(x, y, n_nodes, nbr, k_stride, rows,
+                                                           n_rows_dev, n_rows, w, status, none,
+                                                           RBFFD_OK, stream, true);
+    return wk::launch_mf<84, 56, 6, 2, 2, RBFFD_OP_DY>(x, y, n_nodes, nbr, k_stride, rows,
+                                                       n_rows_dev, n_rows, w, status, none,
+                                                       RBFFD_OK, stream, true);
 }
 }  // namespace rbffd

@@ -31,7 +31,8 @@ def test_header_declares_the_boundary():
     for fn in ["rbffd_knn", "rbffd_weights", "rbffd_weights_backward", "rbffd_assemble_csr",
                "rbffd_spmv", "rbffd_time_steps", "rbffd_solve", "rbffd_weights_op",
                "rbffd_knn3_workspace_size", "rbffd_knn3", "rbffd_weights3", "rbffd_weights3_op",
-               "rbffd_weights3_batch_workspace_size", "rbffd_weights3_batch"]:
+               "rbffd_weights3_batch_workspace_size", "rbffd_weights3_batch",
+               "rbffd_weights_op_batch_workspace_size", "rbffd_weights_op_batch"]:
         assert fn in names
 
 
@@ -105,6 +106,10 @@ def test_argument_errors_before_any_launch(lib):
     assert lib.rbffd_weights3_batch_workspace_size(1000, ctypes.byref(sz3)) == 0
     assert sz3.value >= 2 * 1000 * 4
     assert lib.rbffd_weights3_batch_workspace_size(0, ctypes.byref(sz3)) == -1
+    lib.rbffd_weights_op_batch.argtypes = [P, P, ctypes.c_int64, P, ctypes.c_int32, P,
+                                           ctypes.c_int32, P, P, P, ctypes.c_size_t, P]
+    assert lib.rbffd_weights_op_batch(None, None, 10, None, 56, None, 1, None, None, None, 0,
+                                      None) == -1
     sz = ctypes.c_size_t(0)
     lib.rbffd_solve_workspace_size.argtypes = [ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]
     assert lib.rbffd_solve_workspace_size(1000, ctypes.byref(sz)) == 0

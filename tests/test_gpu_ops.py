@@ -185,3 +185,72 @@ def test_op_padded_supports(m, n):
             assert rel.max() <= 1e-11
             assert np.all(np.isnan(w[~ok][:, :n]))
             assert np.all(w[:, n:] == 0.0)
+
+
+# ---- mixed-order batch of the derivative operators (rbffd_weights_op_batch)
+
+def _op_batch_ref(x, y, nbr, order, oop):
+    """The oracle's weights at each node's order on the standard supports;
+    NaN weights and BAD_ORDER where the order is not 2, 4 or 6."""
+    N, ks = nbr.shape
+    w = np.full((N, ks), np.nan)
+    st = np.full(N, rb.BAD_ORDER, np.int32)
+    for m, n in ((2, 12), (4, 30), (6, 56)):
+        rows = np.nonzero(order == m)[0]
+        if rows.size:
+            w[rows], st[rows] = oracle.weights_op(x, y, nbr, m, n, oop, rows=rows)
+    return w, st
+
+
+@pytest.mark.parametrize("op,oop,name", OPS)
+@pytest.mark.parametrize("mix", ["mixed", "bad"])
+def test_op_batch_bit_exact(op, oop, name, mix):
+    """Per-node orders on a 3200-node disk with a stride of 60 columns:
+    every node's weights and status are the oracle's at its order."""
+    ns = nodes.unit_disk(3000, 200, seed=36)
+    nbr = oracle.knn(ns.x, ns.y, 60)
+    rng = np.random.default_rng(37)
+    vals = [2, 4, 6] if mix == "mixed" else [2, 4, 6, 3, 0, 8]
+    order = rng.choice(np.array(vals, np.int8), ns.n_nodes)
+    say(name, "batch", mix, ns.n_nodes)
+    w_ref, st_ref = _op_batch_ref(ns.x, ns.y, nbr, order, oop)
+    w, st = rb.rbffd_weights_op_batch(dev(ns.x), dev(ns.y), dev(nbr), dev(order), op)
+    w, st = host(w), host(st)
+    assert np.array_equal(st, st_ref)
+    assert np.array_equal(w, w_ref, equal_nan=True)
+
+
+def test_op_batch_full_size_matches_single_order():
+    """The 1M-node square with orders uniform on {2, 4, 6}: the batch's d/dx
+    weights are the single-order launches' at each node's order, bit for
+    bit, on every row."""
+    ns = nodes.workload("square_1m_mixed")
+    X, Y = dev(ns.x), dev(ns.y)
+    NB = rb.rbffd_knn(X, Y, 56)
+    say("d/dx batch square", ns.n_nodes)
+    w_b, st_b = rb.rbffd_weights_op_batch(X, Y, NB, dev(ns.order), rb.OP_DX)
+    assert int((st_b != 0).sum().item()) == 0
+    for m, n in ((2, 12), (4, 30), (6, 56)):
+        sel = torch.as_tensor(ns.order == m).cuda()
+        w_s, _ = rb.rbffd_weights_op(X, Y, NB[:, :n].contiguous(), m, n, rb.OP_DX)
+        assert torch.equal(w_b[sel][:, :n], w_s[sel]), m
+        assert torch.all(w_b[sel][:, n:] == 0.0)
+        del w_s
+
+
+def test_op_batch_argument_errors():
+    ns = nodes.unit_disk(300, 40, seed=38)
+    nbr = oracle.knn(ns.x, ns.y, 56)
+    X, Y = dev(ns.x), dev(ns.y)
+    order = dev(np.full(ns.n_nodes, 4, np.int8))
+    with pytest.raises(ValueError):  # fewer than 56 columns
+        rb.rbffd_weights_op_batch(X, Y, dev(nbr[:, :40]), order, rb.OP_DX)
+    with pytest.raises(rb.RbffdError):  # the Laplacian batch is rbffd_weights
+        rb.rbffd_weights_op_batch(X, Y, dev(nbr), order, rb.OP_LAPLACIAN)
+    lib = rb._load()
+    NB = dev(nbr)
+    w = torch.empty((ns.n_nodes, 56), dtype=torch.float64, device="cuda")
+    ws = torch.empty(16, dtype=torch.uint8, device="cuda")
+    rc = lib.rbffd_weights_op_batch(rb._p(X), rb._p(Y), ns.n_nodes, rb._p(NB), 56, rb._p(order),
+                                    rb.OP_DX, rb._p(w), None, rb._p(ws), 16, rb._stream(X.device))
+    assert rc == -2  # RBFFD_ERR_WORKSPACE
