@@ -74,6 +74,8 @@ def _load():
                                                  P, I64, P, P, P]
             lib.oracle_weights_mixed_form.argtypes = [I64, P, P, P, I32, P, I32, I32, P,
                                                       P, I64, P, P, P, I32]
+            lib.oracle_weights_mixed_op.argtypes = [I64, P, P, P, I32, P, I32, I32, P,
+                                                    P, I64, P, P, P, I32, I32]
             lib.oracle_gj32.argtypes = [ctypes.c_int, P, P]
             lib.oracle_adjoint.argtypes = [I64, P, P, P, I32, P, I32, I32, P,
                                            P, P, P]
@@ -313,12 +315,13 @@ MIXED_LU, MIXED_GJ = 0, 1
 
 def weights_mixed(x, y, nbr, m: int | None = None, n: int | None = None, order=None,
                   n_for_m=(12, 30, 56), rows=None, k_stride: int | None = None,
-                  form: int = MIXED_LU):
+                  form: int = MIXED_LU, op: int = LAPLACIAN):
     """Mixed-precision weights: FP32 factorisation of the FP64-assembled
     system + FP64 refinement, FP64 fallback.  form MIXED_LU: LU factors and
     triangular solves; MIXED_GJ: the Gauss-Jordan inverse applied as a
-    product.  Returns (w, status, corrections); for a stencil that fell back,
-    the corrections tried before it did."""
+    product.  op: LAPLACIAN, D_DX or D_DY (the right-hand side and scale of
+    weights_op).  Returns (w, status, corrections); for a stencil that fell
+    back, the corrections tried before it did."""
     lib = _load()
     x, y, nbr = _f64(x), _f64(y), _i32(nbr)
     _check_supports(x, y, nbr, k_stride)
@@ -330,10 +333,10 @@ def weights_mixed(x, y, nbr, m: int | None = None, n: int | None = None, order=N
     w = np.empty((nr, ks))
     st = np.empty(nr, dtype=np.int32)
     it = np.empty(nr, dtype=np.int32)
-    rc = lib.oracle_weights_mixed_form(N, _p(x), _p(y), _p(nbr), ks, _p(o),
-                                       -1 if m is None else m, -1 if n is None else n,
-                                       _p(_i32(n_for_m)), _p(r), nr, _p(w), _p(st), _p(it),
-                                       int(form))
+    rc = lib.oracle_weights_mixed_op(N, _p(x), _p(y), _p(nbr), ks, _p(o),
+                                     -1 if m is None else m, -1 if n is None else n,
+                                     _p(_i32(n_for_m)), _p(r), nr, _p(w), _p(st), _p(it),
+                                     int(form), int(op))
     if rc != 0:
         raise ValueError(f"oracle_weights_mixed: error {rc}")
     return w, st, it

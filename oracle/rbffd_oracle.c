@@ -47,6 +47,9 @@
  *                     given as LU factors (form 0, as oracle_weights_mixed) or
  *                     as that Gauss-Jordan inverse, applied to each
  *                     right-hand side as a product (form 1).
+ *   oracle_weights_mixed_op  the same for the operator of oracle_assemble_op
+ *                     (the right-hand side and the scale's power change; the
+ *                     refinement and the fallback rule do not).
  *   oracle_csr        the discrete operator of eq. (1) as a CSR matrix, with the
  *                     Dirichlet rows of section IV replaced by identity rows.
  *   oracle_spmv       y = W u - f, a sequential row sum in CSR order.
@@ -627,18 +630,20 @@ static void gj32_apply(int K, const float *S, const int32_t *perm, float *b, flo
 #define MIXED_MAX_CORRECTIONS 10
 #define MIXED_TOL 1e-12
 
-/* One stencil, mixed precision.  Returns the status; *iters = number of
- * corrections applied, or tried before the stencil fell back (0 when the
- * assembly or the FP32 factorisation failed). */
+/* One stencil, mixed precision, for the operator op of oracle_assemble_op
+ * (the system is the same for every operator; only the right-hand side
+ * differs).  Returns the status; *iters = number of corrections applied,
+ * or tried before the stencil fell back (0 when the assembly or the FP32
+ * factorisation failed). */
 static int stencil_solve_mixed(int64_t n_nodes, const double *x, const double *y,
-                               int64_t i, const int32_t *idx, int n, int m,
+                               int64_t i, const int32_t *idx, int n, int m, int op,
                                double *M, double *z, float *M32, float *d32,
                                int32_t *perm, float *dinv32, double *dinv, double *rhs,
                                double *s, int *iters, int form)
 {
     const int K = n + n_monomials(m);
     *iters = 0;
-    int st = oracle_assemble(n_nodes, x, y, i, idx, n, m, M, rhs, s);
+    int st = oracle_assemble_op(n_nodes, x, y, i, idx, n, m, op, M, rhs, s);
     if (st != OR_OK)
         return st;
     for (int e = 0; e < K * K; ++e)
@@ -700,20 +705,21 @@ static int stencil_solve_mixed(int64_t n_nodes, const double *x, const double *y
     if (ok)
         return OR_OK;
     /* FP64 path from scratch; *iters keeps the corrections tried */
-    st = stencil_solve(n_nodes, x, y, i, idx, n, m, 0, M, z, perm, dinv, s);
+    st = stencil_solve(n_nodes, x, y, i, idx, n, m, op, M, z, perm, dinv, s);
     return st == OR_OK ? OR_FELL_BACK : st;
 }
 
-/* As oracle_weights, mixed precision.  iters (may be NULL) receives the
+/* As oracle_weights_op, mixed precision.  iters (may be NULL) receives the
  * number of FP64 refinement corrections per listed node.  form: 0 solves
  * with FP32 LU factors, 1 applies the FP32 Gauss-Jordan inverse. */
-int oracle_weights_mixed_form(int64_t n_nodes, const double *x, const double *y,
-                              const int32_t *nbr, int32_t k_stride,
-                              const int8_t *order, int32_t m_uniform, int32_t n_uniform,
-                              const int32_t *n_for_m, const int64_t *rows, int64_t n_rows,
-                              double *w, int32_t *status, int32_t *iters, int32_t form)
+int oracle_weights_mixed_op(int64_t n_nodes, const double *x, const double *y,
+                            const int32_t *nbr, int32_t k_stride,
+                            const int8_t *order, int32_t m_uniform, int32_t n_uniform,
+                            const int32_t *n_for_m, const int64_t *rows, int64_t n_rows,
+                            double *w, int32_t *status, int32_t *iters, int32_t form,
+                            int32_t op)
 {
-    if (form != 0 && form != 1)
+    if ((form != 0 && form != 1) || op < 0 || op > 2)
         return OR_EARG;
     int kmax = 0;
     if (order) {
@@ -752,11 +758,11 @@ int oracle_weights_mixed_form(int64_t n_nodes, const double *x, const double *y,
             break;
         }
         double s = 0.0;
-        int st = stencil_solve_mixed(n_nodes, x, y, i, nbr + i * (int64_t)k_stride, n, m,
+        int st = stencil_solve_mixed(n_nodes, x, y, i, nbr + i * (int64_t)k_stride, n, m, op,
                                      M, z, M32, d32, perm, dinv32, dinv, rhs, &s, &it, form);
         double *wr = w + t * (int64_t)k_stride;
         if (st == OR_OK || st == OR_FELL_BACK) {
-            double s2 = s * s;
+            double s2 = op == 0 ? s * s : s;
             for (int k = 0; k < n; ++k)
                 wr[k] = z[k] / s2;
         } else {
@@ -772,6 +778,17 @@ int oracle_weights_mixed_form(int64_t n_nodes, const double *x, const double *y,
     }
     free(M); free(M32); free(z); free(d32); free(perm);
     return rc;
+}
+
+/* The Laplacian (op 0). */
+int oracle_weights_mixed_form(int64_t n_nodes, const double *x, const double *y,
+                              const int32_t *nbr, int32_t k_stride,
+                              const int8_t *order, int32_t m_uniform, int32_t n_uniform,
+                              const int32_t *n_for_m, const int64_t *rows, int64_t n_rows,
+                              double *w, int32_t *status, int32_t *iters, int32_t form)
+{
+    return oracle_weights_mixed_op(n_nodes, x, y, nbr, k_stride, order, m_uniform, n_uniform,
+                                   n_for_m, rows, n_rows, w, status, iters, form, 0);
 }
 
 int oracle_weights_mixed(int64_t n_nodes, const double *x, const double *y,

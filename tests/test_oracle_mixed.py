@@ -266,3 +266,45 @@ def test_mixed_gj_fallback_rule_and_cap(i, k, lo, hi, tries):
     assert stm[0] == oracle.FELL_BACK
     assert it[0] == tries
     assert np.array_equal(wm, w64)
+
+
+@pytest.mark.parametrize("form", [oracle.MIXED_LU, oracle.MIXED_GJ])
+@pytest.mark.parametrize("m", [2, 4, 6])
+@pytest.mark.parametrize("op", [oracle.D_DX, oracle.D_DY])
+def test_mixed_derivative_weights(op, m, form):
+    """The mixed form of the derivative operators: the same refinement and
+    fallback rule on the operator's right-hand side.  The refined weights
+    agree with the FP64 derivative weights to the 1e-9 target, a stencil
+    that fell back carries exactly the FP64 weights, and the weights
+    differentiate every monomial of degree <= m exactly at the centre (the
+    polynomial part of eq. (1) with L = d/dx or d/dy)."""
+    ns = nodes.unit_disk(1500, 140, seed=34)
+    n = NFM[m]
+    nbr = oracle.knn(ns.x, ns.y, n)
+    w64, st64 = oracle.weights_op(ns.x, ns.y, nbr, m, n, op)
+    wm, stm, it = oracle.weights_mixed(ns.x, ns.y, nbr, m=m, n=n, form=form, op=op)
+    assert np.all(st64 == 0)
+    assert np.all((stm == 0) | (stm == oracle.FELL_BACK))
+    e = np.abs(wm - w64).max(axis=1) / np.abs(w64).max(axis=1)
+    assert e.max() <= 1e-9
+    assert np.all(it[stm == 0] >= 1) and np.all(it <= 10)
+    fb = stm == oracle.FELL_BACK
+    assert np.array_equal(wm[fb], w64[fb])
+    dx = ns.x[nbr] - ns.x[:, None]
+    dy = ns.y[nbr] - ns.y[:, None]
+    for a in range(m + 1):
+        for b in range(m + 1 - a):
+            p = dx ** a * dy ** b
+            want = 1.0 if (a, b) == ((1, 0) if op == oracle.D_DX else (0, 1)) else 0.0
+            got = (wm * p).sum(axis=1)
+            scale = np.abs(wm * p).sum(axis=1) + want
+            assert np.max(np.abs(got - want) / scale) < 1e-9, (a, b)
+
+
+def test_mixed_laplacian_through_the_operator_entry():
+    ns = nodes.unit_disk(800, 100, seed=35)
+    nbr = oracle.knn(ns.x, ns.y, 30)
+    a = oracle.weights_mixed(ns.x, ns.y, nbr, m=4, n=30)
+    b = oracle.weights_mixed(ns.x, ns.y, nbr, m=4, n=30, op=oracle.LAPLACIAN)
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v)
