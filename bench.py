@@ -585,7 +585,8 @@ def extras_ops(torch, rb, stream, X, Y, ns, m, n):
     """First-derivative weights (rbffd_weights_op, d/dx and d/dy) on the bench
     disk: time per launch, the fraction of the FP64 peak on the Laplacian's
     flop count (the same factorisation and solves), and the largest error of
-    the differentiated u = sin(pi x) sin(pi y) over all nodes."""
+    the differentiated u = sin(pi x) sin(pi y) over all nodes; the mixed
+    precision form beside each, and d/dx at m = 6 in both precisions."""
     nbr = rb.rbffd_knn(X, Y, n)
     N = ns.n_nodes
     u = torch.sin(math.pi * X) * torch.sin(math.pi * Y)
@@ -601,6 +602,19 @@ def extras_ops(torch, rb, stream, X, Y, ns, m, n):
                      / FP64_PEAK_TFLOPS,
                      "failed": int((st != 0).sum().item()),
                      "max_abs_err": (approx - exact[op]).abs().max().item()}
+        # the same operator in mixed precision (FP32 factorisation + FP64
+        # refinement), against the FP64 weights of this call
+        ms_mx = timed(torch, stream, lambda: rb.rbffd_weights_op_mixed(X, Y, nbr, m, n, op))
+        wmx, stmx = rb.rbffd_weights_op_mixed(X, Y, nbr, m, n, op)
+        err = ((wmx - w).abs().amax(1) / w.abs().amax(1)).max().item()
+        res[name]["mixed"] = {"ms": ms_mx, "speedup_vs_fp64": ms / ms_mx,
+                              "fell_back": int((stmx == rb.FELL_BACK_FP64).sum().item()),
+                              "max_rel_err_vs_fp64": err}
+    # m = 6 (K = 84) d/dx, FP64 and mixed, on the same disk
+    nb56 = rb.rbffd_knn(X, Y, 56)
+    ms64 = timed(torch, stream, lambda: rb.rbffd_weights_op(X, Y, nb56, 6, 56, rb.OP_DX))
+    msmx = timed(torch, stream, lambda: rb.rbffd_weights_op_mixed(X, Y, nb56, 6, 56, rb.OP_DX))
+    res["d_dx_m6"] = {"fp64_ms": ms64, "mixed_ms": msmx, "speedup_vs_fp64": ms64 / msmx}
     return res
 
 

@@ -207,6 +207,21 @@ int rbffd_weights_op_batch(const double *x, const double *y, int64_t n_nodes,
                            const int32_t *nbr, int32_t k_stride, const int8_t *order,
                            int32_t op, double *w, int32_t *status, void *workspace,
                            size_t workspace_bytes, void *stream);
+/* rbffd_weights_op_mixed: the d/dx or d/dy weights of rbffd_weights_op in
+ * the mixed-precision form of rbffd_weights (section V: FP32 factorisation
+ * of the FP64-assembled system, FP64 iterative refinement of the
+ * operator's right-hand side, the same stopping and fallback rules; a
+ * stencil that cannot be refined is solved in FP64 with status
+ * RBFFD_FELL_BACK_FP64), on the standard supports (m, n) = (2, 12),
+ * (4, 30), (6, 56) (RBFFD_ERR_UNSUPPORTED otherwise).  refine_steps
+ * [n_nodes] int32 or NULL receives the corrections per stencil.
+ * workspace: rbffd_weights_op_mixed_workspace_size bytes (device).  No
+ * host synchronisation. */
+int rbffd_weights_op_mixed_workspace_size(int64_t n_nodes, int32_t m, size_t *bytes /* host */);
+int rbffd_weights_op_mixed(const double *x, const double *y, int64_t n_nodes,
+                           const int32_t *nbr, int32_t k_stride, int32_t m, int32_t n,
+                           int32_t op, double *w, int32_t *status, int32_t *refine_steps,
+                           void *workspace, size_t workspace_bytes, void *stream);
 
 /* ==========================================================================
  * Three-dimensional nodes (eq. (1) and eq. (2) hold for any dimension d; the

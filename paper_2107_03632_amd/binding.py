@@ -64,6 +64,9 @@ def _load():
             "rbffd_weights_op": ([P, P, I64, P, I32, I32, I32, I32, P, P, P], ctypes.c_int),
             "rbffd_weights_op_batch_workspace_size": ([I64, PSZ], ctypes.c_int),
             "rbffd_weights_op_batch": ([P, P, I64, P, I32, P, I32, P, P, P, SZ, P], ctypes.c_int),
+            "rbffd_weights_op_mixed_workspace_size": ([I64, I32, PSZ], ctypes.c_int),
+            "rbffd_weights_op_mixed": ([P, P, I64, P, I32, I32, I32, I32, P, P, P, P, SZ, P],
+                                       ctypes.c_int),
             "rbffd_knn3_workspace_size": ([I64, I32, PSZ], ctypes.c_int),
             "rbffd_knn3": ([P, P, P, I64, I32, P, P, ctypes.c_size_t, P], ctypes.c_int),
             "rbffd_weights3": ([P, P, P, I64, P, I32, I32, I32, P, P, P], ctypes.c_int),
@@ -332,6 +335,25 @@ def rbffd_weights3(x, y, z, nbr, m: int = 2, n: int = 20, out=None, status=None,
         _check(lib.rbffd_weights3_op(_p(x), _p(y), _p(z), N, _p(nbr), ks, int(m), int(n),
                                      int(op), _p(w), _p(st), _stream(x.device)),
                "rbffd_weights3_op")
+    return w, st
+
+
+def rbffd_weights_op_mixed(x, y, nbr, m: int, n: int, op: int, out=None, status=None,
+                           refine_steps=None):
+    """d/dx (OP_DX) or d/dy (OP_DY) weights in mixed precision (FP32
+    factorisation + FP64 refinement, FP64 fallback) on the standard
+    supports.  refine_steps: an int32 [N] device tensor that receives the
+    corrections per stencil.  Returns (w [N, k_stride], status [N])."""
+    lib = _load()
+    x, y, nbr, N, ks = _nodes2(x, y, nbr)
+    w = _out(out, (N, ks), torch.float64, "out", x.device)
+    st = _out(status, (N,), torch.int32, "status", x.device)
+    it = None if refine_steps is None else _out(refine_steps, (N,), torch.int32,
+                                                 "refine_steps", x.device)
+    ws = _workspace(_size(lib.rbffd_weights_op_mixed_workspace_size, N, int(m)), x.device)
+    _check(lib.rbffd_weights_op_mixed(_p(x), _p(y), N, _p(nbr), ks, int(m), int(n), int(op),
+                                      _p(w), _p(st), _p(it), _p(ws), ws.numel(),
+                                      _stream(x.device)), "rbffd_weights_op_mixed")
     return w, st
 
 

@@ -34,6 +34,8 @@ FLAGS = [
 EXTRA_FLAGS = {
     "weights_mx_k45.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
     "weights_mx_k84.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+    "weights_mx_op_k45.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+    "weights_mx_op_k84.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
 }
 
 

@@ -116,7 +116,9 @@ struct GjLds {
 // One wavefront computes stencil i.  AREG: keep the FP64 entries of the
 // tiles that hold A entries in registers for the residual (else they are
 // recomputed from the FP64 offsets at every correction).
-template <int KP, int NFIX, int MFIX, bool AREG, int UNR, int RCP>
+// OP: 0 the Laplacian, 1 d/dx, 2 d/dy (the right-hand side of the operator
+// and the power of the scale in the weights).
+template <int KP, int NFIX, int MFIX, bool AREG, int UNR, int RCP, int OP = 0>
 __device__ __forceinline__ void weights_gj_wave(
     const double *__restrict__ x, const double *__restrict__ y, int64_t n_nodes,
     const int32_t *__restrict__ nbr, int32_t k_stride, int64_t i, double *__restrict__ w,
@@ -502,9 +504,10 @@ __device__ __forceinline__ void weights_gj_wave(
         double v = 0.0;
         if (kWave * s < n && R < n) {
             const double ux = s_ux[R], uy = s_uy[R];
-            v = 9.0 * sqrt(ux * ux + uy * uy);
+            const double r0 = ux * ux + uy * uy;
+            v = OP == 0 ? 9.0 * sqrt(r0) : -3.0 * sqrt(r0) * (OP == 1 ? ux : uy);
         } else if (R >= n && R < K) {
-            v = (R - n == 3 || R - n == 5) ? 2.0 : 0.0;
+            v = OP == 0 ? ((R - n == 3 || R - n == 5) ? 2.0 : 0.0) : (R - n == OP ? 1.0 : 0.0);
         }
         rhs_s[s] = v;
     }
@@ -683,7 +686,7 @@ __device__ __forceinline__ void weights_gj_wave(
             if (iters) iters[i] = 0;
         }
     } else if (state == 1) {
-        const double s2 = sc * sc;
+        const double s2 = OP == 0 ? sc * sc : sc;  // the operator's power of the scale
 #pragma unroll
         for (int s = 0; s < SL; ++s)
             if (lane + kWave * s < n) wi[lane + kWave * s] = z[s] / s2;
@@ -698,7 +701,7 @@ __device__ __forceinline__ void weights_gj_wave(
     }
 }
 
-template <int KP, int NFIX, int MFIX, bool AREG, int OCC, int UNR, int RCP>
+template <int KP, int NFIX, int MFIX, bool AREG, int OCC, int UNR, int RCP, int OP = 0>
 __global__ __launch_bounds__(kWave)
 __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1))) void weights_gj_kernel(
     const double *__restrict__ x, const double *__restrict__ y, int64_t n_nodes,
@@ -711,13 +714,14 @@ __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1))) void weights_gj_kernel(
     const int64_t t = blockIdx.x;
     if (t >= n_rows) return;
     const int64_t i = rows ? (int64_t)rows[t] : t;
-    weights_gj_wave<KP, NFIX, MFIX, AREG, UNR, RCP>(x, y, n_nodes, nbr, k_stride, i, w, status,
-                                               iters, fb_count, fb_list, lds);
+    weights_gj_wave<KP, NFIX, MFIX, AREG, UNR, RCP, OP>(x, y, n_nodes, nbr, k_stride, i, w,
+                                                   status, iters, fb_count, fb_list, lds);
 }
 
 // One block (one wavefront) per listed stencil; no scratch memory.
 // UNR: 4 unrolls the panel loop fully, 1 keeps it rolled within a tile column.
-template <int KP, int NFIX, int MFIX, bool AREG, int OCC = 0, int UNR = 1, int RCP = 0>
+template <int KP, int NFIX, int MFIX, bool AREG, int OCC = 0, int UNR = 1, int RCP = 0,
+          int OP = 0>
 struct GjLaunch {
     static size_t scratch_bytes(int64_t) { return 0; }
     static int run(const double *x, const double *y, int64_t n_nodes, const int32_t *nbr,
@@ -726,7 +730,7 @@ struct GjLaunch {
                    int32_t *fb_count, int32_t *fb_list, hipStream_t stream) {
         if (n_rows <= 0) return RBFFD_SUCCESS;
         if (n_rows > 0x7fffffff) return RBFFD_ERR_UNSUPPORTED;
-        hipLaunchKernelGGL((weights_gj_kernel<KP, NFIX, MFIX, AREG, OCC, UNR, RCP>),
+        hipLaunchKernelGGL((weights_gj_kernel<KP, NFIX, MFIX, AREG, OCC, UNR, RCP, OP>),
                            dim3((unsigned)n_rows),
                            dim3(kWave), 0, stream, x, y, n_nodes, nbr, k_stride, rows, n_rows_dev,
                            n_rows, w, status, iters, fb_count, fb_list);

@@ -35,7 +35,8 @@ __device__ __forceinline__ float seg_all_or_f(float v, int lane) {
     return __uint_as_float(seg_all<SEG, OpOr>(__float_as_uint(v), lane));
 }
 
-template <int KP, int SEG, int SL, int NFIX, int MFIX, int OCC>
+// OP: 0 the Laplacian, 1 d/dx, 2 d/dy (right-hand side and scale power).
+template <int KP, int SEG, int SL, int NFIX, int MFIX, int OCC, int OP = 0>
 __global__ __launch_bounds__(kWave)
 __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1))) void weights_mx_kernel(
     const double *__restrict__ x, const double *__restrict__ y, int64_t n_nodes,
@@ -160,8 +161,10 @@ __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1))) void weights_mx_kernel(
                 if ((l & 1) == 1) __builtin_amdgcn_sched_barrier(0);
             }
             const double r0 = ux[s] * ux[s] + uy[s] * uy[s];
-            const double rb = 9.0 * sqrt(r0);
-            rhs[s] = prow ? rb : ((qrow && (jr == 3 || jr == 5)) ? 2.0 : 0.0);
+            const double rb =
+                OP == 0 ? 9.0 * sqrt(r0) : -3.0 * sqrt(r0) * (OP == 1 ? ux[s] : uy[s]);
+            const bool rq = OP == 0 ? (jr == 3 || jr == 5) : jr == OP;
+            rhs[s] = prow ? rb : ((qrow && rq) ? (OP == 0 ? 2.0 : 1.0) : 0.0);
             yf[s] = (float)rhs[s];
         }
         asm volatile("" : "+v"(flags));
@@ -375,7 +378,7 @@ __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1))) void weights_mx_kernel(
                 }
             } else if (state == 1) {
                 double *wi = w + i * (int64_t)k_stride;
-                const double s2 = sc * sc;
+                const double s2 = OP == 0 ? sc * sc : sc;  // the operator's scale power
 #pragma unroll
                 for (int s = 0; s < SL; ++s)
                     if (pos[s] < n) wi[pos[s]] = z[s] / s2;
@@ -393,7 +396,7 @@ __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1))) void weights_mx_kernel(
     }
 }
 
-template <int KP, int SEG, int SL, int NFIX, int MFIX, int OCC = 0>
+template <int KP, int SEG, int SL, int NFIX, int MFIX, int OCC = 0, int OP = 0>
 struct MixedLaunch {
     static constexpr int GPB = kWave / SEG;
     // blocks of the grid-stride launch: bounded so the scratch stays modest
@@ -409,7 +412,7 @@ struct MixedLaunch {
                    int64_t n_rows, double *w, int32_t *status, int32_t *iters, double *scratch,
                    int32_t *fb_count, int32_t *fb_list, hipStream_t stream) {
         if (n_rows <= 0) return RBFFD_SUCCESS;
-        hipLaunchKernelGGL((weights_mx_kernel<KP, SEG, SL, NFIX, MFIX, OCC>),
+        hipLaunchKernelGGL((weights_mx_kernel<KP, SEG, SL, NFIX, MFIX, OCC, OP>),
                            dim3((unsigned)blocks(n_rows)), dim3(kWave), 0, stream, x, y, n_nodes,
                            nbr, k_stride, rows, n_rows_dev, n_rows, w, status, iters, scratch,
                            fb_count, fb_list);

@@ -32,7 +32,8 @@ def test_header_declares_the_boundary():
                "rbffd_spmv", "rbffd_time_steps", "rbffd_solve", "rbffd_weights_op",
                "rbffd_knn3_workspace_size", "rbffd_knn3", "rbffd_weights3", "rbffd_weights3_op",
                "rbffd_weights3_batch_workspace_size", "rbffd_weights3_batch",
-               "rbffd_weights_op_batch_workspace_size", "rbffd_weights_op_batch"]:
+               "rbffd_weights_op_batch_workspace_size", "rbffd_weights_op_batch",
+               "rbffd_weights_op_mixed_workspace_size", "rbffd_weights_op_mixed"]:
         assert fn in names
 
 
@@ -110,6 +111,11 @@ def test_argument_errors_before_any_launch(lib):
                                            ctypes.c_int32, P, P, P, ctypes.c_size_t, P]
     assert lib.rbffd_weights_op_batch(None, None, 10, None, 56, None, 1, None, None, None, 0,
                                       None) == -1
+    lib.rbffd_weights_op_mixed.argtypes = [P, P, ctypes.c_int64, P, ctypes.c_int32,
+                                           ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P,
+                                           P, P, ctypes.c_size_t, P]
+    assert lib.rbffd_weights_op_mixed(None, None, 10, None, 30, 4, 30, 1, None, None, None,
+                                      None, 0, None) == -1
     sz = ctypes.c_size_t(0)
     lib.rbffd_solve_workspace_size.argtypes = [ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]
     assert lib.rbffd_solve_workspace_size(1000, ctypes.byref(sz)) == 0

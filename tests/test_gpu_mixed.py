@@ -236,3 +236,49 @@ def test_mixed_blocked_fallback_and_failures(m):
     assert st_mx[i] == oracle.FELL_BACK
     check_mixed(w, st, it, w_mx, st_mx, it_mx, w64, n, exact=False, what=f"fallback m={m}")
     assert np.array_equal(w[i, :n], w64[i, :n])  # the FP64 kernel's weights, bit for bit
+
+
+@pytest.mark.parametrize("op,oop", [(rb.OP_DX, oracle.D_DX), (rb.OP_DY, oracle.D_DY)],
+                         ids=["dx", "dy"])
+@pytest.mark.parametrize("m", [2, 4, 6])
+def test_mixed_derivatives(m, op, oop):
+    """The derivative operators in mixed precision (rbffd_weights_op_mixed)
+    against the oracle's mixed form of the same operator and its FP64
+    derivative weights, as the Laplacian above."""
+    ns = nodes.unit_disk(3000, 200, seed=22)
+    n = NFM[m]
+    nbr = oracle.knn(ns.x, ns.y, n)
+    w_mx, st_mx, it_mx = oracle.weights_mixed(ns.x, ns.y, nbr, m=m, n=n, form=FORM[m], op=oop)
+    w64, _ = oracle.weights_op(ns.x, ns.y, nbr, m, n, oop)
+    it = torch.zeros(ns.n_nodes, dtype=torch.int32, device="cuda")
+    w, st = rb.rbffd_weights_op_mixed(dev(ns.x), dev(ns.y), dev(nbr), m, n, op, refine_steps=it)
+    w, st, it = host(w), host(st), host(it)
+    say("mixed derivative", m, op, "statuses", np.bincount(st), "mean corrections",
+        it[st == 0].mean())
+    check_mixed(w, st, it, w_mx, st_mx, it_mx, w64, n, exact=m == 2, what=f"op {op} m={m}")
+
+
+def test_mixed_derivatives_full_size_and_errors():
+    """The 1M-node square at m = 6, d/dx: sampled rows against the oracle's
+    mixed form; unsupported supports and bad operators are refused."""
+    ns = nodes.workload("square_1m_m6")
+    X, Y = dev(ns.x), dev(ns.y)
+    NB = rb.rbffd_knn(X, Y, 56)
+    it = torch.zeros(ns.n_nodes, dtype=torch.int32, device="cuda")
+    w, st = rb.rbffd_weights_op_mixed(X, Y, NB, 6, 56, rb.OP_DX, refine_steps=it)
+    w, st, it, nbr = host(w), host(st), host(it), host(NB)
+    assert np.all((st == 0) | (st == rb.FELL_BACK_FP64))
+    rows = np.unique(np.concatenate([np.random.default_rng(23).choice(ns.n_nodes, 150, replace=False),
+                                     [0, ns.n_nodes - 1]]))
+    full = np.zeros_like(nbr)
+    full[rows] = nbr[rows]
+    w_mx, st_mx, it_mx = oracle.weights_mixed(ns.x, ns.y, full, m=6, n=56, rows=rows,
+                                              form=oracle.MIXED_GJ, op=oracle.D_DX)
+    w64, _ = oracle.weights_op(ns.x, ns.y, full, 6, 56, oracle.D_DX, rows=rows)
+    check_mixed(w[rows], st[rows], it[rows], w_mx, st_mx, it_mx, w64, 56, exact=False,
+                what="1M d/dx m=6")
+    with pytest.raises(rb.RbffdError):  # a non-standard support
+        rb.rbffd_weights_op_mixed(X[:1000], Y[:1000], NB[:1000, :40].contiguous(), 6, 40,
+                                  rb.OP_DX)
+    with pytest.raises(rb.RbffdError):  # the Laplacian's mixed form is rbffd_weights
+        rb.rbffd_weights_op_mixed(X, Y, NB, 6, 56, rb.OP_LAPLACIAN)
