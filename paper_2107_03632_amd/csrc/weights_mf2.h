@@ -277,25 +277,35 @@ __device__ __forceinline__ void weights_mf2_wave(
             if (k >= nk) break;
             const int c = c0 + k;
             // pivot search over the lane's slots, then per half: exact key
-            // (|a| bits, position)
+            // (|a| bits, position); bb, bp and bv are read only where ba holds
             uint64_t bb = 0;
-            int bp = 0x7fffffff, bsl = 0;
+            int bp = 0, bsl = 0;
             double bv = 0.0;
             bool ba = false;
+            if constexpr (SL == 1) {
+                bb = (uint64_t)__double_as_longlong(pc[0][k]) & 0x7fffffffffffffffull;
+                bp = pos[0];
+                bv = pc[0][k];
+                ba = !done[0];
+            } else {
 #pragma unroll
-            for (int s = 0; s < SL; ++s) {
-                const uint64_t bits =
-                    (uint64_t)__double_as_longlong(pc[s][k]) & 0x7fffffffffffffffull;
-                const bool take = !done[s] && (!ba || bits > bb || (bits == bb && pos[s] < bp));
-                bb = take ? bits : bb;
-                bp = take ? pos[s] : bp;
-                bsl = take ? s : bsl;
-                bv = take ? pc[s][k] : bv;
-                ba = ba || !done[s];
+                for (int s = 0; s < SL; ++s) {
+                    const uint64_t bits =
+                        (uint64_t)__double_as_longlong(pc[s][k]) & 0x7fffffffffffffffull;
+                    const bool take =
+                        !done[s] && (!ba || bits > bb || (bits == bb && pos[s] < bp));
+                    bb = take ? bits : bb;
+                    bp = take ? pos[s] : bp;
+                    bsl = take ? s : bsl;
+                    bv = take ? pc[s][k] : bv;
+                    ba = ba || !done[s];
+                }
             }
             const uint32_t kh = ba ? (uint32_t)(bb >> 32) + 1u : 0u;
             const uint32_t mh = seg_all<32, OpMax>(kh, lane);
-            uint64_t chunk = __ballot(ba && kh == mh);
+            // (each half keeps a row in the search, so its mh >= 1 and only
+            // rows still in the search can equal it)
+            uint64_t chunk = __ballot(kh == mh);
             uint32_t c0m = (uint32_t)chunk, c1m = (uint32_t)(chunk >> 32);
             if (__builtin_expect(((c0m & (c0m - 1u)) | (c1m & (c1m - 1u))) != 0u, 0)) {
                 uint32_t h2 = kh, l2 = ba ? (uint32_t)bb : 0u;
@@ -311,7 +321,7 @@ __device__ __forceinline__ void weights_mf2_wave(
             const int bs = bcast2_i(bsl, w0, w1, h);  // the winner's slot
             const int kp = bcast2_i(bp, w0, w1, h);
             const double piv = bcast2_d(bv, w0, w1, h);
-            const double inv = 1.0 / piv;
+            const double inv = recip_div(piv);
             // row c of U, panel columns c .. c0 + 3 (up to the rhs)
             if (lane == win) {
 #pragma unroll
