@@ -145,3 +145,63 @@ def test_batch_full_size_sampled(batch_form):
     for m in (2, 4, 6):
         sel = ns.order == m
         assert np.all(w[sel][:, NFM[m]:] == 0.0)
+
+
+def _replay_matches(run, outs):
+    """Capture run() in a graph, replay it three times with eager work
+    between the replays, and check every replay against the eager result."""
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        run()  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    ref = [o.clone() for o in outs]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        run()
+    for rep in range(3):
+        for o in outs:
+            o.fill_(-7)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for o, r in zip(outs, ref):
+            assert torch.equal(o.view(torch.int64) if o.dtype == torch.float64 else o,
+                               r.view(torch.int64) if r.dtype == torch.float64 else r), rep
+
+
+def test_operator_and_3d_batches_replay_in_a_graph():
+    """rbffd_weights_op_batch and rbffd_weights3_batch enqueue everything
+    on the stream (no host synchronisation) and replay bit-identically."""
+    ns = nodes.unit_disk(4000, 200, seed=41)
+    nbr = oracle.knn(ns.x, ns.y, 56)
+    X, Y, NB = dev(ns.x), dev(ns.y), dev(nbr)
+    O = dev(np.random.default_rng(42).choice(np.array([2, 4, 6], np.int8), ns.n_nodes))
+    w = torch.empty((ns.n_nodes, 56), dtype=torch.float64, device="cuda")
+    st = torch.empty(ns.n_nodes, dtype=torch.int32, device="cuda")
+    _replay_matches(lambda: rb.rbffd_weights_op_batch(X, Y, NB, O, rb.OP_DY, out=w, status=st),
+                    [w, st])
+    x, y, z = nodes.jittered_cube(14, seed=43)
+    X3, Y3, Z3 = dev(x), dev(y), dev(z)
+    NB3 = rb.rbffd_knn3(X3, Y3, Z3, 70)
+    O3 = dev(np.random.default_rng(44).choice(np.array([2, 4], np.int8), x.shape[0]))
+    w3 = torch.empty((x.shape[0], 70), dtype=torch.float64, device="cuda")
+    st3 = torch.empty(x.shape[0], dtype=torch.int32, device="cuda")
+    _replay_matches(lambda: rb.rbffd_weights3_batch(X3, Y3, Z3, NB3, O3, out=w3, status=st3),
+                    [w3, st3])
+
+
+@pytest.mark.parametrize("m", [2, 4, 6])
+def test_operator_batch_single_order(m):
+    """Every node of one order (the other two lists empty): the batch gives
+    rbffd_weights_op's weights at that order, bit for bit."""
+    n = {2: 12, 4: 30, 6: 56}[m]
+    ns = nodes.unit_disk(2000, 160, seed=45)
+    nbr = oracle.knn(ns.x, ns.y, 56)
+    X, Y, NB = dev(ns.x), dev(ns.y), dev(nbr)
+    O = dev(np.full(ns.n_nodes, m, np.int8))
+    w_b, st_b = rb.rbffd_weights_op_batch(X, Y, NB, O, rb.OP_DX)
+    w_s, st_s = rb.rbffd_weights_op(X, Y, NB[:, :n].contiguous(), m, n, rb.OP_DX)
+    assert torch.equal(st_b, st_s)
+    assert torch.equal(w_b[:, :n], w_s) and torch.all(w_b[:, n:] == 0.0)
