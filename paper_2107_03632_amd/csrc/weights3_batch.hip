@@ -96,9 +96,8 @@ extern "C" int rbffd_weights3_batch(const double *x, const double *y, const doub
     rc = weights3_list_k105(x, y, z, n_nodes, nbr, k_stride, b.lists + n_nodes, b.counts + 1,
                             n_nodes, w, status, s);
     if (rc) return rc;
-    // m = 2 (K = 30): two stencils per wavefront
-    const int64_t blocks = ceil_div(n_nodes, 2) < wk::kListBlocks2 ? ceil_div(n_nodes, 2)
-                                                                   : wk::kListBlocks2;
+    // m = 2 (K = 30): two possible list entries per wavefront
+    const int64_t blocks = ceil_div(n_nodes, 2);
     hipLaunchKernelGGL((wk::weights_mf2_list_kernel<30, 20, 2, 0, 3, 1, RBFFD_OCC_MF2_K30>),
                        dim3((unsigned)blocks), dim3(kWave), 0, s, x, y, z, n_nodes, nbr, k_stride,
                        b.lists, b.counts, w, status, RBFFD_OK);
