@@ -56,11 +56,19 @@ int64_t max_cells(int64_t n_nodes, int32_t k) {
     return 3 * ceil_div(n_nodes, per) + 2;
 }
 
+// Per-block bounding box of the finite nodes; the blocks also clear the two
+// cell histograms z0, z1 [nz] (one launch fewer than a separate fill).
 __global__ __launch_bounds__(kThreads) void bbox_partial(const double *__restrict__ x,
                                                          const double *__restrict__ y,
-                                                         int64_t n, double *__restrict__ part) {
+                                                         int64_t n, double *__restrict__ part,
+                                                         int32_t *__restrict__ z0,
+                                                         int32_t *__restrict__ z1, int64_t nz) {
     double v[4] = {DBL_MAX, -DBL_MAX, DBL_MAX, -DBL_MAX};
     const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x; q < nz; q += stride) {
+        z0[q] = 0;
+        z1[q] = 0;
+    }
     for (int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x; q < n; q += stride) {
         const double a = x[q], b = y[q];
         if (isfinite(a) && isfinite(b)) {
@@ -316,8 +324,9 @@ namespace rbffd {
 namespace {
 
 // The whole search on stream s with the workspace carved as w.  Everything
-// that must start at zero (the two cell histograms) is cleared here by a
-// fill kernel; the rest of the workspace is written before it is read.
+// that must start at zero (the two cell histograms) is cleared by the first
+// kernel (bbox_partial); the rest of the workspace is written before it is
+// read.
 int knn_launch(const double *x, const double *y, int64_t n_nodes, int32_t k, int32_t *nbr,
                const KnnWs &w, hipStream_t s) {
     const int64_t cells = max_cells(n_nodes, k);
@@ -325,11 +334,10 @@ int knn_launch(const double *x, const double *y, int64_t n_nodes, int32_t k, int
     const int parts = (int)(ceil_div(n_nodes, kThreads) < kBBoxBlocks ? ceil_div(n_nodes, kThreads)
                                                                        : kBBoxBlocks);
     int rc;
-    hipLaunchKernelGGL(bbox_partial, dim3(parts), dim3(kThreads), 0, s, x, y, n_nodes, w.part);
+    hipLaunchKernelGGL(bbox_partial, dim3(parts), dim3(kThreads), 0, s, x, y, n_nodes, w.part,
+                       w.counts, w.fill, cells + 1);
     hipLaunchKernelGGL(grid_setup, dim3(1), dim3(kThreads), 0, s, (const double *)w.part, parts,
                        n_nodes, per_cell(k), cells, w.gp);
-    if ((rc = fill_i32(w.counts, 0, cells + 1, s)) != 0) return rc;
-    if ((rc = fill_i32(w.fill, 0, cells + 1, s)) != 0) return rc;
     hipLaunchKernelGGL(cell_count, dim3(nb), dim3(kThreads), 0, s, x, y, n_nodes,
                        (const GridParams *)w.gp, w.cell_of, w.counts);
     if ((rc = exclusive_scan_i32(w.counts, w.counts, cells + 1, w.scan, s)) != 0) return rc;
